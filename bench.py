@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled Yee + LLG step on one MI355X.
+
+One bench "step" is one full time step of the hot path over the workload
+(H/M half step, E step with CPML and source, H/M half step, probes), so a
+run of K steps advances the simulation K time steps.  The workload is the
+single on-chip resonator: 512 x 256 x 128 cells, silicon substrate, PEC CPW
+strips, a 400 x 60 x 4-cell film, PML 10 on every face (synthetic, seeded).
+
+Prints one JSON line: Gcell-updates/s in float32 (float64 in "secondary"),
+the roofline of the dominant kernel measured with HIP events on the
+library's stream over the timed region, and the float64 CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s (Yee+LLG) & % HBM roofline; batched vs single; adjoint/fwd time"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(w, esz):
+    """Bytes one launch of each stencil kernel must move, per full step.
+    E pass: read E(3) H(3) and the uint8 id, write E(3); plus read+write of
+    the two E-type CPML psi per slab cell and slab axis.  H pass (merged):
+    read E(3) H(3), write H(3); plus the two H-type psi per slab cell."""
+    ncell = w.nx * w.ny * w.nz
+    n = (w.nx, w.ny, w.nz)
+    slab = 0
+    for a in range(3):
+        thick = w.npml[2 * a] * (w.bc[2 * a] == 1) + w.npml[2 * a + 1] * (w.bc[2 * a + 1] == 1)
+        slab += thick * ncell // n[a]
+    e_pass = ncell * (9 * esz + 1) + slab * 2 * 2 * esz
+    h_pass = ncell * 9 * esz + slab * 2 * 2 * esz
+    return {"e_pass": e_pass, "h_pass": h_pass, "ncell": ncell, "slab_cells": slab}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "mpx_internal.h"):
+        with open(os.path.join(ROOT, "paper_2510_22221_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, dtype):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
+    were taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        data = json.load(open(p))
+        ent = data.get(f"{kernel}:{dtype}")
+        if ent and ent.get("source_hash") == kernel_source_hash():
+            return ent["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def run_gpu(w, precision, steps, warmup, every):
+    import torch
+    from paper_2510_22221_amd import mpx
+
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    sim = mpx.from_workload(w, precision=precision, stream=stream)
+    sim.step(1)
+    sim.sync()
+    log(f"  setup {time.time() - t0:.1f} s")
+    if warmup > 1:
+        sim.step(warmup - 1)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_timing(every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    sim.sync()
+    wall = time.perf_counter() - t0
+    kt = sim.kernel_time()
+    sim.set_timing(0)
+    return sim, wall, kt
+
+
+def roofline_for(w, esz, kt, dtype_name):
+    ab = algorithmic_bytes(w, esz)
+    names = ["e_pass", "h_pass"]
+    # dominant = the kernel with the larger total time
+    q = max(range(2), key=lambda i: kt[i][0])
+    ms = kt[q][0]
+    achieved = ab[names[q]] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = traffic_from_profiles(names[q], dtype_name)
+    return {"bound": "hbm", "kernel": names[q], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": ab[names[q]], "avg_launch_ms": round(ms, 5),
+            "launches_timed": kt[q][1],
+            "other_kernel": {"kernel": names[1 - q], "avg_launch_ms": round(kt[1 - q][0], 5),
+                             "achieved": round(ab[names[1 - q]] / (kt[1 - q][0] * 1e-3) / 1e9, 1)
+                             if kt[1 - q][0] > 0 else 0.0}}
+
+
+def cpu_baseline(w, nsteps):
+    import oracle.oracle as O
+    O.build()
+    O.set_threads(min(os.cpu_count() or 1, 64))
+    threads = O.get_threads()
+    t0 = time.time()
+    s = O.from_workload(w)
+    log(f"  oracle setup {time.time() - t0:.1f} s, {threads} threads")
+    t0 = time.perf_counter()
+    s.step(nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.ncells * nsteps / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{w.nx}x{w.ny}x{w.nz} resonator, {nsteps} of its time steps, float64, setup excluded, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--f64-steps", type=int, default=4000)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--timing-every", type=int, default=0, help="event-time every n-th step (0: auto)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=256)
+    ap.add_argument("--nz", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
+              "across GPUs by design, but this build runs on one GPU only)", file=sys.stderr)
+        sys.exit(2)
+    from synth import workloads as W
+    from paper_2510_22221_amd import mpx
+
+    w = W.c2(max(args.steps, args.f64_steps) + args.warmup + 2, nx=args.nx, ny=args.ny, nz=args.nz)
+    every = args.timing_every or max(1, args.steps // 2000)
+    log(f"workload {w.name}: {w.ncells} cells, FP32 {args.steps} steps (+{args.warmup} warmup)")
+    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every)
+    del sim
+    value = w.ncells * args.steps / wall / 1e9
+    roof = roofline_for(w, 4, kt, "f32")
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"single on-chip CPW resonator + film, {w.nx}x{w.ny}x{w.nz} cells, "
+                               f"d=(45,2,2) um, PML 10, source + probes, one time step per bench step",
+                   "cells": w.ncells, "precision": "f32 fields, f64 magnetisation",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+    }
+    if not args.no_f64:
+        log(f"FP64 {args.f64_steps} steps")
+        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000))
+        del sim
+        out["secondary"] = [{"dtype": "f64", "value": round(w.ncells * args.f64_steps / wall64 / 1e9, 3),
+                             "unit": "Gcell-updates/s", "steps": args.f64_steps,
+                             "ms_per_step": round(wall64 / args.f64_steps * 1e3, 5),
+                             "roofline": roofline_for(w, 8, kt64, "f64")}]
+    if not args.no_cpu:
+        log(f"CPU oracle baseline: {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * mpx.h -- C ABI of libmpx, the gfx950 (MI355X) implementation of the
+ * explicit time step of Maxwell's equations on a 3-D Yee grid coupled cell
+ * by cell to the Landau-Lifshitz-Gilbert update of the magnetisation.
+ *
+ * The coupled problem is the one stated in arXiv:2510.22221, Methods,
+ * "Numerical Model": Ampere's law with conduction (eq. Ampere) discretised
+ * semi-implicitly in sigma, Faraday's law with B = mu0 (H + M) integrated as
+ * eq. (iterate_H), and the Gilbert-form LLG (eq. LLG) advanced with the
+ * trapezoidal rule of eqs. (llg_tra4)-(llg_tra6) and normalised to the local
+ * saturation magnetisation.  H and M advance in two half steps around each
+ * full E step (the dt/4 and dt/(2 mu0) factors of those equations).
+ *
+ * Conventions shared by every call
+ *   - Every function returns mpx_status; nothing throws across the ABI.
+ *   - Units are SI: m, s, V/m, A/m, S/m.  |gamma| in rad/(s T).
+ *   - Cell (i,j,k) spans [i dx,(i+1) dx] x [j dy,(j+1) dy] x [k dz,(k+1) dz].
+ *     Host arrays are x-fastest: element (i,j,k) of an array with natural
+ *     dims (n0,n1,n2) is at i + n0 (j + n1 k).
+ *   - Natural Yee dims of a field component (mpx_query_field): E_c has N_c
+ *     entries along c and N_a + 1 along the other axes a; H_c has N_c + 1
+ *     along c and N_a along the others; a periodic axis drops the "+1".
+ *   - Host buffers passed in are copied during the call; the caller keeps
+ *     ownership.  Device memory the library allocates is released by
+ *     mpx_destroy.
+ *   - A HIP error makes the handle fail with MPX_E_DEVICE from then on
+ *     (sticky); only mpx_destroy and mpx_last_error still work.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MPX_H
+#define MPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPX_ABI_VERSION 1u
+
+typedef struct mpx_sim mpx_sim;
+
+typedef enum {
+    MPX_OK = 0,
+    MPX_E_INVALID = 1,     /* bad argument; no side effect */
+    MPX_E_STATE = 2,       /* call out of order (e.g. step before materials) */
+    MPX_E_NOMEM = 3,       /* device or host allocation failed */
+    MPX_E_DEVICE = 4,      /* HIP runtime error (sticky) */
+    MPX_E_UNSUPPORTED = 5, /* valid request this library does not implement */
+    MPX_E_RANGE = 6,       /* destination too small */
+    MPX_E_NONFINITE = 7    /* the non-finite watchdog fired */
+} mpx_status;
+
+typedef enum { MPX_F64 = 0, MPX_F32 = 1 } mpx_precision;
+
+typedef enum { MPX_BC_PEC = 0, MPX_BC_PML = 1, MPX_BC_PERIODIC = 2 } mpx_bc;
+
+typedef enum {
+    MPX_EX = 0, MPX_EY = 1, MPX_EZ = 2,
+    MPX_HX = 3, MPX_HY = 4, MPX_HZ = 5,
+    /* the full magnetisation vector at the x-, y- and z-face sites:
+     * 3 components, component-major, each over that face family's natural
+     * dims; zero at non-magnetic sites.  Always float64. */
+    MPX_M_XFACE = 6, MPX_M_YFACE = 7, MPX_M_ZFACE = 8,
+    /* the same minus the initial state M0 = Ms_site u (read only) */
+    MPX_DM_XFACE = 9, MPX_DM_YFACE = 10, MPX_DM_ZFACE = 11
+} mpx_field;
+
+typedef enum {
+    MPX_PROBE_FIELD = 0,       /* one E or H component at one site, 1 value */
+    MPX_PROBE_MEAN_M = 1,      /* film-averaged M, 3 values per sample */
+    MPX_PROBE_FILM_ENERGY = 2  /* EM energy inside the film's cells, 1 value */
+} mpx_probe_kind;
+
+/* Grid.  dt <= 0 selects dt = courant / (c sqrt(dx^-2 + dy^-2 + dz^-2))
+ * (the Courant-limited step of Results, setup section: CFL factor 0.9).
+ * bc[] is -x,+x,-y,+y,-z,+z; a periodic axis must be periodic on both faces.
+ * PML faces are convolutional PML slabs of pml_cells[] cells backed by a PEC
+ * wall, graded sigma = sigma_max rho^order with
+ * sigma_max = pml_sigma_factor (order+1)/(eta0 d) (defaults 3 and 0.8 when
+ * <= 0); the paper names PML on all faces without a formulation. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    double courant;
+    double dt;
+    int32_t bc[6];
+    int32_t pml_cells[6];
+    double pml_order;
+    double pml_sigma_factor;
+} mpx_grid_desc;
+
+/* One entry of the per-cell material table (Methods, "Numerical Model":
+ * eps_r, sigma, Ms, alpha, gamma are spatially dependent).  is_pec != 0 makes
+ * every edge touching the cell a perfect conductor.  Ms > 0 makes the cell
+ * magnetic. */
+typedef struct {
+    double eps_r, sigma;
+    int32_t is_pec;
+    double Ms, alpha, gamma_abs;
+} mpx_material;
+
+/* Soft current source on the E_component edges of a box given in that
+ * component's natural index space: J(t_{n+1/2}) = table[n] (A/m^2), zero
+ * past the end of the table; it enters the E update as
+ * E <- ca E + cb (curl H - J) (the J_src of the E update in Methods). */
+typedef struct {
+    int32_t component;              /* 0..2 = Jx, Jy, Jz */
+    int32_t i0, j0, k0, ni, nj, nk;
+    const double *table;            /* host, float64, copied */
+    int64_t n_table;
+} mpx_source_desc;
+
+/* Probe sampled after every full step (at t_{n+1}) into a ring buffer of
+ * `capacity` samples.  FIELD: field = MPX_EX..MPX_HZ at natural index
+ * (i,j,k) (H probes must lie outside PML slabs).  MEAN_M and FILM_ENERGY
+ * use `film` (films are numbered by their lowest linear cell index). */
+typedef struct {
+    int32_t kind;
+    int32_t field;
+    int32_t i, j, k;
+    int32_t film;
+    int64_t capacity;
+} mpx_probe_desc;
+
+/* ABI version of the loaded library (MPX_ABI_VERSION). */
+uint32_t mpx_abi_version(void);
+
+/* Create a simulation on HIP device `hip_device`.  `hip_stream` is a
+ * hipStream_t the caller owns (it must outlive the handle) or NULL, in which
+ * case the library creates and owns a non-blocking stream at default
+ * priority.  All device work of the handle is ordered on that stream.
+ * Errors: MPX_E_INVALID for non-positive sizes or spacings, courant outside
+ * (0, 1] when dt <= 0, a one-sided periodic axis, PML thicker than a third of
+ * the axis; MPX_E_DEVICE / MPX_E_NOMEM from HIP. */
+mpx_status mpx_create(const mpx_grid_desc *grid, mpx_precision precision, int32_t hip_device,
+                      void *hip_stream, mpx_sim **out);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+mpx_status mpx_destroy(mpx_sim *sim);
+
+/* Natural dims of a field (dims[3] = 1, or 3 for the M fields) and the size
+ * in bytes of a host buffer that holds it (float64 in MPX_F64 mode and for
+ * every M field, float32 for E/H in MPX_F32 mode). */
+mpx_status mpx_query_field(const mpx_sim *sim, int32_t field, int64_t dims[4], int64_t *bytes);
+
+/* Material table (n <= 256 entries) and one uint8 id per cell, host array of
+ * nx*ny*nz bytes, x fastest.  Finds the films (bounding boxes of connected
+ * magnetic cells, boxes closer than two cells merged) and resets M to zero.
+ * Errors: MPX_E_INVALID for an id >= n, a magnetic cell inside or next to a
+ * PML slab, or > 64 films; MPX_E_UNSUPPORTED for a film that touches a
+ * non-periodic domain face or wraps partially around a periodic one. */
+mpx_status mpx_set_materials(mpx_sim *sim, const mpx_material *table, int32_t n, const uint8_t *cell_ids);
+
+/* Uniform static bias field H0 (A/m), part of H_eff (Methods: H_eff collects
+ * the EM field and the static bias). */
+mpx_status mpx_set_bias(mpx_sim *sim, double H0x, double H0y, double H0z);
+
+/* M = Ms_site u at every magnetic face site (u normalised here; the paper
+ * saturates the film along the bias).  This state is also M0 for the
+ * MPX_DM_* fields.  MPX_E_STATE before mpx_set_materials. */
+mpx_status mpx_init_magnetization(mpx_sim *sim, double ux, double uy, double uz);
+
+/* Add a source (at most 16).  *id receives its index. */
+mpx_status mpx_add_source(mpx_sim *sim, const mpx_source_desc *src, int32_t *id);
+
+/* Add a probe (at most 64).  Samples start with the next step. */
+mpx_status mpx_add_probe(mpx_sim *sim, const mpx_probe_desc *probe, int32_t *id);
+
+/* Advance nsteps full steps: H/M half step, E step, H/M half step each
+ * (consecutive H/M half steps are done in one pass).  Asynchronous on the
+ * handle's stream; no host synchronisation inside.  MPX_E_STATE before
+ * mpx_set_materials. */
+mpx_status mpx_step(mpx_sim *sim, int64_t nsteps);
+
+/* Wait for the handle's stream; reports MPX_E_NONFINITE if a probe saw a
+ * non-finite value, MPX_E_DEVICE on a HIP error. */
+mpx_status mpx_synchronize(mpx_sim *sim);
+
+/* Copy a field out (natural dims) to host (dst_is_device = 0) or device
+ * memory.  Synchronises.  MPX_E_RANGE if dst_bytes is below mpx_query_field's
+ * size. */
+mpx_status mpx_read_field(mpx_sim *sim, int32_t field, void *dst, int64_t dst_bytes, int32_t dst_is_device);
+
+/* Overwrite a field (natural dims, the element type of mpx_query_field).
+ * E values on PEC edges and on the faces of non-periodic walls are held at
+ * zero; H values on the upper wall faces are not stored; M values are kept
+ * only at magnetic sites.  MPX_DM_* fields are read-only. */
+mpx_status mpx_write_field(mpx_sim *sim, int32_t field, const void *src, int64_t src_bytes, int32_t src_is_device);
+
+/* Copy the recorded samples of probe `id`, oldest first, into dst (float64;
+ * `capacity` counts samples).  *n_written = samples copied, or the number
+ * required with MPX_E_RANGE. */
+mpx_status mpx_read_probe(mpx_sim *sim, int32_t id, double *dst, int64_t capacity, int64_t *n_written);
+
+/* Discrete EM energy at the current integer time,
+ * dV/2 [sum_edges eps_e E^2 + mu0 sum_faces (H^2 - (dt/(2 mu0))^2 (curl E)^2)],
+ * and the Zeeman term -mu0 dV sum_c sum_{family-c sites} H0_c M_c.  Computed
+ * on the device in float64.  MPX_E_UNSUPPORTED with PML faces. */
+mpx_status mpx_energy(mpx_sim *sim, double *W_em, double *W_zeeman);
+
+/* Step count, time = step dt, dt and number of films. */
+mpx_status mpx_info(const mpx_sim *sim, int64_t *step, double *time, double *dt, int32_t *n_films);
+
+/* Cell box (i0,j0,k0,ni,nj,nk) and magnetic cell count of film `film`. */
+mpx_status mpx_film_box(const mpx_sim *sim, int32_t film, int32_t box[6], int64_t *ncells);
+
+/* Steps captured per HIP graph by mpx_step (default 64; 0 launches every
+ * kernel directly). */
+mpx_status mpx_set_graph_steps(mpx_sim *sim, int32_t steps);
+
+/* Kernel timing with HIP events on the handle's stream.  With every > 0,
+ * mpx_step launches each step's kernels directly (no graph) and brackets the
+ * E pass and the merged H pass of every `every`-th step with events; 0 turns
+ * timing off.  mpx_kernel_time returns, for the last mpx_step call, the
+ * average device time per timed launch (ms) and the number of launches
+ * timed: index 0 = E pass, 1 = merged H pass (arrays of 2). */
+mpx_status mpx_set_timing(mpx_sim *sim, int32_t every);
+mpx_status mpx_kernel_time(mpx_sim *sim, double *avg_ms, int64_t *launches);
+
+/* Human-readable description of the last error on this handle. */
+const char *mpx_last_error(const mpx_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPX_H */

@@ -1,0 +1,1046 @@
+// host.hip -- C ABI of libmpx (include/mpx.h): grid and material setup, film
+// discovery, CPML profiles, sources, probes, the step driver (HIP graphs of
+// step batches on the handle's stream), field readback and diagnostics.
+#include "../../include/mpx.h"
+#include "mpx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mpx;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double C0 = 299792458.0;
+const double MU0 = 4.0e-7 * PI;
+const double EPS0 = 1.0 / (MU0 * C0 * C0);
+
+struct FilmHost {
+    int cb[6];      // cell box
+    int b0[3], bn[3];
+    long long ns;
+    long long ncells;
+    long long lowest;
+    double *M = nullptr, *M1 = nullptr, *H1 = nullptr;
+    int blk0[3], nblk[3];
+};
+
+struct SrcHost {
+    SrcDev dev;
+    double *table = nullptr;
+};
+
+struct ProbeHost {
+    ProbeDev dev;
+};
+
+} // namespace
+
+struct mpx_sim {
+    mpx_grid_desc g{};
+    mpx_precision prec = MPX_F64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n[3] = {0, 0, 0};
+    int per[3] = {0, 0, 0};
+    int px = 0;
+    long long nslot = 0;
+    double d[3] = {0, 0, 0};
+    double dt = 0;
+    size_t esz = 8;
+    void *E[3] = {nullptr, nullptr, nullptr};
+    void *H[3] = {nullptr, nullptr, nullptr};
+    // materials
+    bool have_mat = false;
+    std::vector<mpx_material> mats;
+    std::vector<uint8_t> ids; // natural cell order
+    uint8_t *d_id = nullptr;
+    MatDev *d_mat = nullptr;
+    // PML
+    int nlo[3] = {0, 0, 0}, nhi[3] = {0, 0, 0};
+    void *bE[3] = {}, *cE[3] = {}, *bH[3] = {}, *cH[3] = {};
+    void *psiE[3][3] = {}, *psiH[3][3] = {};
+    bool any_pml = false;
+    // films
+    std::vector<FilmHost> films;
+    FilmDev *d_films = nullptr;
+    int4 *d_blocktab = nullptr;
+    double *d_partial = nullptr;
+    int nblk = 0;
+    double H0[3] = {0, 0, 0};
+    double u[3] = {0, 0, 1};
+    bool have_u = false;
+    // sources, probes
+    std::vector<SrcHost> srcs;
+    std::vector<ProbeHost> probes;
+    ProbeDev *d_probes = nullptr;
+    long long *d_step = nullptr;
+    int *d_flag = nullptr;
+    long long step = 0;
+    // graph
+    int graph_steps = 64;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool graph_valid = false;
+    // timing
+    int timing_every = 0;
+    std::vector<hipEvent_t> ev;
+    size_t evi = 0;
+    double t_ms[2] = {0, 0};
+    long long t_n[2] = {0, 0};
+    // errors
+    bool dead = false;
+    std::string err;
+};
+
+namespace {
+
+mpx_status fail(mpx_sim *s, mpx_status st, const std::string &msg) {
+    if (s) s->err = msg;
+    return st;
+}
+
+mpx_status dev_fail(mpx_sim *s, hipError_t e, const char *what) {
+    s->dead = true;
+    s->err = std::string(what) + ": " + hipGetErrorString(e);
+    return MPX_E_DEVICE;
+}
+
+#define CK(call)                                                   \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return dev_fail(s, _e, #call);       \
+    } while (0)
+
+long long natural_dim(const mpx_sim *s, int field, int a) {
+    // E_c: N_c along c; H_c: N_c (+1 if not periodic) along c; the
+    // other axes the reverse
+    const int c = field % 3;
+    const bool is_e = field < 3;
+    const bool half = is_e ? (a == c) : (a != c);
+    return half ? s->n[a] : s->n[a] + (s->per[a] ? 0 : 1);
+}
+
+int fold_h(int i, int n, int per) {
+    if (per) {
+        if (i < 0) i += n;
+        if (i >= n) i -= n;
+        return i;
+    }
+    return (i < 0 || i >= n) ? -1 : i;
+}
+
+int cell_id_h(const mpx_sim *s, int i, int j, int k) {
+    int ii = fold_h(i, s->n[0], s->per[0]), jj = fold_h(j, s->n[1], s->per[1]), kk = fold_h(k, s->n[2], s->per[2]);
+    if (ii < 0 || jj < 0 || kk < 0) return -1;
+    return s->ids[(size_t)ii + (size_t)s->n[0] * ((size_t)jj + (size_t)s->n[1] * kk)];
+}
+
+// Ms, alpha, |gamma| of the face of family c at natural index idx (the mean
+// over the two cells sharing it, alpha and gamma over the magnetic ones)
+void site_params_h(const mpx_sim *s, int c, const int *idx, double &ms, double &al, double &ga) {
+    double sm = 0, sa = 0, sg = 0;
+    int cnt = 0, nm = 0;
+    for (int u = -1; u <= 0; u++) {
+        int cc[3] = {idx[0], idx[1], idx[2]};
+        cc[c] += u;
+        int m = cell_id_h(s, cc[0], cc[1], cc[2]);
+        if (m < 0) continue;
+        cnt++;
+        sm += s->mats[m].Ms;
+        if (s->mats[m].Ms > 0) {
+            nm++;
+            sa += s->mats[m].alpha;
+            sg += s->mats[m].gamma_abs;
+        }
+    }
+    ms = cnt ? sm / cnt : 0.0;
+    al = nm ? sa / nm : 0.0;
+    ga = nm ? sg / nm : 0.0;
+}
+
+bool edge_is_pec_h(const mpx_sim *s, int c, const int *idx) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    for (int a : {c1, c2})
+        if (!s->per[a] && (idx[a] == 0 || idx[a] >= s->n[a])) return true;
+    for (int u = -1; u <= 0; u++)
+        for (int v = -1; v <= 0; v++) {
+            int cc[3];
+            cc[c] = idx[c];
+            cc[c1] = idx[c1] + u;
+            cc[c2] = idx[c2] + v;
+            int m = cell_id_h(s, cc[0], cc[1], cc[2]);
+            if (m >= 0 && s->mats[m].is_pec) return true;
+        }
+    return false;
+}
+
+bool in_pml_cell(const mpx_sim *s, int a, int i) { return i < s->nlo[a] || i >= s->n[a] - s->nhi[a]; }
+
+template <typename T>
+void fill_params(const mpx_sim *s, KParams<T> &p) {
+    memset(&p, 0, sizeof(p));
+    for (int a = 0; a < 3; a++) {
+        p.n[a] = s->n[a];
+        p.per[a] = s->per[a];
+        p.d[a] = s->d[a];
+        p.dT[a] = (T)s->d[a];
+        p.invd[a] = (T)(1.0 / s->d[a]);
+        p.nlo[a] = s->nlo[a];
+        p.nhi[a] = s->nhi[a];
+        p.bE[a] = (const T *)s->bE[a];
+        p.cE[a] = (const T *)s->cE[a];
+        p.bH[a] = (const T *)s->bH[a];
+        p.cH[a] = (const T *)s->cH[a];
+        p.E[a] = (T *)s->E[a];
+        p.H[a] = (T *)s->H[a];
+        p.H0[a] = s->H0[a];
+        for (int w = 0; w < 3; w++) {
+            p.psiE[a][w] = (T *)s->psiE[a][w];
+            p.psiH[a][w] = (T *)s->psiH[a][w];
+        }
+    }
+    p.px = s->px;
+    p.hcd = s->dt / (2.0 * MU0);
+    p.hc = (T)p.hcd;
+    p.dt = s->dt;
+    p.inv_dt = 1.0 / s->dt;
+    p.eps0 = EPS0;
+    p.mu0 = MU0;
+    p.kf = MU0 * s->dt / 4.0;
+    p.dV = s->d[0] * s->d[1] * s->d[2];
+    p.id = s->d_id;
+    p.mat = s->d_mat;
+    p.nfilm = (int)s->films.size();
+    p.films = s->d_films;
+    p.blocktab = s->d_blocktab;
+    p.partial = s->d_partial;
+    p.nsrc = (int)s->srcs.size();
+    for (int i = 0; i < p.nsrc; i++) p.src[i] = s->srcs[i].dev;
+    p.probes = s->d_probes;
+    p.step = s->d_step;
+    p.flag = s->d_flag;
+}
+
+void free_films(mpx_sim *s) {
+    for (auto &f : s->films) {
+        (void)hipFree(f.M);
+        (void)hipFree(f.M1);
+        (void)hipFree(f.H1);
+    }
+    s->films.clear();
+    (void)hipFree(s->d_films);
+    (void)hipFree(s->d_blocktab);
+    (void)hipFree(s->d_partial);
+    s->d_films = nullptr;
+    s->d_blocktab = nullptr;
+    s->d_partial = nullptr;
+    s->nblk = 0;
+}
+
+void drop_graph(mpx_sim *s) {
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_valid = false;
+}
+
+// connected components of magnetic cells -> bounding boxes; boxes closer than
+// two cells on every axis are merged; ordered by lowest linear cell index
+std::vector<FilmHost> discover_films(const mpx_sim *s) {
+    const long long ncell = (long long)s->n[0] * s->n[1] * s->n[2];
+    std::vector<int> lab(ncell, -1);
+    std::vector<long long> stack;
+    struct Box {
+        int lo[3], hi[3];
+        long long low;
+    };
+    std::vector<Box> boxes;
+    for (long long q = 0; q < ncell; q++) {
+        if (lab[q] >= 0 || !(s->mats[s->ids[q]].Ms > 0)) continue;
+        Box b{{1 << 30, 1 << 30, 1 << 30}, {-1, -1, -1}, q};
+        stack.clear();
+        stack.push_back(q);
+        lab[q] = (int)boxes.size();
+        while (!stack.empty()) {
+            long long pq = stack.back();
+            stack.pop_back();
+            int c[3] = {(int)(pq % s->n[0]), (int)((pq / s->n[0]) % s->n[1]), (int)(pq / ((long long)s->n[0] * s->n[1]))};
+            for (int a = 0; a < 3; a++) {
+                b.lo[a] = std::min(b.lo[a], c[a]);
+                b.hi[a] = std::max(b.hi[a], c[a] + 1);
+            }
+            for (int a = 0; a < 3; a++)
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    int nc[3] = {c[0], c[1], c[2]};
+                    nc[a] += sg;
+                    if (nc[a] < 0 || nc[a] >= s->n[a]) continue;
+                    long long pn = nc[0] + (long long)s->n[0] * (nc[1] + (long long)s->n[1] * nc[2]);
+                    if (lab[pn] < 0 && s->mats[s->ids[pn]].Ms > 0) {
+                        lab[pn] = (int)boxes.size();
+                        stack.push_back(pn);
+                    }
+                }
+        }
+        boxes.push_back(b);
+    }
+    bool merged = true;
+    while (merged) {
+        merged = false;
+        for (size_t x = 0; x < boxes.size() && !merged; x++)
+            for (size_t y = x + 1; y < boxes.size() && !merged; y++) {
+                bool close = true;
+                for (int a = 0; a < 3; a++) {
+                    int gap = boxes[y].lo[a] >= boxes[x].hi[a]   ? boxes[y].lo[a] - boxes[x].hi[a]
+                              : boxes[x].lo[a] >= boxes[y].hi[a] ? boxes[x].lo[a] - boxes[y].hi[a]
+                                                                 : 0;
+                    if (gap >= 2) close = false;
+                }
+                if (close) {
+                    for (int a = 0; a < 3; a++) {
+                        boxes[x].lo[a] = std::min(boxes[x].lo[a], boxes[y].lo[a]);
+                        boxes[x].hi[a] = std::max(boxes[x].hi[a], boxes[y].hi[a]);
+                    }
+                    boxes[x].low = std::min(boxes[x].low, boxes[y].low);
+                    boxes.erase(boxes.begin() + y);
+                    merged = true;
+                }
+            }
+    }
+    std::sort(boxes.begin(), boxes.end(), [](const Box &a, const Box &b) { return a.low < b.low; });
+    std::vector<FilmHost> out;
+    for (auto &b : boxes) {
+        FilmHost f{};
+        for (int a = 0; a < 3; a++) {
+            f.cb[a] = b.lo[a];
+            f.cb[3 + a] = b.hi[a] - b.lo[a];
+        }
+        f.lowest = b.low;
+        f.ncells = 0;
+        for (int k = b.lo[2]; k < b.hi[2]; k++)
+            for (int j = b.lo[1]; j < b.hi[1]; j++)
+                for (int i = b.lo[0]; i < b.hi[0]; i++)
+                    if (s->mats[s->ids[i + (size_t)s->n[0] * (j + (size_t)s->n[1] * k)]].Ms > 0) f.ncells++;
+        out.push_back(f);
+    }
+    return out;
+}
+
+template <typename T>
+mpx_status upload_profiles(mpx_sim *s) {
+    const double m = s->g.pml_order > 0 ? s->g.pml_order : 3.0;
+    const double f = s->g.pml_sigma_factor > 0 ? s->g.pml_sigma_factor : 0.8;
+    const double eta0 = std::sqrt(MU0 / EPS0);
+    for (int a = 0; a < 3; a++) {
+        const int n = s->n[a];
+        const int nlo = s->nlo[a], nhi = s->nhi[a];
+        if (nlo == 0 && nhi == 0) continue;
+        std::vector<T> be(n + 1), ce(n + 1), bh(n + 1), ch(n + 1);
+        const double smax = f * (m + 1.0) / (eta0 * s->d[a]);
+        for (int pp = 0; pp <= n; pp++)
+            for (int half = 0; half < 2; half++) {
+                const double x = pp + 0.5 * half;
+                double rho = 0.0;
+                if (nlo > 0 && x < nlo) rho = (nlo - x) / nlo;
+                if (nhi > 0 && x > n - nhi) rho = (x - (n - nhi)) / nhi;
+                const double sig = smax * std::pow(rho, m);
+                if (half == 0) {
+                    const double b = std::exp(-sig * s->dt / EPS0);
+                    be[pp] = (T)b;
+                    ce[pp] = (T)(b - 1.0);
+                } else {
+                    const double b = std::exp(-sig * (0.5 * s->dt) / EPS0);
+                    bh[pp] = (T)b;
+                    ch[pp] = (T)(b - 1.0);
+                }
+            }
+        void **dst[4] = {&s->bE[a], &s->cE[a], &s->bH[a], &s->cH[a]};
+        std::vector<T> *src[4] = {&be, &ce, &bh, &ch};
+        for (int q = 0; q < 4; q++) {
+            CK(hipMalloc(dst[q], (n + 1) * sizeof(T)));
+            CK(hipMemcpy(*dst[q], src[q]->data(), (n + 1) * sizeof(T), hipMemcpyHostToDevice));
+        }
+        const int S = nlo + nhi;
+        size_t cnt = a == 0 ? (size_t)S * s->n[1] * s->n[2]
+                     : a == 1 ? (size_t)s->px * S * s->n[2]
+                              : (size_t)s->px * s->n[1] * S;
+        for (int c = 0; c < 3; c++) {
+            if (c == a) continue;
+            CK(hipMalloc(&s->psiE[c][a], cnt * sizeof(T)));
+            CK(hipMalloc(&s->psiH[c][a], cnt * sizeof(T)));
+            CK(hipMemset(s->psiE[c][a], 0, cnt * sizeof(T)));
+            CK(hipMemset(s->psiH[c][a], 0, cnt * sizeof(T)));
+        }
+    }
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status enqueue_steps(mpx_sim *s, long long nsteps);
+
+template <typename T>
+mpx_status run_body(mpx_sim *s, const KParams<T> &p, bool last, bool timed) {
+    const int nblk = s->nblk;
+    const int np = (int)s->probes.size();
+    hipStream_t st = s->stream;
+    // event pool: four events per timed step (E pass start/end, H pass start/end)
+    auto rec = [&]() -> mpx_status {
+        if (s->evi >= s->ev.size()) {
+            hipEvent_t e;
+            CK(hipEventCreate(&e));
+            s->ev.push_back(e);
+        }
+        CK(hipEventRecord(s->ev[s->evi++], st));
+        return MPX_OK;
+    };
+    mpx_status r;
+    if (timed && (r = rec()) != MPX_OK) return r;
+    CK(launch_epass<T>(p, st));
+    if (timed && (r = rec()) != MPX_OK) return r;
+    CK(launch_film<T>(p, nblk, 1, st));
+    CK(launch_probes<T>(p, np, st));
+    if (last)
+        CK(launch_commit<T>(p, nblk, st));
+    else
+        CK(launch_film<T>(p, nblk, 2, st));
+    if (timed && (r = rec()) != MPX_OK) return r;
+    CK(launch_hbulk<T>(p, last ? 1 : 2, 1, st));
+    if (timed && (r = rec()) != MPX_OK) return r;
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status enqueue_steps(mpx_sim *s, long long nsteps) {
+    KParams<T> p;
+    fill_params<T>(s, p);
+    hipStream_t st = s->stream;
+    const int nblk = s->nblk;
+    // bracket: first H/M half step with E^n
+    CK(launch_film<T>(p, nblk, 1, st));
+    CK(launch_commit<T>(p, nblk, st));
+    CK(launch_hbulk<T>(p, 1, 0, st));
+    long long body = nsteps - 1;
+    mpx_status r;
+    if (s->timing_every > 0) {
+        // direct launches; every timing_every-th step bracketed by events
+        s->evi = 0;
+        for (long long n = 0; n < body; n++)
+            if ((r = run_body<T>(s, p, false, n % s->timing_every == 0)) != MPX_OK) return r;
+        if ((r = run_body<T>(s, p, true, body % s->timing_every == 0)) != MPX_OK) return r;
+        CK(hipStreamSynchronize(st));
+        s->t_ms[0] = s->t_ms[1] = 0;
+        s->t_n[0] = s->t_n[1] = 0;
+        for (size_t q = 0; q + 3 < s->evi; q += 4) {
+            float a = 0, b = 0;
+            CK(hipEventElapsedTime(&a, s->ev[q], s->ev[q + 1]));
+            CK(hipEventElapsedTime(&b, s->ev[q + 2], s->ev[q + 3]));
+            s->t_ms[0] += a;
+            s->t_ms[1] += b;
+            s->t_n[0]++;
+            s->t_n[1]++;
+        }
+        return MPX_OK;
+    }
+    const int G = s->graph_steps;
+    if (G > 0 && body >= G) {
+        if (!s->graph_valid) {
+            drop_graph(s);
+            CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int n = 0; n < G; n++) {
+                r = run_body<T>(s, p, false, false);
+                if (r != MPX_OK) {
+                    hipGraph_t g;
+                    (void)hipStreamEndCapture(st, &g);
+                    return r;
+                }
+            }
+            CK(hipStreamEndCapture(st, &s->graph));
+            CK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+            s->graph_valid = true;
+        }
+        while (body >= G) {
+            CK(hipGraphLaunch(s->gexec, st));
+            body -= G;
+        }
+    }
+    for (long long n = 0; n < body; n++)
+        if ((r = run_body<T>(s, p, false, false)) != MPX_OK) return r;
+    return run_body<T>(s, p, true, false);
+}
+
+mpx_status check_live(mpx_sim *s) {
+    if (!s) return MPX_E_INVALID;
+    if (s->dead) return MPX_E_DEVICE;
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return dev_fail(s, e, "hipSetDevice");
+    return MPX_OK;
+}
+
+mpx_status upload_probes(mpx_sim *s) {
+    (void)hipFree(s->d_probes);
+    s->d_probes = nullptr;
+    if (s->probes.empty()) return MPX_OK;
+    std::vector<ProbeDev> v;
+    for (auto &pr : s->probes) v.push_back(pr.dev);
+    CK(hipMalloc(&s->d_probes, v.size() * sizeof(ProbeDev)));
+    CK(hipMemcpy(s->d_probes, v.data(), v.size() * sizeof(ProbeDev), hipMemcpyHostToDevice));
+    return MPX_OK;
+}
+
+} // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+uint32_t mpx_abi_version(void) { return MPX_ABI_VERSION; }
+
+mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_device, void *hip_stream,
+                      mpx_sim **out) {
+    if (!g || !out) return MPX_E_INVALID;
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0)) return MPX_E_INVALID;
+    if (prec != MPX_F64 && prec != MPX_F32) return MPX_E_INVALID;
+    const int nn[3] = {g->nx, g->ny, g->nz};
+    for (int a = 0; a < 3; a++) {
+        const int lo = g->bc[2 * a], hi = g->bc[2 * a + 1];
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return MPX_E_INVALID;
+        if ((lo == MPX_BC_PERIODIC) != (hi == MPX_BC_PERIODIC)) return MPX_E_INVALID;
+        const int plo = lo == MPX_BC_PML ? g->pml_cells[2 * a] : 0;
+        const int phi = hi == MPX_BC_PML ? g->pml_cells[2 * a + 1] : 0;
+        if (plo < 0 || phi < 0 || (lo == MPX_BC_PML && plo < 1) || (hi == MPX_BC_PML && phi < 1)) return MPX_E_INVALID;
+        if (3 * (plo + phi) > nn[a]) return MPX_E_INVALID;
+    }
+    double dt = g->dt;
+    if (!(dt > 0)) {
+        if (!(g->courant > 0) || g->courant > 1.0) return MPX_E_INVALID;
+        // Courant-limited step of the 3-D Yee scheme
+        dt = g->courant / (C0 * std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz)));
+    }
+    mpx_sim *s = new mpx_sim();
+    s->g = *g;
+    s->prec = prec;
+    s->device = hip_device;
+    s->esz = prec == MPX_F64 ? 8 : 4;
+    for (int a = 0; a < 3; a++) {
+        s->n[a] = nn[a];
+        s->per[a] = g->bc[2 * a] == MPX_BC_PERIODIC;
+        s->nlo[a] = g->bc[2 * a] == MPX_BC_PML ? g->pml_cells[2 * a] : 0;
+        s->nhi[a] = g->bc[2 * a + 1] == MPX_BC_PML ? g->pml_cells[2 * a + 1] : 0;
+        if (s->nlo[a] || s->nhi[a]) s->any_pml = true;
+    }
+    s->d[0] = g->dx;
+    s->d[1] = g->dy;
+    s->d[2] = g->dz;
+    s->dt = dt;
+    s->px = (g->nx + 31) / 32 * 32;
+    s->nslot = (long long)s->px * g->ny * g->nz;
+    hipError_t e = hipSetDevice(hip_device);
+    if (e != hipSuccess) {
+        delete s;
+        return MPX_E_DEVICE;
+    }
+    mpx_status r = MPX_OK;
+    auto setup = [&]() -> mpx_status {
+        if (hip_stream) {
+            s->stream = (hipStream_t)hip_stream;
+        } else {
+            CK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+            s->own_stream = true;
+        }
+        for (int c = 0; c < 3; c++) {
+            CK(hipMalloc(&s->E[c], s->nslot * s->esz));
+            CK(hipMalloc(&s->H[c], s->nslot * s->esz));
+            CK(hipMemset(s->E[c], 0, s->nslot * s->esz));
+            CK(hipMemset(s->H[c], 0, s->nslot * s->esz));
+        }
+        CK(hipMalloc(&s->d_id, s->nslot));
+        CK(hipMemset(s->d_id, 0, s->nslot));
+        CK(hipMalloc(&s->d_mat, 256 * sizeof(MatDev)));
+        CK(hipMemset(s->d_mat, 0, 256 * sizeof(MatDev)));
+        CK(hipMalloc(&s->d_step, sizeof(long long)));
+        CK(hipMemset(s->d_step, 0, sizeof(long long)));
+        CK(hipMalloc(&s->d_flag, sizeof(int)));
+        CK(hipMemset(s->d_flag, 0, sizeof(int)));
+        return prec == MPX_F64 ? upload_profiles<double>(s) : upload_profiles<float>(s);
+    };
+    r = setup();
+    if (r != MPX_OK) {
+        mpx_destroy(s);
+        return r == MPX_E_DEVICE ? MPX_E_NOMEM : r;
+    }
+    *out = s;
+    return MPX_OK;
+}
+
+mpx_status mpx_destroy(mpx_sim *s) {
+    if (!s) return MPX_OK;
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    for (auto e : s->ev) (void)hipEventDestroy(e);
+    for (int c = 0; c < 3; c++) {
+        (void)hipFree(s->E[c]);
+        (void)hipFree(s->H[c]);
+        (void)hipFree(s->bE[c]);
+        (void)hipFree(s->cE[c]);
+        (void)hipFree(s->bH[c]);
+        (void)hipFree(s->cH[c]);
+        for (int w = 0; w < 3; w++) {
+            (void)hipFree(s->psiE[c][w]);
+            (void)hipFree(s->psiH[c][w]);
+        }
+    }
+    free_films(s);
+    for (auto &src : s->srcs) (void)hipFree(src.table);
+    for (auto &pr : s->probes) (void)hipFree(pr.dev.data);
+    (void)hipFree(s->d_probes);
+    (void)hipFree(s->d_id);
+    (void)hipFree(s->d_mat);
+    (void)hipFree(s->d_step);
+    (void)hipFree(s->d_flag);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return MPX_OK;
+}
+
+mpx_status mpx_query_field(const mpx_sim *s, int32_t field, int64_t dims[4], int64_t *bytes) {
+    if (!s || !dims || field < 0 || field > 11) return MPX_E_INVALID;
+    const int f = field < 6 ? field : 3 + (field - 6) % 3;
+    for (int a = 0; a < 3; a++) dims[a] = natural_dim(s, f, a);
+    dims[3] = field < 6 ? 1 : 3;
+    const size_t esz = field < 6 ? s->esz : 8;
+    if (bytes) *bytes = dims[0] * dims[1] * dims[2] * dims[3] * (int64_t)esz;
+    return MPX_OK;
+}
+
+mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, const uint8_t *cell_ids) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!table || !cell_ids || n < 1 || n > 256) return fail(s, MPX_E_INVALID, "bad material table");
+    const long long ncell = (long long)s->n[0] * s->n[1] * s->n[2];
+    for (long long q = 0; q < ncell; q++)
+        if (cell_ids[q] >= n) return fail(s, MPX_E_INVALID, "cell id outside the material table");
+    std::vector<mpx_material> mats(table, table + n);
+    std::vector<uint8_t> ids(cell_ids, cell_ids + ncell);
+    // a magnetic cell may not sit in, or next to, a PML slab
+    for (int k = 0; k < s->n[2]; k++)
+        for (int j = 0; j < s->n[1]; j++)
+            for (int i = 0; i < s->n[0]; i++) {
+                if (!(mats[ids[i + (size_t)s->n[0] * (j + (size_t)s->n[1] * k)]].Ms > 0)) continue;
+                const int c3[3] = {i, j, k};
+                for (int a = 0; a < 3; a++)
+                    for (int dd = -1; dd <= 1; dd++) {
+                        const int x = c3[a] + dd;
+                        if (x < 0 || x >= s->n[a]) continue;
+                        if (in_pml_cell(s, a, x)) return fail(s, MPX_E_INVALID, "magnetic cell in or next to a PML");
+                    }
+            }
+    s->mats = mats;
+    s->ids = ids;
+    std::vector<FilmHost> films = discover_films(s);
+    if ((int)films.size() > kMaxFilms) return fail(s, MPX_E_INVALID, "more than 64 films");
+    for (auto &f : films) {
+        for (int a = 0; a < 3; a++) {
+            const int lo = f.cb[a], nn = f.cb[3 + a];
+            if (s->per[a] && nn == s->n[a]) {
+                f.b0[a] = 0;
+                f.bn[a] = s->n[a];
+            } else if (lo >= 1 && lo + nn + 1 <= s->n[a]) {
+                f.b0[a] = lo;
+                f.bn[a] = nn + 1;
+            } else {
+                s->have_mat = false;
+                return fail(s, MPX_E_UNSUPPORTED, "film touches a domain face (keep one cell of gap)");
+            }
+        }
+        f.ns = (long long)f.bn[0] * f.bn[1] * f.bn[2];
+    }
+    drop_graph(s);
+    free_films(s);
+    s->films = films;
+    // device copies
+    std::vector<MatDev> md(256);
+    memset(md.data(), 0, md.size() * sizeof(MatDev));
+    for (int q = 0; q < n; q++) {
+        md[q].eps_r = mats[q].eps_r;
+        md[q].sigma = mats[q].sigma;
+        md[q].Ms = mats[q].Ms;
+        md[q].alpha = mats[q].alpha;
+        md[q].gamma_abs = mats[q].gamma_abs;
+        md[q].is_pec = mats[q].is_pec ? 1 : 0;
+    }
+    CK(hipMemcpy(s->d_mat, md.data(), 256 * sizeof(MatDev), hipMemcpyHostToDevice));
+    std::vector<uint8_t> slots(s->nslot, 0);
+    for (int k = 0; k < s->n[2]; k++)
+        for (int j = 0; j < s->n[1]; j++)
+            memcpy(&slots[(size_t)s->px * (j + (size_t)s->n[1] * k)], &ids[(size_t)s->n[0] * (j + (size_t)s->n[1] * k)],
+                   s->n[0]);
+    CK(hipMemcpy(s->d_id, slots.data(), s->nslot, hipMemcpyHostToDevice));
+    std::vector<int4> bt;
+    std::vector<FilmDev> fd;
+    for (int fi = 0; fi < (int)s->films.size(); fi++) {
+        FilmHost &f = s->films[fi];
+        CK(hipMalloc(&f.M, 9 * f.ns * sizeof(double)));
+        CK(hipMalloc(&f.M1, 9 * f.ns * sizeof(double)));
+        CK(hipMalloc(&f.H1, 3 * f.ns * sizeof(double)));
+        CK(hipMemset(f.M, 0, 9 * f.ns * sizeof(double)));
+        CK(hipMemset(f.M1, 0, 9 * f.ns * sizeof(double)));
+        CK(hipMemset(f.H1, 0, 3 * f.ns * sizeof(double)));
+        for (int c = 0; c < 3; c++) {
+            f.blk0[c] = (int)bt.size();
+            const long long tiles = (f.ns + 255) / 256;
+            f.nblk[c] = (int)tiles;
+            for (long long t = 0; t < tiles; t++) bt.push_back(make_int4(fi, c, (int)(t * 256), 0));
+        }
+        FilmDev d{};
+        for (int a = 0; a < 3; a++) {
+            d.b0[a] = f.b0[a];
+            d.bn[a] = f.bn[a];
+            d.blk0[a] = f.blk0[a];
+            d.nblk[a] = f.nblk[a];
+        }
+        for (int a = 0; a < 6; a++) d.cb[a] = f.cb[a];
+        d.ns = f.ns;
+        d.ncells = (double)f.ncells;
+        d.M = f.M;
+        d.M1 = f.M1;
+        d.H1 = f.H1;
+        fd.push_back(d);
+    }
+    s->nblk = (int)bt.size();
+    if (!fd.empty()) {
+        CK(hipMalloc(&s->d_films, fd.size() * sizeof(FilmDev)));
+        CK(hipMemcpy(s->d_films, fd.data(), fd.size() * sizeof(FilmDev), hipMemcpyHostToDevice));
+        CK(hipMalloc(&s->d_blocktab, bt.size() * sizeof(int4)));
+        CK(hipMemcpy(s->d_blocktab, bt.data(), bt.size() * sizeof(int4), hipMemcpyHostToDevice));
+        CK(hipMalloc(&s->d_partial, bt.size() * sizeof(double)));
+        CK(hipMemset(s->d_partial, 0, bt.size() * sizeof(double)));
+    }
+    s->have_mat = true;
+    s->have_u = false;
+    return MPX_OK;
+}
+
+mpx_status mpx_set_bias(mpx_sim *s, double hx, double hy, double hz) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz)) return fail(s, MPX_E_INVALID, "bias");
+    s->H0[0] = hx;
+    s->H0[1] = hy;
+    s->H0[2] = hz;
+    drop_graph(s);
+    return MPX_OK;
+}
+
+mpx_status mpx_init_magnetization(mpx_sim *s, double ux, double uy, double uz) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "init_magnetization before set_materials");
+    const double nrm = std::sqrt(ux * ux + uy * uy + uz * uz);
+    if (!(nrm > 0) || !std::isfinite(nrm)) return fail(s, MPX_E_INVALID, "direction");
+    s->u[0] = ux / nrm;
+    s->u[1] = uy / nrm;
+    s->u[2] = uz / nrm;
+    s->have_u = true;
+    CK(hipStreamSynchronize(s->stream));
+    for (auto &f : s->films) {
+        std::vector<double> m(9 * f.ns, 0.0);
+        for (int c = 0; c < 3; c++)
+            for (long long l = 0; l < f.ns; l++) {
+                const int idx[3] = {f.b0[0] + (int)(l % f.bn[0]), f.b0[1] + (int)((l / f.bn[0]) % f.bn[1]),
+                                    f.b0[2] + (int)(l / ((long long)f.bn[0] * f.bn[1]))};
+                double ms, al, ga;
+                site_params_h(s, c, idx, ms, al, ga);
+                for (int w = 0; w < 3; w++) m[(c * 3 + w) * f.ns + l] = ms > 0 ? ms * s->u[w] : 0.0;
+            }
+        CK(hipMemcpy(f.M, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_add_source(mpx_sim *s, const mpx_source_desc *src, int32_t *id) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!src || src->component < 0 || src->component > 2 || src->n_table < 0 || (!src->table && src->n_table > 0))
+        return fail(s, MPX_E_INVALID, "bad source");
+    if (src->ni < 0 || src->nj < 0 || src->nk < 0) return fail(s, MPX_E_INVALID, "bad source box");
+    if ((int)s->srcs.size() >= kMaxSources) return fail(s, MPX_E_INVALID, "too many sources");
+    SrcHost h{};
+    h.dev.comp = src->component;
+    const int b[6] = {src->i0, src->j0, src->k0, src->ni, src->nj, src->nk};
+    for (int a = 0; a < 6; a++) h.dev.box[a] = b[a];
+    h.dev.n = src->n_table;
+    CK(hipMalloc(&h.table, std::max<int64_t>(1, src->n_table) * sizeof(double)));
+    if (src->n_table > 0)
+        CK(hipMemcpy(h.table, src->table, src->n_table * sizeof(double), hipMemcpyHostToDevice));
+    h.dev.table = h.table;
+    s->srcs.push_back(h);
+    drop_graph(s);
+    if (id) *id = (int32_t)s->srcs.size() - 1;
+    return MPX_OK;
+}
+
+mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!pd || pd->capacity < 1 || pd->kind < 0 || pd->kind > 2) return fail(s, MPX_E_INVALID, "bad probe");
+    if ((int)s->probes.size() >= kMaxProbes) return fail(s, MPX_E_INVALID, "too many probes");
+    ProbeHost h{};
+    h.dev.kind = pd->kind;
+    h.dev.field = pd->field;
+    h.dev.i = pd->i;
+    h.dev.j = pd->j;
+    h.dev.k = pd->k;
+    h.dev.film = pd->film;
+    h.dev.nval = pd->kind == MPX_PROBE_MEAN_M ? 3 : 1;
+    h.dev.cap = pd->capacity;
+    h.dev.start = s->step;
+    if (pd->kind == MPX_PROBE_FIELD) {
+        if (pd->field < 0 || pd->field > 5) return fail(s, MPX_E_INVALID, "probe field");
+        const int idx[3] = {pd->i, pd->j, pd->k};
+        for (int a = 0; a < 3; a++)
+            if (idx[a] < 0 || idx[a] >= natural_dim(s, pd->field, a)) return fail(s, MPX_E_INVALID, "probe index");
+        if (pd->field >= 3) {
+            const int c = pd->field - 3;
+            for (int a = 0; a < 3; a++)
+                if (a != c && idx[a] < s->n[a] && in_pml_cell(s, a, idx[a]))
+                    return fail(s, MPX_E_UNSUPPORTED, "H probe inside a PML slab");
+        }
+    } else {
+        if (!s->have_mat) return fail(s, MPX_E_STATE, "film probe before set_materials");
+        if (pd->film < 0 || pd->film >= (int)s->films.size()) return fail(s, MPX_E_INVALID, "probe film");
+    }
+    CK(hipMalloc(&h.dev.data, pd->capacity * h.dev.nval * sizeof(double)));
+    CK(hipMemset(h.dev.data, 0, pd->capacity * h.dev.nval * sizeof(double)));
+    s->probes.push_back(h);
+    drop_graph(s);
+    if ((r = upload_probes(s)) != MPX_OK) return r;
+    if (id) *id = (int32_t)s->probes.size() - 1;
+    return MPX_OK;
+}
+
+mpx_status mpx_step(mpx_sim *s, int64_t nsteps) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (nsteps < 0) return fail(s, MPX_E_INVALID, "negative step count");
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "step before set_materials");
+    if (!s->films.empty() && !s->have_u) return fail(s, MPX_E_STATE, "step before init_magnetization");
+    if (nsteps == 0) return MPX_OK;
+    r = s->prec == MPX_F64 ? enqueue_steps<double>(s, nsteps) : enqueue_steps<float>(s, nsteps);
+    if (r != MPX_OK) return r;
+    s->step += nsteps;
+    return MPX_OK;
+}
+
+mpx_status mpx_synchronize(mpx_sim *s) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    CK(hipStreamSynchronize(s->stream));
+    int flag = 0;
+    CK(hipMemcpy(&flag, s->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) return fail(s, MPX_E_NONFINITE, "a probe recorded a non-finite value");
+    return MPX_OK;
+}
+
+mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_bytes, int32_t dst_is_device) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    int64_t dims[4], bytes;
+    if (field < 0 || field > 11 || !dst) return fail(s, MPX_E_INVALID, "bad field");
+    mpx_query_field(s, field, dims, &bytes);
+    if (dst_bytes < bytes) return fail(s, MPX_E_RANGE, "destination too small");
+    CK(hipStreamSynchronize(s->stream));
+    std::vector<char> host(bytes, 0);
+    if (field < 6) {
+        std::vector<char> slots(s->nslot * s->esz);
+        void *src = field < 3 ? s->E[field] : s->H[field - 3];
+        CK(hipMemcpy(slots.data(), src, slots.size(), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < dims[2]; k++)
+            for (int64_t j = 0; j < dims[1]; j++) {
+                if (k >= s->n[2] || j >= s->n[1]) continue;
+                const int64_t ni = std::min<int64_t>(dims[0], s->n[0]);
+                memcpy(&host[(size_t)(dims[0] * (j + dims[1] * k)) * s->esz],
+                       &slots[(size_t)(s->px * (j + (int64_t)s->n[1] * k)) * s->esz], ni * s->esz);
+            }
+    } else {
+        const int c = (field - 6) % 3;
+        const bool delta = field >= 9;
+        double *h = (double *)host.data();
+        const int64_t nsite = dims[0] * dims[1] * dims[2];
+        for (auto &f : s->films) {
+            std::vector<double> m(9 * f.ns);
+            CK(hipMemcpy(m.data(), f.M, m.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (long long l = 0; l < f.ns; l++) {
+                const int idx[3] = {f.b0[0] + (int)(l % f.bn[0]), f.b0[1] + (int)((l / f.bn[0]) % f.bn[1]),
+                                    f.b0[2] + (int)(l / ((long long)f.bn[0] * f.bn[1]))};
+                double ms, al, ga;
+                site_params_h(s, c, idx, ms, al, ga);
+                if (!(ms > 0)) continue;
+                const int64_t q = idx[0] + dims[0] * (idx[1] + dims[1] * (int64_t)idx[2]);
+                for (int w = 0; w < 3; w++) {
+                    double v = m[(c * 3 + w) * f.ns + l];
+                    if (delta) v -= (s->have_u ? ms * s->u[w] : 0.0);
+                    h[w * nsite + q] = v;
+                }
+            }
+        }
+    }
+    if (dst_is_device)
+        CK(hipMemcpy(dst, host.data(), bytes, hipMemcpyHostToDevice));
+    else
+        memcpy(dst, host.data(), bytes);
+    return MPX_OK;
+}
+
+mpx_status mpx_write_field(mpx_sim *s, int32_t field, const void *src, int64_t src_bytes, int32_t src_is_device) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    int64_t dims[4], bytes;
+    if (field < 0 || field > 8 || !src) return fail(s, MPX_E_INVALID, "bad field");
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "write_field before set_materials");
+    mpx_query_field(s, field, dims, &bytes);
+    if (src_bytes < bytes) return fail(s, MPX_E_RANGE, "source too small");
+    CK(hipStreamSynchronize(s->stream));
+    std::vector<char> host(bytes);
+    if (src_is_device)
+        CK(hipMemcpy(host.data(), src, bytes, hipMemcpyDeviceToHost));
+    else
+        memcpy(host.data(), src, bytes);
+    if (field < 6) {
+        std::vector<char> slots(s->nslot * s->esz, 0);
+        for (int64_t k = 0; k < std::min<int64_t>(dims[2], s->n[2]); k++)
+            for (int64_t j = 0; j < std::min<int64_t>(dims[1], s->n[1]); j++)
+                for (int64_t i = 0; i < std::min<int64_t>(dims[0], s->n[0]); i++) {
+                    const int idx[3] = {(int)i, (int)j, (int)k};
+                    if (field < 3 && edge_is_pec_h(s, field, idx)) continue;
+                    memcpy(&slots[(size_t)(i + s->px * (j + (int64_t)s->n[1] * k)) * s->esz],
+                           &host[(size_t)(i + dims[0] * (j + dims[1] * k)) * s->esz], s->esz);
+                }
+        void *dstp = field < 3 ? s->E[field] : s->H[field - 3];
+        CK(hipMemcpy(dstp, slots.data(), slots.size(), hipMemcpyHostToDevice));
+    } else {
+        const int c = field - 6;
+        const double *h = (const double *)host.data();
+        const int64_t nsite = dims[0] * dims[1] * dims[2];
+        for (auto &f : s->films) {
+            std::vector<double> m(9 * f.ns);
+            CK(hipMemcpy(m.data(), f.M, m.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (long long l = 0; l < f.ns; l++) {
+                const int idx[3] = {f.b0[0] + (int)(l % f.bn[0]), f.b0[1] + (int)((l / f.bn[0]) % f.bn[1]),
+                                    f.b0[2] + (int)(l / ((long long)f.bn[0] * f.bn[1]))};
+                double ms, al, ga;
+                site_params_h(s, c, idx, ms, al, ga);
+                if (!(ms > 0)) continue;
+                const int64_t q = idx[0] + dims[0] * (idx[1] + dims[1] * (int64_t)idx[2]);
+                for (int w = 0; w < 3; w++) m[(c * 3 + w) * f.ns + l] = h[w * nsite + q];
+            }
+            CK(hipMemcpy(f.M, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_read_probe(mpx_sim *s, int32_t id, double *dst, int64_t capacity, int64_t *n_written) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (id < 0 || id >= (int)s->probes.size() || !n_written) return fail(s, MPX_E_INVALID, "bad probe id");
+    const ProbeDev &P = s->probes[id].dev;
+    const long long samples = s->step - P.start;
+    const long long have = std::min<long long>(samples, P.cap);
+    *n_written = have;
+    if (capacity < have || (!dst && have > 0)) return fail(s, MPX_E_RANGE, "probe destination too small");
+    CK(hipStreamSynchronize(s->stream));
+    std::vector<double> buf(P.cap * P.nval);
+    CK(hipMemcpy(buf.data(), P.data, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const long long first = samples - have;
+    for (long long t = 0; t < have; t++) {
+        const long long slot = (first + t) % P.cap;
+        for (int w = 0; w < P.nval; w++) dst[t * P.nval + w] = buf[slot * P.nval + w];
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_energy(mpx_sim *s, double *W_em, double *W_z) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!W_em || !W_z) return MPX_E_INVALID;
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "energy before set_materials");
+    if (s->any_pml) return fail(s, MPX_E_UNSUPPORTED, "energy with PML faces");
+    const long long nb = (long long)((s->n[0] + 63) / 64) * ((s->n[1] + 3) / 4) * s->n[2];
+    double *part = nullptr, *out = nullptr;
+    CK(hipMalloc(&part, 2 * nb * sizeof(double)));
+    CK(hipMalloc(&out, 3 * sizeof(double)));
+    CK(hipMemsetAsync(out, 0, 3 * sizeof(double), s->stream));
+    hipError_t e;
+    if (s->prec == MPX_F64) {
+        KParams<double> p;
+        fill_params<double>(s, p);
+        e = launch_energy<double>(p, s->nblk, part, out, s->stream);
+    } else {
+        KParams<float> p;
+        fill_params<float>(s, p);
+        e = launch_energy<float>(p, s->nblk, part, out, s->stream);
+    }
+    if (e != hipSuccess) return dev_fail(s, e, "energy kernels");
+    double h[3];
+    CK(hipStreamSynchronize(s->stream));
+    CK(hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
+    (void)hipFree(part);
+    (void)hipFree(out);
+    const double dV = s->d[0] * s->d[1] * s->d[2];
+    *W_em = 0.5 * dV * (h[0] + MU0 * h[1]);
+    *W_z = -MU0 * dV * h[2];
+    return MPX_OK;
+}
+
+mpx_status mpx_info(const mpx_sim *s, int64_t *step, double *time, double *dt, int32_t *n_films) {
+    if (!s) return MPX_E_INVALID;
+    if (step) *step = s->step;
+    if (time) *time = s->step * s->dt;
+    if (dt) *dt = s->dt;
+    if (n_films) *n_films = (int32_t)s->films.size();
+    return MPX_OK;
+}
+
+mpx_status mpx_film_box(const mpx_sim *s, int32_t film, int32_t box[6], int64_t *ncells) {
+    if (!s || !box || film < 0 || film >= (int)s->films.size()) return MPX_E_INVALID;
+    for (int a = 0; a < 6; a++) box[a] = s->films[film].cb[a];
+    if (ncells) *ncells = s->films[film].ncells;
+    return MPX_OK;
+}
+
+mpx_status mpx_set_graph_steps(mpx_sim *s, int32_t steps) {
+    if (!s || steps < 0) return MPX_E_INVALID;
+    if (steps != s->graph_steps) drop_graph(s);
+    s->graph_steps = steps;
+    return MPX_OK;
+}
+
+mpx_status mpx_set_timing(mpx_sim *s, int32_t every) {
+    if (!s || every < 0) return MPX_E_INVALID;
+    s->timing_every = every;
+    return MPX_OK;
+}
+
+mpx_status mpx_kernel_time(mpx_sim *s, double *avg_ms, int64_t *launches) {
+    if (!s || !avg_ms || !launches) return MPX_E_INVALID;
+    // E pass and merged H pass, the two stencil kernels
+    avg_ms[0] = s->t_n[0] ? s->t_ms[0] / s->t_n[0] : 0.0;
+    avg_ms[1] = s->t_n[1] ? s->t_ms[1] / s->t_n[1] : 0.0;
+    launches[0] = s->t_n[0];
+    launches[1] = s->t_n[1];
+    return MPX_OK;
+}
+
+const char *mpx_last_error(const mpx_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+} // extern "C"

@@ -1,0 +1,102 @@
+// mpx_internal.h -- device-side data structures of libmpx and the launcher
+// declarations shared by kernels.hip and host.hip.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpx {
+
+constexpr int kMaxSources = 16;
+constexpr int kMaxProbes = 64;
+constexpr int kMaxFilms = 64;
+
+struct MatDev {
+    double eps_r, sigma, Ms, alpha, gamma_abs;
+    int is_pec, pad;
+};
+
+// A film: cell box cb (i0,j0,k0,ni,nj,nk), the slot box of its face sites
+// (b0, bn; the cell box grown by one face on each non-spanned axis), and the
+// magnetisation of every face family stored over that box, float64:
+//   M [family][component][site], the state
+//   M1[family][component][site], H1[family][site], the scratch of the first
+//   half step of a merged pair (the values at the integer time)
+struct FilmDev {
+    int b0[3], bn[3];
+    int cb[6];
+    long long ns;
+    double ncells;
+    double *M, *M1, *H1;
+    int blk0[3], nblk[3];
+};
+
+struct SrcDev {
+    int comp;
+    int box[6];
+    long long n;
+    const double *table;
+};
+
+struct ProbeDev {
+    int kind, field, i, j, k, film, nval, pad;
+    long long cap, start;
+    double *data;
+};
+
+template <typename T>
+struct KParams {
+    int n[3];
+    int px;
+    int per[3];
+    double d[3];
+    T dT[3];
+    T invd[3];
+    T hc;        // dt / (2 mu0)
+    double hcd;  // the same in float64
+    double dt, inv_dt, eps0, mu0, kf, dV;
+    double H0[3];
+    T *E[3];
+    T *H[3];
+    const uint8_t *id;
+    const MatDev *mat;
+    int nlo[3], nhi[3];
+    const T *bE[3];
+    const T *cE[3];
+    const T *bH[3];
+    const T *cH[3];
+    T *psiE[3][3]; // [component][derivative axis]
+    T *psiH[3][3];
+    int nfilm;
+    const FilmDev *films;
+    const int4 *blocktab;
+    double *partial;
+    int nsrc;
+    SrcDev src[kMaxSources];
+    const ProbeDev *probes;
+    long long *step;
+    int *flag;
+
+    __host__ __device__ long long slot(int i, int j, int k) const {
+        return (long long)i + (long long)px * ((long long)j + (long long)n[1] * k);
+    }
+    // CPML slab storage along axis w: slab position sp in [0, nlo + nhi)
+    __host__ __device__ long long psi_index(int w, const int *idx) const {
+        const int S = nlo[w] + nhi[w];
+        const int p = idx[w];
+        const int sp = p < nlo[w] ? p : nlo[w] + (p - (n[w] - nhi[w]));
+        if (w == 0) return (long long)sp + (long long)S * ((long long)idx[1] + (long long)n[1] * idx[2]);
+        if (w == 1) return (long long)idx[0] + (long long)px * ((long long)sp + (long long)S * idx[2]);
+        return (long long)idx[0] + (long long)px * ((long long)idx[1] + (long long)n[1] * sp);
+    }
+};
+
+template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s);
+template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
+template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, hipStream_t s);
+template <typename T> hipError_t launch_commit(const KParams<T> &p, int nblk, hipStream_t s);
+template <typename T> hipError_t launch_probes(const KParams<T> &p, int nprobe, hipStream_t s);
+template <typename T>
+hipError_t launch_energy(const KParams<T> &p, int nblk, double *part, double *out, hipStream_t s);
+
+} // namespace mpx

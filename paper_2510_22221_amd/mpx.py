@@ -1,0 +1,294 @@
+"""ctypes binding of libmpx (include/mpx.h): argument marshalling only.
+
+Every step of the coupled Yee + LLG update runs in the HIP kernels of
+``libmpx.so``; this module converts Python/numpy/torch arguments to the C ABI
+and back.  There is no fallback: if the shared library is missing or was not
+built for this tree, loading raises.
+
+PyTorch is optional plumbing: a torch stream can be handed to the library
+(``stream=torch.cuda.current_stream()``) and fields can be read into, or
+written from, CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpx.h")
+
+F64, F32 = 0, 1
+PEC, PML, PERIODIC = 0, 1, 2
+EX, EY, EZ, HX, HY, HZ, MXF, MYF, MZF, DMXF, DMYF, DMZF = range(12)
+PROBE_FIELD, PROBE_MEAN_M, PROBE_FILM_ENERGY = 0, 1, 2
+ABI_VERSION = 1
+
+STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4: "MPX_E_DEVICE",
+          5: "MPX_E_UNSUPPORTED", 6: "MPX_E_RANGE", 7: "MPX_E_NONFINITE"}
+
+# every function the header declares (checked by the CPU test suite)
+EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "mpx_set_materials",
+           "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
+           "mpx_synchronize", "mpx_read_field", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
+           "mpx_film_box", "mpx_set_graph_steps", "mpx_set_timing", "mpx_kernel_time", "mpx_last_error"]
+
+
+class MpxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("courant", C.c_double), ("dt", C.c_double),
+                ("bc", C.c_int32 * 6), ("pml_cells", C.c_int32 * 6),
+                ("pml_order", C.c_double), ("pml_sigma_factor", C.c_double)]
+
+
+class Material(C.Structure):
+    _fields_ = [("eps_r", C.c_double), ("sigma", C.c_double), ("is_pec", C.c_int32),
+                ("Ms", C.c_double), ("alpha", C.c_double), ("gamma_abs", C.c_double)]
+
+
+class SourceDesc(C.Structure):
+    _fields_ = [("component", C.c_int32), ("i0", C.c_int32), ("j0", C.c_int32), ("k0", C.c_int32),
+                ("ni", C.c_int32), ("nj", C.c_int32), ("nk", C.c_int32),
+                ("table", C.c_void_p), ("n_table", C.c_int64)]
+
+
+class ProbeDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("field", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
+                ("k", C.c_int32), ("film", C.c_int32), ("capacity", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmpx.so; raises if it is absent (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmpx.so not found at {path}: build it with paper_2510_22221_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    L = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "mpx_abi_version": (C.c_uint32, []),
+        "mpx_create": (I32, [C.POINTER(GridDesc), I32, I32, P, C.POINTER(P)]),
+        "mpx_destroy": (I32, [P]),
+        "mpx_query_field": (I32, [P, I32, C.POINTER(I64), C.POINTER(I64)]),
+        "mpx_set_materials": (I32, [P, C.POINTER(Material), I32, P]),
+        "mpx_set_bias": (I32, [P, D, D, D]),
+        "mpx_init_magnetization": (I32, [P, D, D, D]),
+        "mpx_add_source": (I32, [P, C.POINTER(SourceDesc), C.POINTER(I32)]),
+        "mpx_add_probe": (I32, [P, C.POINTER(ProbeDesc), C.POINTER(I32)]),
+        "mpx_step": (I32, [P, I64]),
+        "mpx_synchronize": (I32, [P]),
+        "mpx_read_field": (I32, [P, I32, P, I64, I32]),
+        "mpx_write_field": (I32, [P, I32, P, I64, I32]),
+        "mpx_read_probe": (I32, [P, I32, P, I64, C.POINTER(I64)]),
+        "mpx_energy": (I32, [P, C.POINTER(D), C.POINTER(D)]),
+        "mpx_info": (I32, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]),
+        "mpx_film_box": (I32, [P, I32, C.POINTER(I32), C.POINTER(I64)]),
+        "mpx_set_graph_steps": (I32, [P, I32]),
+        "mpx_set_timing": (I32, [P, I32]),
+        "mpx_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64)]),
+        "mpx_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if L.mpx_abi_version() != ABI_VERSION:
+        raise RuntimeError("libmpx ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Sim:
+    """One coupled Yee + LLG simulation on one GPU."""
+
+    def __init__(self, nx, ny, nz, d, dt=0.0, courant=0.9, bc=(PEC,) * 6, npml=(0,) * 6, pml_order=3.0,
+                 pml_factor=0.8, precision=F64, device=0, stream=None):
+        self._L = load()
+        g = GridDesc()
+        g.nx, g.ny, g.nz = int(nx), int(ny), int(nz)
+        g.dx, g.dy, g.dz = (float(v) for v in d)
+        g.courant = float(courant)
+        g.dt = float(dt)
+        for a in range(6):
+            g.bc[a] = int(bc[a])
+            g.pml_cells[a] = int(npml[a])
+        g.pml_order = float(pml_order)
+        g.pml_sigma_factor = float(pml_factor)
+        h = C.c_void_p()
+        rc = self._L.mpx_create(C.byref(g), int(precision), int(device), _stream_ptr(stream), C.byref(h))
+        if rc != 0:
+            raise MpxError(rc, "mpx_create")
+        self._h = h
+        self.precision = precision
+        self.shape = (int(nz), int(ny), int(nx))
+        self.dtype = np.float64 if precision == F64 else np.float32
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.mpx_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, rc, what):
+        if rc != 0:
+            raise MpxError(rc, f"{what}: {self._L.mpx_last_error(self._h).decode()}")
+
+    # ---- setup -------------------------------------------------------------
+    def set_materials(self, table, ids):
+        n = len(table)
+        mats = (Material * n)()
+        for q, m in enumerate(table):
+            mats[q].eps_r, mats[q].sigma, mats[q].is_pec = float(m[0]), float(m[1]), int(m[2])
+            mats[q].Ms, mats[q].alpha, mats[q].gamma_abs = float(m[3]), float(m[4]), float(m[5])
+        ids = np.ascontiguousarray(ids, dtype=np.uint8)
+        if ids.shape != self.shape:
+            raise ValueError("ids must have shape (nz, ny, nx)")
+        self._ck(self._L.mpx_set_materials(self._h, mats, n, ids.ctypes.data), "set_materials")
+
+    def set_bias(self, h0):
+        self._ck(self._L.mpx_set_bias(self._h, *(float(v) for v in h0)), "set_bias")
+
+    def init_magnetization(self, u):
+        self._ck(self._L.mpx_init_magnetization(self._h, *(float(v) for v in u)), "init_magnetization")
+
+    def add_source(self, comp, box, table):
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        sd = SourceDesc(int(comp), *(int(b) for b in box), t.ctypes.data, t.size)
+        sid = C.c_int32()
+        self._ck(self._L.mpx_add_source(self._h, C.byref(sd), C.byref(sid)), "add_source")
+        return sid.value
+
+    def add_probe(self, kind, field=0, ijk=(0, 0, 0), film=0, cap=1 << 16):
+        pd = ProbeDesc(int(kind), int(field), *(int(v) for v in ijk), int(film), int(cap))
+        pid = C.c_int32()
+        self._ck(self._L.mpx_add_probe(self._h, C.byref(pd), C.byref(pid)), "add_probe")
+        return pid.value
+
+    def set_graph_steps(self, n):
+        self._ck(self._L.mpx_set_graph_steps(self._h, int(n)), "set_graph_steps")
+
+    def set_timing(self, every):
+        """0: off; n > 0: event-time every n-th step (direct launches)."""
+        self._ck(self._L.mpx_set_timing(self._h, int(every)), "set_timing")
+
+    # ---- stepping ------------------------------------------------------------
+    def step(self, n):
+        self._ck(self._L.mpx_step(self._h, int(n)), "step")
+
+    def sync(self):
+        self._ck(self._L.mpx_synchronize(self._h), "synchronize")
+
+    def kernel_time(self):
+        """(avg ms per launch, launches) of the E pass and the H pass."""
+        ms = (C.c_double * 2)()
+        n = (C.c_int64 * 2)()
+        self._ck(self._L.mpx_kernel_time(self._h, ms, n), "kernel_time")
+        return [(ms[q], n[q]) for q in range(2)]
+
+    # ---- fields ------------------------------------------------------------------
+    def dims(self, field):
+        d = (C.c_int64 * 4)()
+        nb = C.c_int64()
+        self._ck(self._L.mpx_query_field(self._h, int(field), d, C.byref(nb)), "query_field")
+        return tuple(int(v) for v in d), int(nb.value)
+
+    def get(self, field, out=None):
+        (nx, ny, nz, nc), nb = self.dims(field)
+        dt = np.float64 if field >= 6 else self.dtype
+        if out is not None and hasattr(out, "data_ptr"):  # torch CUDA tensor
+            if out.numel() * out.element_size() < nb:
+                raise ValueError("output tensor too small")
+            self._ck(self._L.mpx_read_field(self._h, int(field), C.c_void_p(out.data_ptr()), nb, 1), "read_field")
+            return out
+        arr = np.empty((nc, nz, ny, nx), dtype=dt)
+        self._ck(self._L.mpx_read_field(self._h, int(field), arr.ctypes.data, nb, 0), "read_field")
+        return arr[0] if nc == 1 else arr
+
+    def set(self, field, arr):
+        (nx, ny, nz, nc), nb = self.dims(field)
+        if hasattr(arr, "data_ptr"):
+            self._ck(self._L.mpx_write_field(self._h, int(field), C.c_void_p(arr.data_ptr()), nb, 1), "write_field")
+            return
+        dt = np.float64 if field >= 6 else self.dtype
+        a = np.ascontiguousarray(arr, dtype=dt).reshape(-1)
+        if a.size * a.itemsize != nb:
+            raise ValueError("wrong field size")
+        self._ck(self._L.mpx_write_field(self._h, int(field), a.ctypes.data, nb, 0), "write_field")
+
+    def read_probe(self, pid, nval=1):
+        n = C.c_int64()
+        rc = self._L.mpx_read_probe(self._h, int(pid), None, 0, C.byref(n))
+        if rc not in (0, 6):
+            self._ck(rc, "read_probe")
+        buf = np.empty(max(1, n.value) * nval, dtype=np.float64)
+        self._ck(self._L.mpx_read_probe(self._h, int(pid), buf.ctypes.data, n.value, C.byref(n)), "read_probe")
+        out = buf[: n.value * nval]
+        return out.reshape(n.value, nval) if nval > 1 else out
+
+    def energy(self):
+        a, b = C.c_double(), C.c_double()
+        self._ck(self._L.mpx_energy(self._h, C.byref(a), C.byref(b)), "energy")
+        return a.value, b.value
+
+    def info(self):
+        st, t, dt, nf = C.c_int64(), C.c_double(), C.c_double(), C.c_int32()
+        self._ck(self._L.mpx_info(self._h, C.byref(st), C.byref(t), C.byref(dt), C.byref(nf)), "info")
+        return {"step": st.value, "time": t.value, "dt": dt.value, "films": nf.value}
+
+    def films(self):
+        out = []
+        for f in range(self.info()["films"]):
+            box = (C.c_int32 * 6)()
+            nc = C.c_int64()
+            self._ck(self._L.mpx_film_box(self._h, f, box, C.byref(nc)), "film_box")
+            out.append((tuple(int(v) for v in box), int(nc.value)))
+        return out
+
+
+def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None):
+    """Build a Sim from a ``synth.workloads.Workload`` (same inputs the
+    oracle takes)."""
+    s = Sim(w.nx, w.ny, w.nz, w.d, dt=w.dt, courant=w.courant, bc=w.bc, npml=w.npml, pml_order=w.pml_order,
+            pml_factor=w.pml_factor, precision=precision, device=device, stream=stream)
+    s.set_materials(w.materials, w.ids)
+    s.set_bias(w.H0)
+    s.init_magnetization(w.m_dir)
+    for f, arr in (w.init_fields or {}).items():
+        s.set(f, arr)
+    for src in w.sources:
+        s.add_source(src.comp, src.box, src.table)
+    for p in w.probes:
+        kind = {"field": PROBE_FIELD, "mean_m": PROBE_MEAN_M, "film_energy": PROBE_FILM_ENERGY}[p.kind]
+        s.add_probe(kind, p.field, p.ijk, p.film, cap=max(1, p.cap or w.nsteps))
+    if graph_steps is not None:
+        s.set_graph_steps(graph_steps)
+    return s

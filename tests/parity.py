@@ -1,0 +1,60 @@
+"""Helpers for GPU-vs-oracle parity (test infrastructure).
+
+Relative L2 is taken per group, as the parity metric is defined: {E}, {H}
+and {M - M0} (M itself would hide errors behind the large M0), plus each
+probe trace.
+"""
+import numpy as np
+
+import oracle.oracle as O
+from paper_2510_22221_amd import mpx
+
+GROUPS = {"E": (0, 1, 2), "H": (3, 4, 5), "dM": (9, 10, 11)}
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return float(np.linalg.norm(a))
+    return float(np.linalg.norm(a - b) / nb)
+
+
+def group_errors(g, o):
+    out = {}
+    for name, fields in GROUPS.items():
+        a = np.concatenate([np.asarray(g.get(f), dtype=np.float64).ravel() for f in fields])
+        b = np.concatenate([o.get(f).ravel() for f in fields])
+        out[name] = rel(a, b)
+    return out
+
+
+def probe_errors(g, o, w):
+    out = []
+    for pid, p in enumerate(w.probes):
+        nval = 3 if p.kind == "mean_m" else 1
+        a = g.read_probe(pid, nval)
+        b = o.read_probe(pid, nval)
+        if p.kind == "mean_m":
+            # The film average is ~Ms, so its relative L2 is dominated by the
+            # offset; also bound the absolute difference, which is limited by
+            # the summation order of the film sum (~1 ulp of Ms).
+            scale = float(np.abs(b).max())
+            assert float(np.abs(a - b).max()) <= 1e-14 * scale, "mean-M probe"
+        out.append(rel(a, b))
+    return out
+
+
+def run_pair(w, nsteps, precision=mpx.F64, graph_steps=None, threads=None, chunks=1):
+    o = O.from_workload(w, threads=threads)
+    g = mpx.from_workload(w, precision=precision, graph_steps=graph_steps)
+    per = nsteps // chunks
+    done = 0
+    for c in range(chunks):
+        n = per if c < chunks - 1 else nsteps - done
+        g.step(n)
+        o.step(n)
+        done += n
+    g.sync()
+    return g, o

@@ -1,0 +1,221 @@
+"""GPU (libmpx, gfx950) against the FP64 oracle, element by element.
+
+Tolerances: float64 mode 1e-11 relative L2 per group ({E}, {H}, {M - M0})
+and per probe trace; float32 mode 1e-4.  The float64 kernels evaluate every
+value in the oracle's operation order, so most float64 cases agree bitwise.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from paper_2510_22221_amd import mpx
+from synth import workloads as W
+from tests.parity import group_errors, probe_errors, rel, run_pair
+from tests.spectral import tone_frequency
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+
+F64_TOL = 1e-11
+F32_TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _libs():
+    O.build()
+    mpx.load()
+
+
+def check(g, o, w, tol):
+    errs = group_errors(g, o)
+    perr = probe_errors(g, o, w)
+    say(f"  groups {errs}  probes max {max(perr) if perr else 0:.2e}")
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    for v in perr:
+        assert v <= tol
+
+
+# ------------------------------------------------------------------ C1
+@pytest.mark.parametrize("prec,tol", [(mpx.F64, F64_TOL), (mpx.F32, F32_TOL)])
+def test_c1_full(prec, tol):
+    w = W.c1(2000)
+    say(f"C1 32^3 2000 steps prec={prec}")
+    g, o = run_pair(w, 2000, prec, threads=THREADS, chunks=3)
+    check(g, o, w, tol)
+
+
+def test_c1_f64_bitwise_and_graph_invariant():
+    """Graph capture, chunking and repeats do not change float64 results."""
+    w = W.c1(300)
+    say("C1 300 steps: graphs off vs graphs of 7 vs chunked")
+    a = mpx.from_workload(w, graph_steps=0)
+    a.step(300)
+    b = mpx.from_workload(w, graph_steps=7)
+    for n in (1, 2, 97, 200):
+        b.step(n)
+    o = O.from_workload(w, threads=THREADS)
+    o.step(300)
+    for f in (0, 1, 2, 3, 4, 5, 6, 7, 8):
+        assert np.array_equal(a.get(f), b.get(f)), f
+    for pid, p in enumerate(w.probes):
+        nval = 3 if p.kind == "mean_m" else 1
+        assert np.array_equal(a.read_probe(pid, nval), b.read_probe(pid, nval))
+    errs = group_errors(a, o)
+    say(f"  vs oracle {errs}")
+    assert max(errs.values()) <= F64_TOL
+
+
+# ------------------------------------------------------------------ random cases
+CASES = [
+    ("pec", (W.PEC,) * 6, (0,) * 6),
+    ("periodic-x", (W.PERIODIC, W.PERIODIC, W.PEC, W.PEC, W.PEC, W.PEC), (0,) * 6),
+    ("pml", (W.PML,) * 6, (2,) * 6),
+    ("mixed", (W.PML, W.PEC, W.PERIODIC, W.PERIODIC, W.PEC, W.PML), (2, 0, 0, 0, 0, 3)),
+]
+
+
+@pytest.mark.parametrize("name,bc,npml", CASES)
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_fields_materials(name, bc, npml, seed):
+    """Random dielectric / conductor / PEC cells, two magnetic materials in
+    one film, random initial E and H, a source; ragged sizes."""
+    film = name != "pml"
+    nx, ny, nz = (13, 11, 9) if film else (17, 12, 10)
+    w = W.random_case(seed, nx=nx, ny=ny, nz=nz, bc=bc, npml=npml, film=film, nsteps=25)
+    if name == "pml":   # the random film would sit inside the slabs
+        w.ids[w.ids == 3] = 0
+        w.ids[w.ids == 5] = 0
+    rng = np.random.default_rng(100 + seed)
+    o = O.from_workload(w)
+    init = {}
+    for f in range(6):
+        nx_, ny_, nz_, _ = o.dims(f)
+        v = rng.normal(size=(nz_, ny_, nx_)) * (1.0 if f < 3 else 1 / 377.0)
+        if f >= 3:   # H normal to a non-periodic wall starts at zero
+            c = f - 3
+            if not (bc[2 * c] == W.PERIODIC):
+                sl = [slice(None)] * 3
+                sl[2 - c] = 0
+                v[tuple(sl)] = 0
+                sl[2 - c] = -1
+                v[tuple(sl)] = 0
+        init[f] = v
+    w.init_fields = init
+    say(f"random {name} seed {seed} {nx}x{ny}x{nz}")
+    for prec, tol in ((mpx.F64, F64_TOL), (mpx.F32, 1e-4)):
+        g, o = run_pair(w, 25, prec, chunks=2)
+        check(g, o, w, tol)
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 3])
+def test_tiny_step_counts(nsteps):
+    w = W.c1(nsteps)
+    say(f"C1 {nsteps} steps")
+    g, o = run_pair(w, nsteps)
+    check(g, o, w, F64_TOL)
+
+
+def test_degenerate_one_cell_periodic_axes():
+    """1 x 1 x N column, periodic laterally: plane wave along z."""
+    w = W.box(1, 1, 48, bc=(W.PERIODIC,) * 4 + (W.PEC, W.PEC), nsteps=200)
+    z = (np.arange(49) * w.d[2])
+    e0 = np.sin(3 * math.pi * z / (48 * w.d[2]))[:, None, None] * np.ones((1, 1, 1))
+    e0[0] = e0[-1] = 0
+    w.init_fields = {0: e0}
+    say("1x1x48 column")
+    g, o = run_pair(w, 200)
+    check(g, o, w, F64_TOL)
+
+
+# ------------------------------------------------------------------ physics on the GPU, FP32
+def test_f32_larmor_frequency():
+    """Uniform periodic macrospin (every cell magnetic) in float32 mode:
+    precession frequency within 0.1% of the float64 oracle."""
+    w = W.box(4, 4, 4, bc=(W.PERIODIC,) * 6, nsteps=0)
+    w.materials = [(1.0, 0.0, 0, 1.4e5, 0.0, W.GAMMA)]
+    w.H0 = (0.0, 0.0, 8e4)
+    th = math.radians(10)
+    w.m_dir = (math.sin(th), 0.0, math.cos(th))
+    Om = np.linalg.norm(np.array(w.H0) + 1.4e5 * np.array(w.m_dir))
+    f_exp = 4e-7 * math.pi * W.GAMMA * Om / (2 * math.pi)
+    n = int(1.2 / (f_exp * w.dt))
+    w.nsteps = n
+    w.probes = [W.Probe("mean_m", film=0, cap=n)]
+    say(f"Larmor f32 {n} steps")
+    g = mpx.from_workload(w, precision=mpx.F32)
+    g.step(n)
+    g.sync()
+    f = tone_frequency(g.read_probe(0, 3)[:, 0], w.dt)
+    assert abs(f / f_exp - 1) < 1e-3, (f, f_exp)
+
+
+def test_f32_thin_film_kittel_frequency():
+    """In-plane thin film between PEC plates (the oracle's Kittel pin) run on
+    the GPU in float32: frequency within 0.1% of the float64 oracle trace."""
+    nz, t = 32, 2
+    d = (50e-6, 50e-6, 2e-6)
+    w = W.box(2, 2, nz, d=d, bc=(W.PERIODIC,) * 4 + (W.PEC, W.PEC))
+    w.materials = [W.VACUUM, (1.0, 0.0, 0, 1.4e5, 0.0, W.GAMMA)]
+    w.ids[15:15 + t] = 1
+    tilt = math.radians(1.0)
+    w.H0, w.m_dir = (8e4, 0.0, 0.0), (math.cos(tilt), math.sin(tilt), 0.0)
+    f_exp = 4e-7 * math.pi * W.GAMMA / (2 * math.pi) * math.sqrt((8e4 + 1.4e5 * t / nz) * (8e4 + 1.4e5))
+    n = int(1.6 / (f_exp * w.dt))
+    w.nsteps = n
+    w.probes = [W.Probe("mean_m", film=0, cap=n)]
+    say(f"thin film f32 {n} steps")
+    g = mpx.from_workload(w, precision=mpx.F32)
+    g.step(n)
+    g.sync()
+    o = O.from_workload(w)
+    o.step(n)
+    fg = tone_frequency(g.read_probe(0, 3)[:, 1], w.dt)
+    fo = tone_frequency(o.read_probe(0, 3)[:, 1], w.dt)
+    say(f"  f gpu {fg:.6e} oracle {fo:.6e} expected {f_exp:.6e}")
+    assert abs(fg / fo - 1) < 1e-3
+    assert rel(g.read_probe(0, 3)[:, 1] - g.read_probe(0, 3)[:1, 1], o.read_probe(0, 3)[:, 1] - o.read_probe(0, 3)[:1, 1]) < 1e-3
+
+
+# ------------------------------------------------------------------ C2 (scaled and full size)
+@pytest.mark.parametrize("prec,tol", [(mpx.F64, F64_TOL), (mpx.F32, F32_TOL)])
+def test_c2_scaled(prec, tol):
+    w = W.c2(300, nx=128, ny=64, nz=64)
+    say(f"C2 scaled 128x64x64 300 steps prec={prec}")
+    g, o = run_pair(w, 300, prec, threads=THREADS, chunks=2)
+    check(g, o, w, tol)
+
+
+def test_c2_full_size_f64():
+    """The benchmark's workload at full size, 12 steps in the benchmark's
+    launch configuration (graph of the default length not reached: direct)."""
+    w = W.c2(12)
+    say("C2 full 512x256x128, 12 steps, F64")
+    g, o = run_pair(w, 12, mpx.F64, threads=THREADS)
+    check(g, o, w, F64_TOL)
+
+
+# ------------------------------------------------------------------ energy and watchdog
+def test_energy_matches_oracle():
+    w = W.c1(50)
+    g, o = run_pair(w, 50)
+    ge, oe = g.energy(), o.energy()
+    assert abs(ge[0] / oe[0] - 1) < 1e-12 and abs(ge[1] / oe[1] - 1) < 1e-12
+
+
+def test_nonfinite_watchdog():
+    w = W.c1(3)
+    g = mpx.from_workload(w)
+    e = g.get(mpx.EZ)
+    e[16, 16, 8] = np.nan
+    g.set(mpx.EZ, e)
+    g.step(2)
+    with pytest.raises(mpx.MpxError, match="NONFINITE"):
+        g.sync()
