@@ -33,24 +33,26 @@ def log(msg):
 
 
 def algorithmic_bytes(w, esz):
-    """Bytes one launch of each stencil kernel must move, per full step.
-    E pass: read E(3) H(3) and the uint8 id, write E(3); plus read+write of
-    the two E-type CPML psi per slab cell and slab axis.  H pass (merged):
-    read E(3) H(3), write H(3); plus the two H-type psi per slab cell."""
+    """Bytes each stencil kernel must move per launch (one full step).
+    Fused pass: read E(3), H(3) and the uint8 id, write E(3), H(3); per slab
+    cell and slab axis, read + write the two E-type and the two H-type CPML
+    psi.  Two-pass schedule: the E pass reads E, H, id and writes E (+ the
+    E-type psi), the H pass reads E, H and writes H (+ the H-type psi)."""
     ncell = w.nx * w.ny * w.nz
     n = (w.nx, w.ny, w.nz)
     slab = 0
     for a in range(3):
         thick = w.npml[2 * a] * (w.bc[2 * a] == 1) + w.npml[2 * a + 1] * (w.bc[2 * a + 1] == 1)
         slab += thick * ncell // n[a]
-    e_pass = ncell * (9 * esz + 1) + slab * 2 * 2 * esz
-    h_pass = ncell * 9 * esz + slab * 2 * 2 * esz
-    return {"e_pass": e_pass, "h_pass": h_pass, "ncell": ncell, "slab_cells": slab}
+    return {"fused": ncell * (12 * esz + 1) + slab * 8 * esz,
+            "e_pass": ncell * (9 * esz + 1) + slab * 4 * esz,
+            "h_pass": ncell * 9 * esz + slab * 4 * esz,
+            "ncell": ncell, "slab_cells": slab}
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "mpx_internal.h"):
+    for f in ("kernels.hip", "fused.hip", "device_common.h", "mpx_internal.h"):
         with open(os.path.join(ROOT, "paper_2510_22221_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,13 +74,13 @@ def traffic_from_profiles(kernel, dtype):
     return None
 
 
-def run_gpu(w, precision, steps, warmup, every):
+def run_gpu(w, precision, steps, warmup, every, fused=True):
     import torch
     from paper_2510_22221_amd import mpx
 
     stream = torch.cuda.current_stream()
     t0 = time.time()
-    sim = mpx.from_workload(w, precision=precision, stream=stream)
+    sim = mpx.from_workload(w, precision=precision, stream=stream, fused=fused)
     sim.step(1)
     sim.sync()
     log(f"  setup {time.time() - t0:.1f} s")
@@ -98,21 +100,24 @@ def run_gpu(w, precision, steps, warmup, every):
     return sim, wall, kt
 
 
-def roofline_for(w, esz, kt, dtype_name):
+def roofline_for(w, esz, kt, dtype_name, fused=True):
     ab = algorithmic_bytes(w, esz)
-    names = ["e_pass", "h_pass"]
-    # dominant = the kernel with the larger total time
-    q = max(range(2), key=lambda i: kt[i][0])
-    ms = kt[q][0]
-    achieved = ab[names[q]] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    traffic = traffic_from_profiles(names[q], dtype_name)
-    return {"bound": "hbm", "kernel": names[q], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": ab[names[q]], "avg_launch_ms": round(ms, 5),
-            "launches_timed": kt[q][1],
-            "other_kernel": {"kernel": names[1 - q], "avg_launch_ms": round(kt[1 - q][0], 5),
-                             "achieved": round(ab[names[1 - q]] / (kt[1 - q][0] * 1e-3) / 1e9, 1)
-                             if kt[1 - q][0] > 0 else 0.0}}
+    if fused:
+        name, ms, nl = "fused", kt[0][0], kt[0][1]
+    else:
+        # the dominant of the two stencil kernels
+        q = 0 if kt[0][0] >= kt[1][0] else 1
+        name, ms, nl = ("e_pass", "h_pass")[q], kt[q][0], kt[q][1]
+    achieved = ab[name] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": traffic_from_profiles(name, dtype_name),
+           "algorithmic_bytes_per_launch": ab[name], "avg_launch_ms": round(ms, 5), "launches_timed": nl,
+           "film_and_probe_kernels_ms_per_step": round(kt[2][0], 5)}
+    if not fused:
+        out["other_stencil_kernel"] = {"kernel": ("h_pass", "e_pass")[0 if name == "e_pass" else 1],
+                                       "avg_launch_ms": round(kt[1 if name == "e_pass" else 0][0], 5)}
+    return out
 
 
 def cpu_baseline(w, nsteps):
@@ -145,6 +150,7 @@ def main():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
+    ap.add_argument("--two-pass", action="store_true", help="separate E and H passes instead of the fused pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
@@ -156,10 +162,11 @@ def main():
     w = W.c2(max(args.steps, args.f64_steps) + args.warmup + 2, nx=args.nx, ny=args.ny, nz=args.nz)
     every = args.timing_every or max(1, args.steps // 2000)
     log(f"workload {w.name}: {w.ncells} cells, FP32 {args.steps} steps (+{args.warmup} warmup)")
-    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every)
+    fused = not args.two_pass
+    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every, fused)
     del sim
     value = w.ncells * args.steps / wall / 1e9
-    roof = roofline_for(w, 4, kt, "f32")
+    roof = roofline_for(w, 4, kt, "f32", fused)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -176,17 +183,18 @@ def main():
         "config": {"workload": f"single on-chip CPW resonator + film, {w.nx}x{w.ny}x{w.nz} cells, "
                                f"d=(45,2,2) um, PML 10, source + probes, one time step per bench step",
                    "cells": w.ncells, "precision": "f32 fields, f64 magnetisation",
+                   "schedule": "fused E + merged H/M pass" if fused else "separate E and H passes",
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
     if not args.no_f64:
         log(f"FP64 {args.f64_steps} steps")
-        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000))
+        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000), fused)
         del sim
         out["secondary"] = [{"dtype": "f64", "value": round(w.ncells * args.f64_steps / wall64 / 1e9, 3),
                              "unit": "Gcell-updates/s", "steps": args.f64_steps,
                              "ms_per_step": round(wall64 / args.f64_steps * 1e3, 5),
-                             "roofline": roofline_for(w, 8, kt64, "f64")}]
+                             "roofline": roofline_for(w, 8, kt64, "f64", fused)}]
     if not args.no_cpu:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

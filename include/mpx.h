@@ -131,8 +131,8 @@ uint32_t mpx_abi_version(void);
  * case the library creates and owns a non-blocking stream at default
  * priority.  All device work of the handle is ordered on that stream.
  * Errors: MPX_E_INVALID for non-positive sizes or spacings, courant outside
- * (0, 1] when dt <= 0, a one-sided periodic axis, PML thicker than a third of
- * the axis; MPX_E_DEVICE / MPX_E_NOMEM from HIP. */
+ * (0, 1] when dt <= 0, a one-sided periodic axis, PML slabs that leave no
+ * interior cell on an axis; MPX_E_DEVICE / MPX_E_NOMEM from HIP. */
 mpx_status mpx_create(const mpx_grid_desc *grid, mpx_precision precision, int32_t hip_device,
                       void *hip_stream, mpx_sim **out);
 
@@ -182,6 +182,14 @@ mpx_status mpx_synchronize(mpx_sim *sim);
  * size. */
 mpx_status mpx_read_field(mpx_sim *sim, int32_t field, void *dst, int64_t dst_bytes, int32_t dst_is_device);
 
+/* Copy the sub-box box = (i0,j0,k0,ni,nj,nk) of a field (natural index
+ * space of that field) out, x fastest, ni*nj*nk elements per component (the M
+ * fields: 3 components, component-major).  Synchronises.  MPX_E_INVALID if
+ * the box leaves the field's natural dims, MPX_E_RANGE if dst_bytes is too
+ * small. */
+mpx_status mpx_read_field_region(mpx_sim *sim, int32_t field, const int32_t box[6], void *dst, int64_t dst_bytes,
+                                 int32_t dst_is_device);
+
 /* Overwrite a field (natural dims, the element type of mpx_query_field).
  * E values on PEC edges and on the faces of non-periodic walls are held at
  * zero; H values on the upper wall faces are not stored; M values are kept
@@ -209,12 +217,23 @@ mpx_status mpx_film_box(const mpx_sim *sim, int32_t film, int32_t box[6], int64_
  * kernel directly). */
 mpx_status mpx_set_graph_steps(mpx_sim *sim, int32_t steps);
 
+/* Step schedule.  fused = 1..4 (default 1): one fused stencil pass per step
+ * (E step and the merged H/M half-step pair in one z-marching sweep over
+ * ping-pong buffers, z-chunks of `kchunk` planes; 0 keeps the current chunk,
+ * default 16); the value picks a tile variant (1: two rows per thread,
+ * >= 2 waves per SIMD; 2: two rows, >= 4 waves; 3: one row, >= 2 waves;
+ * 4: one row, >= 4 waves).  fused = 0: a separate E pass and H pass, in
+ * place.  All give identical results. */
+mpx_status mpx_set_schedule(mpx_sim *sim, int32_t fused, int32_t kchunk);
+
 /* Kernel timing with HIP events on the handle's stream.  With every > 0,
- * mpx_step launches each step's kernels directly (no graph) and brackets the
- * E pass and the merged H pass of every `every`-th step with events; 0 turns
- * timing off.  mpx_kernel_time returns, for the last mpx_step call, the
- * average device time per timed launch (ms) and the number of launches
- * timed: index 0 = E pass, 1 = merged H pass (arrays of 2). */
+ * mpx_step launches each step's kernels directly (no graph) and brackets
+ * three groups of every `every`-th step with events; 0 turns timing off.
+ * mpx_kernel_time fills avg_ms[3] (average device time per timed launch,
+ * ms) and launches[3] for the last mpx_step call: 0 = the main stencil
+ * kernel (fused pass, or the E pass of the two-pass schedule), 1 = the H pass
+ * of the two-pass schedule (0 launches when fused), 2 = the film half steps
+ * and probes of a step together. */
 mpx_status mpx_set_timing(mpx_sim *sim, int32_t every);
 mpx_status mpx_kernel_time(mpx_sim *sim, double *avg_ms, int64_t *launches);
 

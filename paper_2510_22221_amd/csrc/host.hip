@@ -26,8 +26,10 @@ struct FilmHost {
     long long ns;
     long long ncells;
     long long lowest;
-    double *M = nullptr, *M1 = nullptr, *H1 = nullptr;
+    double *M = nullptr, *M1 = nullptr, *H1 = nullptr, *prm = nullptr, *Bn = nullptr, *Bs = nullptr;
     int blk0[3], nblk[3];
+    int e0[3], en[3];
+    long long nse;
 };
 
 struct SrcHost {
@@ -54,8 +56,16 @@ struct mpx_sim {
     double d[3] = {0, 0, 0};
     double dt = 0;
     size_t esz = 8;
+    // field buffers: set 0 and its ping-pong partner set 1 (the fused pass
+    // reads one set and writes the other); `parity` selects the current one
     void *E[3] = {nullptr, nullptr, nullptr};
     void *H[3] = {nullptr, nullptr, nullptr};
+    void *E2[3] = {nullptr, nullptr, nullptr};
+    void *H2[3] = {nullptr, nullptr, nullptr};
+    int parity = 0;
+    int fused = 1;
+    int kchunk = 16;
+    void *d_coef = nullptr;
     // materials
     bool have_mat = false;
     std::vector<mpx_material> mats;
@@ -65,14 +75,16 @@ struct mpx_sim {
     // PML
     int nlo[3] = {0, 0, 0}, nhi[3] = {0, 0, 0};
     void *bE[3] = {}, *cE[3] = {}, *bH[3] = {}, *cH[3] = {};
-    void *psiE[3][3] = {}, *psiH[3][3] = {};
+    void *psiE[3][3] = {}, *psiH[3][3] = {}, *psiE2[3][3] = {};
     bool any_pml = false;
     // films
     std::vector<FilmHost> films;
     FilmDev *d_films = nullptr;
     int4 *d_blocktab = nullptr;
+    int4 *d_blocktab_ext = nullptr;
     double *d_partial = nullptr;
     int nblk = 0;
+    int nblk_ext = 0;
     double H0[3] = {0, 0, 0};
     double u[3] = {0, 0, 1};
     bool have_u = false;
@@ -83,17 +95,17 @@ struct mpx_sim {
     long long *d_step = nullptr;
     int *d_flag = nullptr;
     long long step = 0;
-    // graph
+    // graphs of step batches, one per starting parity
     int graph_steps = 64;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    bool graph_valid = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    bool graph_valid[2] = {false, false};
     // timing
     int timing_every = 0;
     std::vector<hipEvent_t> ev;
     size_t evi = 0;
-    double t_ms[2] = {0, 0};
-    long long t_n[2] = {0, 0};
+    double t_ms[3] = {0, 0, 0};
+    long long t_n[3] = {0, 0, 0};
     // errors
     bool dead = false;
     std::string err;
@@ -183,9 +195,17 @@ bool edge_is_pec_h(const mpx_sim *s, int c, const int *idx) {
 
 bool in_pml_cell(const mpx_sim *s, int a, int i) { return i < s->nlo[a] || i >= s->n[a] - s->nhi[a]; }
 
+// buffer sets by parity
+void *const *Eset(const mpx_sim *s, int par) { return par ? s->E2 : s->E; }
+void *const *Hset(const mpx_sim *s, int par) { return par ? s->H2 : s->H; }
+void *psiEset(const mpx_sim *s, int par, int c, int w) { return par ? s->psiE2[c][w] : s->psiE[c][w]; }
+
+enum ParamMode { MODE_INPLACE = 0, MODE_FUSED = 1, MODE_AFTER_FUSED = 2 };
+
 template <typename T>
-void fill_params(const mpx_sim *s, KParams<T> &p) {
+void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int par = -1) {
     memset(&p, 0, sizeof(p));
+    if (par < 0) par = s->parity;
     for (int a = 0; a < 3; a++) {
         p.n[a] = s->n[a];
         p.per[a] = s->per[a];
@@ -198,11 +218,16 @@ void fill_params(const mpx_sim *s, KParams<T> &p) {
         p.cE[a] = (const T *)s->cE[a];
         p.bH[a] = (const T *)s->bH[a];
         p.cH[a] = (const T *)s->cH[a];
-        p.E[a] = (T *)s->E[a];
-        p.H[a] = (T *)s->H[a];
+        const int nx = par ^ 1;
+        p.E[a] = (T *)Eset(s, mode == MODE_AFTER_FUSED ? nx : par)[a];
+        p.H[a] = (T *)Hset(s, par)[a];
+        p.Hw[a] = (T *)Hset(s, mode == MODE_AFTER_FUSED ? nx : par)[a];
+        p.Eb[a] = (T *)Eset(s, nx)[a];
+        p.Hb[a] = (T *)Hset(s, nx)[a];
         p.H0[a] = s->H0[a];
         for (int w = 0; w < 3; w++) {
-            p.psiE[a][w] = (T *)s->psiE[a][w];
+            p.psiE[a][w] = (T *)psiEset(s, par, a, w);
+            p.psiEb[a][w] = (T *)psiEset(s, nx, a, w);
             p.psiH[a][w] = (T *)s->psiH[a][w];
         }
     }
@@ -217,9 +242,12 @@ void fill_params(const mpx_sim *s, KParams<T> &p) {
     p.dV = s->d[0] * s->d[1] * s->d[2];
     p.id = s->d_id;
     p.mat = s->d_mat;
+    p.coef = (const CoefDev<T> *)s->d_coef;
     p.nfilm = (int)s->films.size();
     p.films = s->d_films;
     p.blocktab = s->d_blocktab;
+    p.blocktab_ext = s->d_blocktab_ext;
+    p.nblk_ext = s->nblk_ext;
     p.partial = s->d_partial;
     p.nsrc = (int)s->srcs.size();
     for (int i = 0; i < p.nsrc; i++) p.src[i] = s->srcs[i].dev;
@@ -233,23 +261,31 @@ void free_films(mpx_sim *s) {
         (void)hipFree(f.M);
         (void)hipFree(f.M1);
         (void)hipFree(f.H1);
+        (void)hipFree(f.prm);
+        (void)hipFree(f.Bn);
+        (void)hipFree(f.Bs);
     }
     s->films.clear();
     (void)hipFree(s->d_films);
     (void)hipFree(s->d_blocktab);
+    (void)hipFree(s->d_blocktab_ext);
     (void)hipFree(s->d_partial);
     s->d_films = nullptr;
     s->d_blocktab = nullptr;
+    s->d_blocktab_ext = nullptr;
     s->d_partial = nullptr;
     s->nblk = 0;
+    s->nblk_ext = 0;
 }
 
 void drop_graph(mpx_sim *s) {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->gexec = nullptr;
-    s->graph = nullptr;
-    s->graph_valid = false;
+    for (int q = 0; q < 2; q++) {
+        if (s->gexec[q]) (void)hipGraphExecDestroy(s->gexec[q]);
+        if (s->graph[q]) (void)hipGraphDestroy(s->graph[q]);
+        s->gexec[q] = nullptr;
+        s->graph[q] = nullptr;
+        s->graph_valid[q] = false;
+    }
 }
 
 // connected components of magnetic cells -> bounding boxes; boxes closer than
@@ -374,105 +410,158 @@ mpx_status upload_profiles(mpx_sim *s) {
         for (int c = 0; c < 3; c++) {
             if (c == a) continue;
             CK(hipMalloc(&s->psiE[c][a], cnt * sizeof(T)));
+            CK(hipMalloc(&s->psiE2[c][a], cnt * sizeof(T)));
             CK(hipMalloc(&s->psiH[c][a], cnt * sizeof(T)));
             CK(hipMemset(s->psiE[c][a], 0, cnt * sizeof(T)));
+            CK(hipMemset(s->psiE2[c][a], 0, cnt * sizeof(T)));
             CK(hipMemset(s->psiH[c][a], 0, cnt * sizeof(T)));
         }
     }
     return MPX_OK;
 }
 
+// One step of the body (not the last): the fused pass or the two separate
+// stencil passes, then the film half steps and the probes.  `par` is the
+// current buffer parity; the fused schedule flips it.
 template <typename T>
-mpx_status enqueue_steps(mpx_sim *s, long long nsteps);
-
-template <typename T>
-mpx_status run_body(mpx_sim *s, const KParams<T> &p, bool last, bool timed) {
+mpx_status run_body(mpx_sim *s, int &par, bool timed) {
     const int nblk = s->nblk;
     const int np = (int)s->probes.size();
     hipStream_t st = s->stream;
-    // event pool: four events per timed step (E pass start/end, H pass start/end)
-    auto rec = [&]() -> mpx_status {
-        if (s->evi >= s->ev.size()) {
+    // six events per timed step: group g (0 = main stencil kernel, 1 = second
+    // stencil kernel of the two-pass schedule, 2 = film and probe kernels)
+    // brackets with slots base + 2g and base + 2g + 1
+    size_t base = s->evi;
+    if (timed) {
+        while (s->ev.size() < base + 6) {
             hipEvent_t e;
             CK(hipEventCreate(&e));
             s->ev.push_back(e);
         }
-        CK(hipEventRecord(s->ev[s->evi++], st));
+        s->evi += 6;
+    }
+    auto rec = [&](int g, int end) -> mpx_status {
+        if (timed) CK(hipEventRecord(s->ev[base + 2 * g + end], st));
         return MPX_OK;
     };
     mpx_status r;
-    if (timed && (r = rec()) != MPX_OK) return r;
+    if (s->fused) {
+        KParams<T> pa, pb;
+        fill_params<T>(s, pa, MODE_FUSED, par);
+        fill_params<T>(s, pb, MODE_AFTER_FUSED, par);
+        if ((r = rec(0, 0)) != MPX_OK) return r;
+        CK(launch_fused<T>(pa, s->kchunk, s->fused, st));
+        if ((r = rec(0, 1)) != MPX_OK) return r;
+        if ((r = rec(1, 0)) != MPX_OK) return r; // no second stencil kernel
+        if ((r = rec(1, 1)) != MPX_OK) return r;
+        if ((r = rec(2, 0)) != MPX_OK) return r;
+        CK(launch_film<T>(pb, nblk, 1, 0, st));
+        CK(launch_probes<T>(pb, np, st));
+        if (nblk)
+            CK(launch_film<T>(pb, nblk, 2, 1, st));
+        else
+            CK(launch_tick(s->d_step, st));
+        if ((r = rec(2, 1)) != MPX_OK) return r;
+        par ^= 1;
+        return MPX_OK;
+    }
+    // two-pass schedule, in place: E pass, film half steps and probes, then
+    // the bulk H pass (the film kernels read H before the bulk pass moves it)
+    KParams<T> p;
+    fill_params<T>(s, p, MODE_INPLACE, par);
+    if ((r = rec(0, 0)) != MPX_OK) return r;
     CK(launch_epass<T>(p, st));
-    if (timed && (r = rec()) != MPX_OK) return r;
-    CK(launch_film<T>(p, nblk, 1, st));
+    if ((r = rec(0, 1)) != MPX_OK) return r;
+    if ((r = rec(2, 0)) != MPX_OK) return r;
+    CK(launch_film<T>(p, nblk, 1, 0, st));
     CK(launch_probes<T>(p, np, st));
-    if (last)
-        CK(launch_commit<T>(p, nblk, st));
-    else
-        CK(launch_film<T>(p, nblk, 2, st));
-    if (timed && (r = rec()) != MPX_OK) return r;
-    CK(launch_hbulk<T>(p, last ? 1 : 2, 1, st));
-    if (timed && (r = rec()) != MPX_OK) return r;
+    CK(launch_film<T>(p, nblk, 2, 0, st));
+    if ((r = rec(2, 1)) != MPX_OK) return r;
+    if ((r = rec(1, 0)) != MPX_OK) return r;
+    CK(launch_hbulk<T>(p, 2, 1, st));
+    if ((r = rec(1, 1)) != MPX_OK) return r;
+    return MPX_OK;
+}
+
+// the last step of a call: E pass, first H/M half step (probes), commit
+template <typename T>
+mpx_status run_last(mpx_sim *s, int par) {
+    KParams<T> p;
+    fill_params<T>(s, p, MODE_INPLACE, par);
+    hipStream_t st = s->stream;
+    CK(launch_epass<T>(p, st));
+    CK(launch_film<T>(p, s->nblk, 1, 0, st));
+    CK(launch_probes<T>(p, (int)s->probes.size(), st));
+    CK(launch_commit<T>(p, s->nblk, st));
+    CK(launch_hbulk<T>(p, 1, 1, st));
     return MPX_OK;
 }
 
 template <typename T>
 mpx_status enqueue_steps(mpx_sim *s, long long nsteps) {
-    KParams<T> p;
-    fill_params<T>(s, p);
     hipStream_t st = s->stream;
     const int nblk = s->nblk;
-    // bracket: first H/M half step with E^n
-    CK(launch_film<T>(p, nblk, 1, st));
-    CK(launch_commit<T>(p, nblk, st));
-    CK(launch_hbulk<T>(p, 1, 0, st));
+    {
+        // bracket: first H/M half step with E^n, in place
+        KParams<T> p;
+        fill_params<T>(s, p, MODE_INPLACE, s->parity);
+        CK(launch_film<T>(p, nblk, 1, 0, st));
+        CK(launch_commit<T>(p, nblk, st));
+        CK(launch_hbulk<T>(p, 1, 0, st));
+    }
     long long body = nsteps - 1;
     mpx_status r;
+    int par = s->parity;
     if (s->timing_every > 0) {
-        // direct launches; every timing_every-th step bracketed by events
         s->evi = 0;
         for (long long n = 0; n < body; n++)
-            if ((r = run_body<T>(s, p, false, n % s->timing_every == 0)) != MPX_OK) return r;
-        if ((r = run_body<T>(s, p, true, body % s->timing_every == 0)) != MPX_OK) return r;
+            if ((r = run_body<T>(s, par, n % s->timing_every == 0)) != MPX_OK) return r;
+        if ((r = run_last<T>(s, par)) != MPX_OK) return r;
+        s->parity = par;
         CK(hipStreamSynchronize(st));
-        s->t_ms[0] = s->t_ms[1] = 0;
-        s->t_n[0] = s->t_n[1] = 0;
-        for (size_t q = 0; q + 3 < s->evi; q += 4) {
-            float a = 0, b = 0;
-            CK(hipEventElapsedTime(&a, s->ev[q], s->ev[q + 1]));
-            CK(hipEventElapsedTime(&b, s->ev[q + 2], s->ev[q + 3]));
-            s->t_ms[0] += a;
-            s->t_ms[1] += b;
-            s->t_n[0]++;
-            s->t_n[1]++;
+        for (int g = 0; g < 3; g++) {
+            s->t_ms[g] = 0;
+            s->t_n[g] = 0;
         }
+        for (size_t q = 0; q + 5 < s->evi; q += 6)
+            for (int g = 0; g < 3; g++) {
+                float a = 0;
+                CK(hipEventElapsedTime(&a, s->ev[q + 2 * g], s->ev[q + 2 * g + 1]));
+                s->t_ms[g] += a;
+                s->t_n[g]++;
+            }
+        if (s->fused) s->t_n[1] = 0;
         return MPX_OK;
     }
-    const int G = s->graph_steps;
+    // HIP graph of G body steps (G even, so the buffer parity is unchanged
+    // after a replay); one graph per starting parity
+    const int G = (s->graph_steps + 1) / 2 * 2;
     if (G > 0 && body >= G) {
-        if (!s->graph_valid) {
-            drop_graph(s);
+        if (!s->graph_valid[par]) {
             CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int cp = par;
             for (int n = 0; n < G; n++) {
-                r = run_body<T>(s, p, false, false);
+                r = run_body<T>(s, cp, false);
                 if (r != MPX_OK) {
                     hipGraph_t g;
                     (void)hipStreamEndCapture(st, &g);
                     return r;
                 }
             }
-            CK(hipStreamEndCapture(st, &s->graph));
-            CK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
-            s->graph_valid = true;
+            CK(hipStreamEndCapture(st, &s->graph[par]));
+            CK(hipGraphInstantiate(&s->gexec[par], s->graph[par], nullptr, nullptr, 0));
+            s->graph_valid[par] = true;
         }
         while (body >= G) {
-            CK(hipGraphLaunch(s->gexec, st));
+            CK(hipGraphLaunch(s->gexec[par], st));
             body -= G;
         }
     }
     for (long long n = 0; n < body; n++)
-        if ((r = run_body<T>(s, p, false, false)) != MPX_OK) return r;
-    return run_body<T>(s, p, true, false);
+        if ((r = run_body<T>(s, par, false)) != MPX_OK) return r;
+    r = run_last<T>(s, par);
+    s->parity = par;
+    return r;
 }
 
 mpx_status check_live(mpx_sim *s) {
@@ -517,7 +606,7 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
         const int plo = lo == MPX_BC_PML ? g->pml_cells[2 * a] : 0;
         const int phi = hi == MPX_BC_PML ? g->pml_cells[2 * a + 1] : 0;
         if (plo < 0 || phi < 0 || (lo == MPX_BC_PML && plo < 1) || (hi == MPX_BC_PML && phi < 1)) return MPX_E_INVALID;
-        if (3 * (plo + phi) > nn[a]) return MPX_E_INVALID;
+        if (plo + phi >= nn[a]) return MPX_E_INVALID;
     }
     double dt = g->dt;
     if (!(dt > 0)) {
@@ -559,9 +648,14 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
         for (int c = 0; c < 3; c++) {
             CK(hipMalloc(&s->E[c], s->nslot * s->esz));
             CK(hipMalloc(&s->H[c], s->nslot * s->esz));
+            CK(hipMalloc(&s->E2[c], s->nslot * s->esz));
+            CK(hipMalloc(&s->H2[c], s->nslot * s->esz));
             CK(hipMemset(s->E[c], 0, s->nslot * s->esz));
             CK(hipMemset(s->H[c], 0, s->nslot * s->esz));
+            CK(hipMemset(s->E2[c], 0, s->nslot * s->esz));
+            CK(hipMemset(s->H2[c], 0, s->nslot * s->esz));
         }
+        CK(hipMalloc(&s->d_coef, 256 * (prec == MPX_F64 ? sizeof(CoefDev<double>) : sizeof(CoefDev<float>))));
         CK(hipMalloc(&s->d_id, s->nslot));
         CK(hipMemset(s->d_id, 0, s->nslot));
         CK(hipMalloc(&s->d_mat, 256 * sizeof(MatDev)));
@@ -587,15 +681,19 @@ mpx_status mpx_destroy(mpx_sim *s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     drop_graph(s);
     for (auto e : s->ev) (void)hipEventDestroy(e);
+    (void)hipFree(s->d_coef);
     for (int c = 0; c < 3; c++) {
         (void)hipFree(s->E[c]);
         (void)hipFree(s->H[c]);
+        (void)hipFree(s->E2[c]);
+        (void)hipFree(s->H2[c]);
         (void)hipFree(s->bE[c]);
         (void)hipFree(s->cE[c]);
         (void)hipFree(s->bH[c]);
         (void)hipFree(s->cH[c]);
         for (int w = 0; w < 3; w++) {
             (void)hipFree(s->psiE[c][w]);
+            (void)hipFree(s->psiE2[c][w]);
             (void)hipFree(s->psiH[c][w]);
         }
     }
@@ -679,13 +777,41 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         md[q].is_pec = mats[q].is_pec ? 1 : 0;
     }
     CK(hipMemcpy(s->d_mat, md.data(), 256 * sizeof(MatDev), hipMemcpyHostToDevice));
+    // coefficients of edges whose four cells share one id: the same sequence
+    // of operations as for any edge (sum of four in order, mean, ca, cb)
+    {
+        std::vector<CoefDev<double>> cd(256);
+        std::vector<CoefDev<float>> cf(256);
+        memset(cd.data(), 0, cd.size() * sizeof(cd[0]));
+        memset(cf.data(), 0, cf.size() * sizeof(cf[0]));
+        for (int q = 0; q < n; q++) {
+            double se = 0.0, ss = 0.0;
+            for (int r4 = 0; r4 < 4; r4++) {
+                se += mats[q].eps_r;
+                ss += mats[q].sigma;
+            }
+            const double eps = EPS0 * (se / 4);
+            const double sig = ss / 4;
+            const double den = sig / 2.0 + eps / s->dt;
+            cd[q].ca = -(sig / 2.0 - eps / s->dt) / den;
+            cd[q].cb = 1.0 / den;
+            cd[q].pec = mats[q].is_pec ? 1 : 0;
+            cf[q].ca = (float)cd[q].ca;
+            cf[q].cb = (float)cd[q].cb;
+            cf[q].pec = cd[q].pec;
+        }
+        if (s->prec == MPX_F64)
+            CK(hipMemcpy(s->d_coef, cd.data(), 256 * sizeof(cd[0]), hipMemcpyHostToDevice));
+        else
+            CK(hipMemcpy(s->d_coef, cf.data(), 256 * sizeof(cf[0]), hipMemcpyHostToDevice));
+    }
     std::vector<uint8_t> slots(s->nslot, 0);
     for (int k = 0; k < s->n[2]; k++)
         for (int j = 0; j < s->n[1]; j++)
             memcpy(&slots[(size_t)s->px * (j + (size_t)s->n[1] * k)], &ids[(size_t)s->n[0] * (j + (size_t)s->n[1] * k)],
                    s->n[0]);
     CK(hipMemcpy(s->d_id, slots.data(), s->nslot, hipMemcpyHostToDevice));
-    std::vector<int4> bt;
+    std::vector<int4> bt, bte;
     std::vector<FilmDev> fd;
     for (int fi = 0; fi < (int)s->films.size(); fi++) {
         FilmHost &f = s->films[fi];
@@ -695,12 +821,41 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         CK(hipMemset(f.M, 0, 9 * f.ns * sizeof(double)));
         CK(hipMemset(f.M1, 0, 9 * f.ns * sizeof(double)));
         CK(hipMemset(f.H1, 0, 3 * f.ns * sizeof(double)));
+        {
+            // per-face Ms, alpha, |gamma| (the same means the kernels would form)
+            std::vector<double> prm(9 * f.ns);
+            for (int c = 0; c < 3; c++)
+                for (long long l = 0; l < f.ns; l++) {
+                    const int idx[3] = {f.b0[0] + (int)(l % f.bn[0]), f.b0[1] + (int)((l / f.bn[0]) % f.bn[1]),
+                                        f.b0[2] + (int)(l / ((long long)f.bn[0] * f.bn[1]))};
+                    double ms, al, ga;
+                    site_params_h(s, c, idx, ms, al, ga);
+                    prm[(c * 3 + 0) * f.ns + l] = ms;
+                    prm[(c * 3 + 1) * f.ns + l] = al;
+                    prm[(c * 3 + 2) * f.ns + l] = ga;
+                }
+            CK(hipMalloc(&f.prm, prm.size() * sizeof(double)));
+            CK(hipMemcpy(f.prm, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
         for (int c = 0; c < 3; c++) {
             f.blk0[c] = (int)bt.size();
             const long long tiles = (f.ns + 255) / 256;
             f.nblk[c] = (int)tiles;
             for (long long t = 0; t < tiles; t++) bt.push_back(make_int4(fi, c, (int)(t * 256), 0));
         }
+        // face box grown by one layer on the low side of each non-spanned axis
+        for (int a = 0; a < 3; a++) {
+            const bool span = s->per[a] && f.bn[a] == s->n[a];
+            f.e0[a] = span ? 0 : f.b0[a] - 1;
+            f.en[a] = span ? s->n[a] : f.bn[a] + 1;
+        }
+        f.nse = (long long)f.en[0] * f.en[1] * f.en[2];
+        CK(hipMalloc(&f.Bn, 3 * f.nse * sizeof(double)));
+        CK(hipMalloc(&f.Bs, 3 * f.nse * sizeof(double)));
+        CK(hipMemset(f.Bn, 0, 3 * f.nse * sizeof(double)));
+        CK(hipMemset(f.Bs, 0, 3 * f.nse * sizeof(double)));
+        for (int c = 0; c < 3; c++)
+            for (long long t = 0; t < (f.nse + 255) / 256; t++) bte.push_back(make_int4(fi, c, (int)(t * 256), 0));
         FilmDev d{};
         for (int a = 0; a < 3; a++) {
             d.b0[a] = f.b0[a];
@@ -714,6 +869,14 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         d.M = f.M;
         d.M1 = f.M1;
         d.H1 = f.H1;
+        d.prm = f.prm;
+        for (int a = 0; a < 3; a++) {
+            d.e0[a] = f.e0[a];
+            d.en[a] = f.en[a];
+        }
+        d.nse = f.nse;
+        d.Bn = f.Bn;
+        d.Bs = f.Bs;
         fd.push_back(d);
     }
     s->nblk = (int)bt.size();
@@ -722,6 +885,9 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         CK(hipMemcpy(s->d_films, fd.data(), fd.size() * sizeof(FilmDev), hipMemcpyHostToDevice));
         CK(hipMalloc(&s->d_blocktab, bt.size() * sizeof(int4)));
         CK(hipMemcpy(s->d_blocktab, bt.data(), bt.size() * sizeof(int4), hipMemcpyHostToDevice));
+        CK(hipMalloc(&s->d_blocktab_ext, bte.size() * sizeof(int4)));
+        CK(hipMemcpy(s->d_blocktab_ext, bte.data(), bte.size() * sizeof(int4), hipMemcpyHostToDevice));
+        s->nblk_ext = (int)bte.size();
         CK(hipMalloc(&s->d_partial, bt.size() * sizeof(double)));
         CK(hipMemset(s->d_partial, 0, bt.size() * sizeof(double)));
     }
@@ -862,7 +1028,7 @@ mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_byte
     std::vector<char> host(bytes, 0);
     if (field < 6) {
         std::vector<char> slots(s->nslot * s->esz);
-        void *src = field < 3 ? s->E[field] : s->H[field - 3];
+        void *src = field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3];
         CK(hipMemcpy(slots.data(), src, slots.size(), hipMemcpyDeviceToHost));
         for (int64_t k = 0; k < dims[2]; k++)
             for (int64_t j = 0; j < dims[1]; j++) {
@@ -901,6 +1067,77 @@ mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_byte
     return MPX_OK;
 }
 
+mpx_status mpx_read_field_region(mpx_sim *s, int32_t field, const int32_t box[6], void *dst, int64_t dst_bytes,
+                                 int32_t dst_is_device) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    int64_t dims[4], bytes;
+    if (field < 0 || field > 11 || !dst || !box) return fail(s, MPX_E_INVALID, "bad field");
+    mpx_query_field(s, field, dims, &bytes);
+    for (int a = 0; a < 3; a++)
+        if (box[a] < 0 || box[3 + a] < 0 || box[a] + box[3 + a] > dims[a]) return fail(s, MPX_E_INVALID, "bad box");
+    const int64_t nr = (int64_t)box[3] * box[4] * box[5];
+    const size_t esz = field < 6 ? s->esz : 8;
+    const int64_t need = nr * dims[3] * (int64_t)esz;
+    if (dst_bytes < need) return fail(s, MPX_E_RANGE, "destination too small");
+    CK(hipStreamSynchronize(s->stream));
+    std::vector<char> host(need, 0);
+    if (field < 6) {
+        void *src = field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3];
+        const int ni = box[3];
+        std::vector<char> row((size_t)ni * esz);
+        for (int k = 0; k < box[5]; k++)
+            for (int j = 0; j < box[4]; j++) {
+                const int gj = box[1] + j, gk = box[2] + k;
+                if (gj >= s->n[1] || gk >= s->n[2] || ni == 0) continue;
+                // contiguous run of the row inside the stored lattice
+                const int gi0 = box[0];
+                const int cnt = std::max(0, std::min(ni, s->n[0] - gi0));
+                if (cnt == 0) continue;
+                const size_t off = ((size_t)gi0 + (size_t)s->px * ((size_t)gj + (size_t)s->n[1] * gk)) * esz;
+                CK(hipMemcpy(&host[((size_t)j + (size_t)box[4] * k) * ni * esz], (const char *)src + off,
+                             (size_t)cnt * esz, hipMemcpyDeviceToHost));
+            }
+    } else {
+        const int c = (field - 6) % 3;
+        const bool delta = field >= 9;
+        double *h = (double *)host.data();
+        for (auto &f : s->films) {
+            // intersect the film's face box with the region
+            int lo[3], hi[3];
+            bool empty = false;
+            for (int a = 0; a < 3; a++) {
+                lo[a] = std::max(f.b0[a], box[a]);
+                hi[a] = std::min(f.b0[a] + f.bn[a], box[a] + box[3 + a]);
+                if (hi[a] <= lo[a]) empty = true;
+            }
+            if (empty) continue;
+            std::vector<double> m(9 * f.ns);
+            CK(hipMemcpy(m.data(), f.M, m.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (int k = lo[2]; k < hi[2]; k++)
+                for (int j = lo[1]; j < hi[1]; j++)
+                    for (int i = lo[0]; i < hi[0]; i++) {
+                        const int idx[3] = {i, j, k};
+                        double ms, al, ga;
+                        site_params_h(s, c, idx, ms, al, ga);
+                        if (!(ms > 0)) continue;
+                        const long long l = (i - f.b0[0]) + (long long)f.bn[0] * ((j - f.b0[1]) + (long long)f.bn[1] * (k - f.b0[2]));
+                        const int64_t q = (i - box[0]) + (int64_t)box[3] * ((j - box[1]) + (int64_t)box[4] * (k - box[2]));
+                        for (int w = 0; w < 3; w++) {
+                            double v = m[(c * 3 + w) * f.ns + l];
+                            if (delta) v -= (s->have_u ? ms * s->u[w] : 0.0);
+                            h[w * nr + q] = v;
+                        }
+                    }
+        }
+    }
+    if (dst_is_device)
+        CK(hipMemcpy(dst, host.data(), need, hipMemcpyHostToDevice));
+    else
+        memcpy(dst, host.data(), need);
+    return MPX_OK;
+}
+
 mpx_status mpx_write_field(mpx_sim *s, int32_t field, const void *src, int64_t src_bytes, int32_t src_is_device) {
     mpx_status r = check_live(s);
     if (r != MPX_OK) return r;
@@ -925,7 +1162,7 @@ mpx_status mpx_write_field(mpx_sim *s, int32_t field, const void *src, int64_t s
                     memcpy(&slots[(size_t)(i + s->px * (j + (int64_t)s->n[1] * k)) * s->esz],
                            &host[(size_t)(i + dims[0] * (j + dims[1] * k)) * s->esz], s->esz);
                 }
-        void *dstp = field < 3 ? s->E[field] : s->H[field - 3];
+        void *dstp = field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3];
         CK(hipMemcpy(dstp, slots.data(), slots.size(), hipMemcpyHostToDevice));
     } else {
         const int c = field - 6;
@@ -1033,11 +1270,19 @@ mpx_status mpx_set_timing(mpx_sim *s, int32_t every) {
 
 mpx_status mpx_kernel_time(mpx_sim *s, double *avg_ms, int64_t *launches) {
     if (!s || !avg_ms || !launches) return MPX_E_INVALID;
-    // E pass and merged H pass, the two stencil kernels
-    avg_ms[0] = s->t_n[0] ? s->t_ms[0] / s->t_n[0] : 0.0;
-    avg_ms[1] = s->t_n[1] ? s->t_ms[1] / s->t_n[1] : 0.0;
-    launches[0] = s->t_n[0];
-    launches[1] = s->t_n[1];
+    for (int g = 0; g < 3; g++) {
+        avg_ms[g] = s->t_n[g] ? s->t_ms[g] / s->t_n[g] : 0.0;
+        launches[g] = s->t_n[g];
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_set_schedule(mpx_sim *s, int32_t fused, int32_t kchunk) {
+    if (!s || kchunk < 0) return MPX_E_INVALID;
+    drop_graph(s);
+    if (fused < 0 || fused > 4) return MPX_E_INVALID;
+    s->fused = fused;
+    if (kchunk > 0) s->kchunk = kchunk;
     return MPX_OK;
 }
 

@@ -19,18 +19,9 @@
 // with the same sequence of IEEE operations as the plain definition (the
 // library is built with -ffp-contract=off), so repeated runs, tile shapes and
 // the fused pass all give bitwise identical float64 results.
-#include "mpx_internal.h"
+#include "device_common.h"
 
 namespace mpx {
-
-__device__ __forceinline__ int fold(int i, int n, int per) {
-    if (per) {
-        if (i < 0) i += n;
-        if (i >= n) i -= n;
-        return i;
-    }
-    return (i < 0 || i >= n) ? -1 : i;
-}
 
 template <typename T>
 __device__ __forceinline__ T ldz(const KParams<T> &p, const T *a, int i, int j, int k) {
@@ -46,19 +37,6 @@ __device__ __forceinline__ int cell_id(const int *n, const int *per, int px, con
     return id[(long long)ii + (long long)px * ((long long)jj + (long long)n[1] * kk)];
 }
 
-// central difference over a spacing: a true division in float64 (the plain
-// definition), a multiply by the reciprocal in float32
-template <typename T>
-__device__ __forceinline__ T dif(T hi, T lo, T d, T invd) {
-    if constexpr (sizeof(T) == 8) {
-        (void)invd;
-        return (hi - lo) / d;
-    } else {
-        (void)d;
-        return (hi - lo) * invd;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // magnetic-face test: the face of family c at slot idx is magnetic when it
 // lies in a film's site box and one of the two cells sharing it has Ms > 0
@@ -69,169 +47,235 @@ __device__ __forceinline__ int film_of_site(const KParams<T> &p, int c, const in
         const FilmDev &F = p.films[f];
         if (idx[0] >= F.b0[0] && idx[0] < F.b0[0] + F.bn[0] && idx[1] >= F.b0[1] && idx[1] < F.b0[1] + F.bn[1] &&
             idx[2] >= F.b0[2] && idx[2] < F.b0[2] + F.bn[2]) {
-            int lo[3] = {idx[0], idx[1], idx[2]};
-            lo[c] -= 1;
-            int m0 = cell_id(p.n, p.per, p.px, p.id, lo[0], lo[1], lo[2]);
-            int m1 = cell_id(p.n, p.per, p.px, p.id, idx[0], idx[1], idx[2]);
-            bool mag = (m0 >= 0 && p.mat[m0].Ms > 0.0) || (m1 >= 0 && p.mat[m1].Ms > 0.0);
-            return mag ? f : -1;
+            const long long l = (long long)(idx[0] - F.b0[0]) +
+                                (long long)F.bn[0] * ((long long)(idx[1] - F.b0[1]) + (long long)F.bn[1] * (idx[2] - F.b0[2]));
+            return F.prm[(c * 3) * F.ns + l] > 0.0 ? f : -1;
         }
     }
     return -1;
 }
 
 // ---------------------------------------------------------------------------
-// bulk H/M pass for non-magnetic faces: NHALF consecutive half steps with the
-// same E (1 = a bracket half step, 2 = the merged pair around an integer time)
+// Two-pass schedule: a bulk H/M pass for non-magnetic faces and a separate E
+// pass, both in place, one thread per (i, j, k) slot and all three
+// components unrolled at compile time.
 // ---------------------------------------------------------------------------
+
+// slot of the +1 / -1 neighbour along axis A (wrapping on a periodic axis);
+// -1 when it lies outside the domain
+template <typename T, int A>
+__device__ __forceinline__ long long nb_up(const KParams<T> &p, const int *idx, long long q) {
+    if (idx[A] + 1 < p.n[A]) return q + (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
+    if (!p.per[A]) return -1;
+    return q - (long long)(p.n[A] - 1) * (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
+}
+
+template <typename T, int A>
+__device__ __forceinline__ long long nb_dn(const KParams<T> &p, const int *idx, long long q) {
+    if (idx[A] > 0) return q - (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
+    if (!p.per[A]) return -1;
+    return q + (long long)(p.n[A] - 1) * (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldq(const T *a, long long q) {
+    return q >= 0 ? a[q] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ bool slab(const KParams<T> &p, int a, int x) {
+    return x < p.nlo[a] || x >= p.n[a] - p.nhi[a];
+}
+
+// block-uniform: does the (x, y) tile of this block at plane k touch a CPML
+// slab / a film's face box?
+template <typename T>
+__device__ __forceinline__ void tile_flags(const KParams<T> &p, int i0, int j0, int tx, int ty, int k, bool &tpml,
+                                           bool &tfilm) {
+    const int lo[3] = {i0, j0, k}, hi[3] = {i0 + tx - 1, j0 + ty - 1, k};
+    tpml = false;
+    for (int a = 0; a < 3; a++) {
+        if (p.nlo[a] > 0 && lo[a] < p.nlo[a]) tpml = true;
+        if (p.nhi[a] > 0 && hi[a] >= p.n[a] - p.nhi[a]) tpml = true;
+    }
+    tfilm = false;
+    for (int f = 0; f < p.nfilm; f++) {
+        const FilmDev &F = p.films[f];
+        bool in = true;
+        for (int a = 0; a < 3; a++)
+            if (F.b0[a] + F.bn[a] <= lo[a] || F.b0[a] > hi[a]) in = false;
+        if (in) tfilm = true;
+    }
+}
+
+template <typename T, int NHALF, int C>
+__device__ __forceinline__ void hbulk_comp(const KParams<T> &p, const int *idx, long long q, bool tpml, bool tfilm) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    if (tfilm && film_of_site(p, C, idx) >= 0) return;
+    const T e2a = p.E[C2][q];
+    const T e2b = ldq(p.E[C2], nb_up<T, C1>(p, idx, q));
+    const T e1a = p.E[C1][q];
+    const T e1b = ldq(p.E[C1], nb_up<T, C2>(p, idx, q));
+    const T d1r = dif(e2b, e2a, p.dT[C1], p.invd[C1]);
+    const T d2r = dif(e1b, e1a, p.dT[C2], p.invd[C2]);
+    // H_C sits at half positions along C1 and C2
+    const int a1 = idx[C1], a2 = idx[C2];
+    bool s1 = false, s2 = false;
+    long long q1 = 0, q2 = 0;
+    T ps1 = T(0), ps2 = T(0);
+    if (tpml) {
+        s1 = p.psiH[C][C1] && slab(p, C1, a1);
+        s2 = p.psiH[C][C2] && slab(p, C2, a2);
+        if (s1) {
+            q1 = p.psi_index(C1, idx);
+            ps1 = p.psiH[C][C1][q1];
+        }
+        if (s2) {
+            q2 = p.psi_index(C2, idx);
+            ps2 = p.psiH[C][C2][q2];
+        }
+    }
+    T h = p.H[C][q];
+#pragma unroll
+    for (int hs = 0; hs < NHALF; hs++) {
+        T d1 = d1r, d2 = d2r;
+        if (s1) {
+            ps1 = p.bH[C1][a1] * ps1 + p.cH[C1][a1] * d1;
+            d1 += ps1;
+        }
+        if (s2) {
+            ps2 = p.bH[C2][a2] * ps2 + p.cH[C2][a2] * d2;
+            d2 += ps2;
+        }
+        h = h - p.hc * (d1 - d2);
+    }
+    p.H[C][q] = h;
+    if (s1) p.psiH[C][C1][q1] = ps1;
+    if (s2) p.psiH[C][C2][q2] = ps2;
+}
+
+// NHALF consecutive half steps with the same E (1 = a bracket half step,
+// 2 = the merged pair around an integer time)
 template <typename T, int NHALF>
 __global__ void __launch_bounds__(256) k_hbulk(KParams<T> p, int inc_step) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
     if (inc_step && i == 0 && j == 0 && k == 0) p.step[0] = p.step[0] + 1;
+    bool tpml, tfilm;
+    tile_flags(p, blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockDim.x, blockDim.y, k, tpml, tfilm);
     if (i >= p.n[0] || j >= p.n[1]) return;
     const long long q = p.slot(i, j, k);
     const int idx[3] = {i, j, k};
-    for (int c = 0; c < 3; c++) {
-        if (p.nfilm && film_of_site(p, c, idx) >= 0) continue;
-        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-        int u1[3] = {i, j, k}, u2[3] = {i, j, k};
-        u1[c1] += 1;
-        u2[c2] += 1;
-        const T e2a = p.E[c2][q];
-        const T e2b = ldz(p, p.E[c2], u1[0], u1[1], u1[2]);
-        const T e1a = p.E[c1][q];
-        const T e1b = ldz(p, p.E[c1], u2[0], u2[1], u2[2]);
-        const T d1r = dif(e2b, e2a, p.dT[c1], p.invd[c1]);
-        const T d2r = dif(e1b, e1a, p.dT[c2], p.invd[c2]);
-        // H_c sits at half positions along c1 and c2
-        const int a1 = idx[c1], a2 = idx[c2];
-        const bool s1 = p.psiH[c][c1] && (a1 < p.nlo[c1] || a1 >= p.n[c1] - p.nhi[c1]);
-        const bool s2 = p.psiH[c][c2] && (a2 < p.nlo[c2] || a2 >= p.n[c2] - p.nhi[c2]);
-        long long q1 = 0, q2 = 0;
-        T ps1 = T(0), ps2 = T(0);
-        if (s1) {
-            q1 = p.psi_index(c1, idx);
-            ps1 = p.psiH[c][c1][q1];
-        }
-        if (s2) {
-            q2 = p.psi_index(c2, idx);
-            ps2 = p.psiH[c][c2][q2];
-        }
-        T h = p.H[c][q];
-#pragma unroll
-        for (int hs = 0; hs < NHALF; hs++) {
-            T d1 = d1r, d2 = d2r;
-            if (s1) {
-                ps1 = p.bH[c1][a1] * ps1 + p.cH[c1][a1] * d1;
-                d1 += ps1;
-            }
-            if (s2) {
-                ps2 = p.bH[c2][a2] * ps2 + p.cH[c2][a2] * d2;
-                d2 += ps2;
-            }
-            h = h - p.hc * (d1 - d2);
-        }
-        p.H[c][q] = h;
-        if (s1) p.psiH[c][c1][q1] = ps1;
-        if (s2) p.psiH[c][c2][q2] = ps2;
-    }
+    hbulk_comp<T, NHALF, 0>(p, idx, q, tpml, tfilm);
+    hbulk_comp<T, NHALF, 1>(p, idx, q, tpml, tfilm);
+    hbulk_comp<T, NHALF, 2>(p, idx, q, tpml, tfilm);
 }
 
-// ---------------------------------------------------------------------------
-// edge coefficients from the per-cell material ids: eps and sigma are the
-// means over the four cells sharing the edge, the edge is PEC if any is PEC
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ bool edge_coef(const KParams<T> &p, int c, const int *idx, T &ca, T &cb) {
-    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-    double se = 0.0, ss = 0.0;
-    int cnt = 0;
-    bool pec = false;
-    for (int u = -1; u <= 0; u++)
-        for (int v = -1; v <= 0; v++) {
-            int cc[3];
-            cc[c] = idx[c];
-            cc[c1] = idx[c1] + u;
-            cc[c2] = idx[c2] + v;
-            int m = cell_id(p.n, p.per, p.px, p.id, cc[0], cc[1], cc[2]);
-            if (m < 0) continue;
-            se += p.mat[m].eps_r;
-            ss += p.mat[m].sigma;
-            pec = pec || p.mat[m].is_pec;
-            cnt++;
-        }
-    if (pec || cnt == 0) return false;
-    if constexpr (sizeof(T) == 8) {
-        const double eps = p.eps0 * (se / cnt);
-        const double sig = ss / cnt;
-        const double den = sig / 2.0 + eps / p.dt;
-        ca = -(sig / 2.0 - eps / p.dt) / den;
-        cb = 1.0 / den;
+// E update of component C at slot q; the coefficient table of single-id
+// edges is in LDS
+template <typename T, int C>
+__device__ __forceinline__ void epass_comp(const KParams<T> &p, const int *idx, long long q, bool tpml, long long step,
+                                           const T *sca, const T *scb, const uint8_t *spec) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    // tangential to a non-periodic wall: held at zero
+    if ((!p.per[C1] && idx[C1] == 0) || (!p.per[C2] && idx[C2] == 0)) return;
+    const long long qd1 = nb_dn<T, C1>(p, idx, q), qd2 = nb_dn<T, C2>(p, idx, q);
+    // the four cells sharing the edge, (C1, C2) offsets (-1,-1),(-1,0),(0,-1),(0,0)
+    const long long qd12 = qd1 >= 0 ? nb_dn<T, C2>(p, idx, qd1) : -1;
+    const int m0 = p.id[qd12], m1 = p.id[qd1], m2 = p.id[qd2], m3 = p.id[q];
+    T ca, cb;
+    if (m0 == m1 && m0 == m2 && m0 == m3) {
+        if (spec[m0]) return;
+        ca = sca[m0];
+        cb = scb[m0];
     } else {
-        const float eps = float(p.eps0) * (float(se) / float(cnt));
-        const float sig = float(ss) / float(cnt);
-        const float den = sig * 0.5f + eps * float(p.inv_dt);
-        const float rden = 1.0f / den;
-        ca = -(sig * 0.5f - eps * float(p.inv_dt)) * rden;
-        cb = rden;
+        const MatDev &A0 = p.mat[m0], &A1 = p.mat[m1], &A2 = p.mat[m2], &A3 = p.mat[m3];
+        if (A0.is_pec || A1.is_pec || A2.is_pec || A3.is_pec) return;
+        if constexpr (sizeof(T) == 8) {
+            double se = 0.0, ss = 0.0;
+            se += A0.eps_r;
+            ss += A0.sigma;
+            se += A1.eps_r;
+            ss += A1.sigma;
+            se += A2.eps_r;
+            ss += A2.sigma;
+            se += A3.eps_r;
+            ss += A3.sigma;
+            const double eps = p.eps0 * (se / 4);
+            const double sig = ss / 4;
+            const double den = sig / 2.0 + eps / p.dt;
+            ca = -(sig / 2.0 - eps / p.dt) / den;
+            cb = 1.0 / den;
+        } else {
+            const float se = float(A0.eps_r) + float(A1.eps_r) + float(A2.eps_r) + float(A3.eps_r);
+            const float ss = float(A0.sigma) + float(A1.sigma) + float(A2.sigma) + float(A3.sigma);
+            const float eps = float(p.eps0) * (se * 0.25f);
+            const float sig = ss * 0.25f;
+            const float ed = eps * float(p.inv_dt);
+            const float rden = 1.0f / (sig * 0.5f + ed);
+            ca = -(sig * 0.5f - ed) * rden;
+            cb = rden;
+        }
     }
-    return true;
+    const T h2a = p.H[C2][q];
+    const T h2b = ldq(p.H[C2], qd1);
+    const T h1a = p.H[C1][q];
+    const T h1b = ldq(p.H[C1], qd2);
+    T d1 = dif(h2a, h2b, p.dT[C1], p.invd[C1]);
+    T d2 = dif(h1a, h1b, p.dT[C2], p.invd[C2]);
+    if (tpml) {
+        // E_C sits at integer positions along C1 and C2
+        const int a1 = idx[C1], a2 = idx[C2];
+        if (p.psiE[C][C1] && slab(p, C1, a1)) {
+            const long long qq = p.psi_index(C1, idx);
+            const T ps = p.bE[C1][a1] * p.psiE[C][C1][qq] + p.cE[C1][a1] * d1;
+            p.psiE[C][C1][qq] = ps;
+            d1 += ps;
+        }
+        if (p.psiE[C][C2] && slab(p, C2, a2)) {
+            const long long qq = p.psi_index(C2, idx);
+            const T ps = p.bE[C2][a2] * p.psiE[C][C2][qq] + p.cE[C2][a2] * d2;
+            p.psiE[C][C2][qq] = ps;
+            d2 += ps;
+        }
+    }
+    double J = 0.0;
+    for (int s = 0; s < p.nsrc; s++) {
+        const SrcDev &S = p.src[s];
+        if (S.comp != C) continue;
+        if (idx[0] < S.box[0] || idx[0] >= S.box[0] + S.box[3] || idx[1] < S.box[1] || idx[1] >= S.box[1] + S.box[4] ||
+            idx[2] < S.box[2] || idx[2] >= S.box[2] + S.box[5])
+            continue;
+        if (step < S.n) J += S.table[step];
+    }
+    p.E[C][q] = ca * p.E[C][q] + cb * ((d1 - d2) - T(J));
 }
 
-// ---------------------------------------------------------------------------
-// E pass: full step on every non-PEC edge, CPML psi in the slabs, soft source
-// ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_epass(KParams<T> p) {
+    __shared__ T sca[256], scb[256];
+    __shared__ uint8_t spec[256];
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    {
+        const CoefDev<T> cf = p.coef[t];
+        sca[t] = cf.ca;
+        scb[t] = cf.cb;
+        spec[t] = (uint8_t)cf.pec;
+    }
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
+    bool tpml, tfilm;
+    tile_flags(p, blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockDim.x, blockDim.y, k, tpml, tfilm);
     if (i >= p.n[0] || j >= p.n[1]) return;
     const long long q = p.slot(i, j, k);
     const int idx[3] = {i, j, k};
     const long long step = p.step[0];
-    for (int c = 0; c < 3; c++) {
-        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-        // tangential to a non-periodic wall: held at zero
-        if ((!p.per[c1] && idx[c1] == 0) || (!p.per[c2] && idx[c2] == 0)) continue;
-        T ca, cb;
-        if (!edge_coef(p, c, idx, ca, cb)) continue;
-        int l1[3] = {i, j, k}, l2[3] = {i, j, k};
-        l1[c1] -= 1;
-        l2[c2] -= 1;
-        const T h2a = p.H[c2][q];
-        const T h2b = ldz(p, p.H[c2], l1[0], l1[1], l1[2]);
-        const T h1a = p.H[c1][q];
-        const T h1b = ldz(p, p.H[c1], l2[0], l2[1], l2[2]);
-        T d1 = dif(h2a, h2b, p.dT[c1], p.invd[c1]);
-        T d2 = dif(h1a, h1b, p.dT[c2], p.invd[c2]);
-        // E_c sits at integer positions along c1 and c2
-        const int a1 = idx[c1], a2 = idx[c2];
-        if (p.psiE[c][c1] && (a1 < p.nlo[c1] || a1 >= p.n[c1] - p.nhi[c1])) {
-            const long long qq = p.psi_index(c1, idx);
-            const T ps = p.bE[c1][a1] * p.psiE[c][c1][qq] + p.cE[c1][a1] * d1;
-            p.psiE[c][c1][qq] = ps;
-            d1 += ps;
-        }
-        if (p.psiE[c][c2] && (a2 < p.nlo[c2] || a2 >= p.n[c2] - p.nhi[c2])) {
-            const long long qq = p.psi_index(c2, idx);
-            const T ps = p.bE[c2][a2] * p.psiE[c][c2][qq] + p.cE[c2][a2] * d2;
-            p.psiE[c][c2][qq] = ps;
-            d2 += ps;
-        }
-        double J = 0.0;
-        for (int s = 0; s < p.nsrc; s++) {
-            const SrcDev &S = p.src[s];
-            if (S.comp != c) continue;
-            if (i < S.box[0] || i >= S.box[0] + S.box[3] || j < S.box[1] || j >= S.box[1] + S.box[4] ||
-                k < S.box[2] || k >= S.box[2] + S.box[5])
-                continue;
-            if (step < S.n) J += S.table[step];
-        }
-        p.E[c][q] = ca * p.E[c][q] + cb * ((d1 - d2) - T(J));
-    }
+    epass_comp<T, 0>(p, idx, q, tpml, step, sca, scb, spec);
+    epass_comp<T, 1>(p, idx, q, tpml, step, sca, scb, spec);
+    epass_comp<T, 2>(p, idx, q, tpml, step, sca, scb, spec);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,12 +354,7 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     const FilmDev &F = p.films[f];
     bool inside;
     const long long l = film_local<T>(F, idx, inside);
-    bool mag = false;
-    if (inside) {
-        double ms, al, ga;
-        site_params(p, cq, idx, ms, al, ga);
-        mag = ms > 0.0;
-    }
+    const bool mag = inside && F.prm[(cq * 3) * F.ns + l] > 0.0;
     double b;
     if (mag) {
         if (phase == 1)
@@ -341,9 +380,26 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// B^ prepass: B^n and B^* of every face of the grown face box
 template <typename T>
-__global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase) {
+__global__ void __launch_bounds__(256) k_bhat(KParams<T> p, int phase) {
+    const int4 bt = p.blocktab_ext[blockIdx.x];
+    const int f = bt.x, c = bt.y;
+    const FilmDev &F = p.films[f];
+    const long long l = (long long)bt.z + threadIdx.x;
+    if (l >= F.nse) return;
+    const int idx[3] = {F.e0[0] + (int)(l % F.en[0]), F.e0[1] + (int)((l / F.en[0]) % F.en[1]),
+                        F.e0[2] + (int)(l / ((long long)F.en[0] * F.en[1]))};
+    double bn, bs;
+    bhat(p, phase, f, c, idx, bn, bs);
+    F.Bn[c * F.nse + l] = bn;
+    F.Bs[c * F.nse + l] = bs;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase, int inc_step) {
     __shared__ double red[256];
+    if (inc_step && blockIdx.x == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
     const int4 bt = p.blocktab[blockIdx.x]; // film, family, first local index
     const int f = bt.x, c = bt.y;
     const FilmDev &F = p.films[f];
@@ -354,11 +410,19 @@ __global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase) {
         idx[0] = F.b0[0] + (int)(l % F.bn[0]);
         idx[1] = F.b0[1] + (int)((l / F.bn[0]) % F.bn[1]);
         idx[2] = F.b0[2] + (int)(l / ((long long)F.bn[0] * F.bn[1]));
-        double ms, al, ga;
-        site_params(p, c, idx, ms, al, ga);
+        const double ms = F.prm[(c * 3 + 0) * F.ns + l];
+        const double al = F.prm[(c * 3 + 1) * F.ns + l];
+        const double ga = F.prm[(c * 3 + 2) * F.ns + l];
         if (ms > 0.0) {
-            double bn, bs;
-            bhat(p, phase, f, c, idx, bn, bs);
+            // index in the grown face box (every face the solve reads lies in it)
+            // (-1 outside it: cannot happen for accepted film placements)
+            auto ext = [&](const int *q) -> long long {
+                const int r0 = q[0] - F.e0[0], r1 = q[1] - F.e0[1], r2 = q[2] - F.e0[2];
+                if (r0 < 0 || r0 >= F.en[0] || r1 < 0 || r1 >= F.en[1] || r2 < 0 || r2 >= F.en[2]) return -1;
+                return (long long)r0 + (long long)F.en[0] * ((long long)r1 + (long long)F.en[1] * r2);
+            };
+            const long long le = ext(idx);
+            const double bn = le >= 0 ? F.Bn[c * F.nse + le] : 0.0, bs = le >= 0 ? F.Bs[c * F.nse + le] : 0.0;
             double P[3], Q[3], M[3];
             P[c] = bs;
             Q[c] = bn;
@@ -373,7 +437,9 @@ __global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase) {
                         q[c] += u - 1;
                         q[cp] += v;
                         for (int a = 0; a < 3; a++) q[a] = fold(q[a], p.n[a], p.per[a]);
-                        bhat(p, phase, f, cp, q, vn[u][v], vs[u][v]);
+                        const long long lq = ext(q);
+                        vn[u][v] = lq >= 0 ? F.Bn[cp * F.nse + lq] : 0.0;
+                        vs[u][v] = lq >= 0 ? F.Bs[cp * F.nse + lq] : 0.0;
                     }
                 Q[cp] = ((vn[0][0] + vn[1][0]) + (vn[0][1] + vn[1][1])) * 0.25;
                 P[cp] = ((vs[0][0] + vs[1][0]) + (vs[0][1] + vs[1][1])) * 0.25;
@@ -404,7 +470,7 @@ __global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase) {
                 F.H1[c * F.ns + l] = hnew;
             } else {
                 for (int w = 0; w < 3; w++) F.M[(c * 3 + w) * F.ns + l] = Mn[w];
-                p.H[c][p.slot(idx[0], idx[1], idx[2])] = (T)hnew;
+                p.Hw[c][p.slot(idx[0], idx[1], idx[2])] = (T)hnew;
             }
             own = Mn[c];
         }
@@ -431,11 +497,9 @@ __global__ void __launch_bounds__(256) k_film_commit(KParams<T> p) {
     idx[0] = F.b0[0] + (int)(l % F.bn[0]);
     idx[1] = F.b0[1] + (int)((l / F.bn[0]) % F.bn[1]);
     idx[2] = F.b0[2] + (int)(l / ((long long)F.bn[0] * F.bn[1]));
-    double ms, al, ga;
-    site_params(p, c, idx, ms, al, ga);
-    if (!(ms > 0.0)) return;
+    if (!(F.prm[(c * 3) * F.ns + l] > 0.0)) return;
     for (int w = 0; w < 3; w++) F.M[(c * 3 + w) * F.ns + l] = F.M1[(c * 3 + w) * F.ns + l];
-    p.H[c][p.slot(idx[0], idx[1], idx[2])] = (T)F.H1[c * F.ns + l];
+    p.Hw[c][p.slot(idx[0], idx[1], idx[2])] = (T)F.H1[c * F.ns + l];
 }
 
 // ---------------------------------------------------------------------------
@@ -627,9 +691,8 @@ __global__ void __launch_bounds__(256) k_zeeman(KParams<T> p) {
         idx[0] = F.b0[0] + (int)(l % F.bn[0]);
         idx[1] = F.b0[1] + (int)((l / F.bn[0]) % F.bn[1]);
         idx[2] = F.b0[2] + (int)(l / ((long long)F.bn[0] * F.bn[1]));
-        double ms, al, ga;
-        site_params(p, c, idx, ms, al, ga);
-        if (ms > 0.0) z = p.H0[c] * F.M[(c * 3 + c) * F.ns + l];
+        (void)idx;
+        if (F.prm[(c * 3) * F.ns + l] > 0.0) z = p.H0[c] * F.M[(c * 3 + c) * F.ns + l];
     }
     red[threadIdx.x] = z;
     __syncthreads();
@@ -697,9 +760,19 @@ hipError_t launch_epass(const KParams<T> &p, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_film(const KParams<T> &p, int nblk, int phase, hipStream_t s) {
+hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s) {
     if (nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_film<T>, dim3(nblk), dim3(256), 0, s, p, phase);
+    hipLaunchKernelGGL(k_bhat<T>, dim3(p.nblk_ext), dim3(256), 0, s, p, phase);
+    hipLaunchKernelGGL(k_film<T>, dim3(nblk), dim3(256), 0, s, p, phase, inc);
+    return hipGetLastError();
+}
+
+__global__ void k_tick(long long *step) {
+    if (threadIdx.x == 0) step[0] = step[0] + 1;
+}
+
+hipError_t launch_tick(long long *step, hipStream_t s) {
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, step);
     return hipGetLastError();
 }
 
@@ -733,7 +806,7 @@ hipError_t launch_energy(const KParams<T> &p, int nblk, double *part, double *ou
 #define MPX_INSTANTIATE(T)                                                                  \
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);         \
     template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                   \
-    template hipError_t launch_film<T>(const KParams<T> &, int, int, hipStream_t);          \
+    template hipError_t launch_film<T>(const KParams<T> &, int, int, int, hipStream_t);     \
     template hipError_t launch_commit<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_probes<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_energy<T>(const KParams<T> &, int, double *, double *, hipStream_t);

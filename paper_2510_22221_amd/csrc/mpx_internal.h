@@ -28,7 +28,14 @@ struct FilmDev {
     long long ns;
     double ncells;
     double *M, *M1, *H1;
+    const double *prm; // [family][Ms_s, alpha_s, |gamma|_s][site], from the ids
     int blk0[3], nblk[3];
+    // B^ and B^* of every face of the face box grown by one layer on the low
+    // side of each axis it does not span (the neighbours the LLG reads),
+    // [family][site], written by a prepass before each half step
+    int e0[3], en[3];
+    long long nse;
+    double *Bn, *Bs;
 };
 
 struct SrcDev {
@@ -42,6 +49,15 @@ struct ProbeDev {
     int kind, field, i, j, k, film, nval, pad;
     long long cap, start;
     double *data;
+};
+
+// Coefficients of an edge whose four cells share one material id, computed
+// on the host with the same operation sequence the device uses for mixed
+// edges (so the fast path is bitwise identical to the general one).
+template <typename T>
+struct CoefDev {
+    T ca, cb;
+    int pec, pad;
 };
 
 template <typename T>
@@ -58,6 +74,11 @@ struct KParams {
     double H0[3];
     T *E[3];
     T *H[3];
+    T *Hw[3];      // where the film kernels write H of magnetic faces
+    T *Eb[3];      // fused pass: destinations (ping-pong partners of E, H)
+    T *Hb[3];
+    T *psiEb[3][3];
+    const CoefDev<T> *coef;
     const uint8_t *id;
     const MatDev *mat;
     int nlo[3], nhi[3];
@@ -70,6 +91,8 @@ struct KParams {
     int nfilm;
     const FilmDev *films;
     const int4 *blocktab;
+    const int4 *blocktab_ext; // blocks of the B^ prepass (film, family, first)
+    int nblk_ext;
     double *partial;
     int nsrc;
     SrcDev src[kMaxSources];
@@ -93,7 +116,9 @@ struct KParams {
 
 template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s);
 template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
-template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, hipStream_t s);
+template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
+template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
+hipError_t launch_tick(long long *step, hipStream_t s);
 template <typename T> hipError_t launch_commit(const KParams<T> &p, int nblk, hipStream_t s);
 template <typename T> hipError_t launch_probes(const KParams<T> &p, int nprobe, hipStream_t s);
 template <typename T>

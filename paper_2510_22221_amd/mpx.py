@@ -33,8 +33,9 @@ STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "mpx_set_materials",
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
-           "mpx_synchronize", "mpx_read_field", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
-           "mpx_film_box", "mpx_set_graph_steps", "mpx_set_timing", "mpx_kernel_time", "mpx_last_error"]
+           "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
+           "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
+           "mpx_last_error"]
 
 
 class MpxError(RuntimeError):
@@ -93,12 +94,14 @@ def load(path: str = LIB_PATH):
         "mpx_step": (I32, [P, I64]),
         "mpx_synchronize": (I32, [P]),
         "mpx_read_field": (I32, [P, I32, P, I64, I32]),
+        "mpx_read_field_region": (I32, [P, I32, C.POINTER(I32), P, I64, I32]),
         "mpx_write_field": (I32, [P, I32, P, I64, I32]),
         "mpx_read_probe": (I32, [P, I32, P, I64, C.POINTER(I64)]),
         "mpx_energy": (I32, [P, C.POINTER(D), C.POINTER(D)]),
         "mpx_info": (I32, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]),
         "mpx_film_box": (I32, [P, I32, C.POINTER(I32), C.POINTER(I64)]),
         "mpx_set_graph_steps": (I32, [P, I32]),
+        "mpx_set_schedule": (I32, [P, I32, I32]),
         "mpx_set_timing": (I32, [P, I32]),
         "mpx_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64)]),
         "mpx_last_error": (C.c_char_p, [P]),
@@ -207,12 +210,19 @@ class Sim:
     def sync(self):
         self._ck(self._L.mpx_synchronize(self._h), "synchronize")
 
+    def set_schedule(self, fused=True, kchunk=0):
+        """fused: False/0 = separate E and H passes; True/1..4 = fused pass
+        (the integer picks the tile variant)."""
+        v = int(fused) if not isinstance(fused, bool) else (1 if fused else 0)
+        self._ck(self._L.mpx_set_schedule(self._h, v, int(kchunk)), "set_schedule")
+
     def kernel_time(self):
-        """(avg ms per launch, launches) of the E pass and the H pass."""
-        ms = (C.c_double * 2)()
-        n = (C.c_int64 * 2)()
+        """[(avg ms per launch, launches)] of: the main stencil kernel, the
+        second stencil kernel (two-pass schedule only), film + probe kernels."""
+        ms = (C.c_double * 3)()
+        n = (C.c_int64 * 3)()
         self._ck(self._L.mpx_kernel_time(self._h, ms, n), "kernel_time")
-        return [(ms[q], n[q]) for q in range(2)]
+        return [(ms[q], n[q]) for q in range(3)]
 
     # ---- fields ------------------------------------------------------------------
     def dims(self, field):
@@ -231,6 +241,17 @@ class Sim:
             return out
         arr = np.empty((nc, nz, ny, nx), dtype=dt)
         self._ck(self._L.mpx_read_field(self._h, int(field), arr.ctypes.data, nb, 0), "read_field")
+        return arr[0] if nc == 1 else arr
+
+    def get_region(self, field, box):
+        """Sub-box (i0, j0, k0, ni, nj, nk) of a field, numpy [k, j, i] (or
+        [3, k, j, i] for the M fields)."""
+        (_, _, _, nc), _ = self.dims(field)
+        dt = np.float64 if field >= 6 else self.dtype
+        b = (C.c_int32 * 6)(*(int(v) for v in box))
+        arr = np.empty((nc, box[5], box[4], box[3]), dtype=dt)
+        self._ck(self._L.mpx_read_field_region(self._h, int(field), b, arr.ctypes.data, arr.nbytes, 0),
+                 "read_field_region")
         return arr[0] if nc == 1 else arr
 
     def set(self, field, arr):
@@ -274,7 +295,7 @@ class Sim:
         return out
 
 
-def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None):
+def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None, fused=None, kchunk=0):
     """Build a Sim from a ``synth.workloads.Workload`` (same inputs the
     oracle takes)."""
     s = Sim(w.nx, w.ny, w.nz, w.d, dt=w.dt, courant=w.courant, bc=w.bc, npml=w.npml, pml_order=w.pml_order,
@@ -291,4 +312,6 @@ def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None):
         s.add_probe(kind, p.field, p.ijk, p.film, cap=max(1, p.cap or w.nsteps))
     if graph_steps is not None:
         s.set_graph_steps(graph_steps)
+    if fused is not None or kchunk:
+        s.set_schedule(True if fused is None else fused, kchunk)
     return s

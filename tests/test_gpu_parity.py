@@ -35,7 +35,7 @@ def _libs():
 
 def check(g, o, w, tol):
     errs = group_errors(g, o)
-    perr = probe_errors(g, o, w)
+    perr = probe_errors(g, o, w, f64=tol < 1e-9)
     say(f"  groups {errs}  probes max {max(perr) if perr else 0:.2e}")
     for k, v in errs.items():
         assert v <= tol, (k, v)
@@ -219,3 +219,37 @@ def test_nonfinite_watchdog():
     g.step(2)
     with pytest.raises(mpx.MpxError, match="NONFINITE"):
         g.sync()
+
+
+# ------------------------------------------------------------------ schedules
+SCHED_CASES = [
+    ("c1", lambda: W.c1(120), 120),
+    ("random-pml", lambda: W.random_case(3, nx=70, ny=19, nz=23, bc=(W.PML,) * 6, npml=(3,) * 6, film=False,
+                                         nsteps=40), 40),
+    ("random-periodic", lambda: W.random_case(4, nx=13, ny=11, nz=9,
+                                              bc=(W.PERIODIC, W.PERIODIC, W.PERIODIC, W.PERIODIC, W.PEC, W.PEC),
+                                              nsteps=40), 40),
+]
+
+
+@pytest.mark.parametrize("name,make,nsteps", SCHED_CASES)
+def test_fused_schedule_bitwise_equals_two_pass(name, make, nsteps):
+    """The fused E + merged H/M pass (several z-chunk sizes, partial tiles)
+    gives float64 results bitwise equal to the separate E and H passes, and
+    float32 results within rounding."""
+    w = make()
+    say(f"schedules {name}")
+    ref = mpx.from_workload(w, fused=False)
+    ref.step(nsteps)
+    for variant, kchunk in ((1, 1), (1, 5), (1, 16), (2, 7), (3, 16), (4, 3)):
+        g = mpx.from_workload(w, fused=variant, kchunk=kchunk)
+        g.step(nsteps // 2)
+        g.step(nsteps - nsteps // 2)
+        for f in (0, 1, 2, 3, 4, 5, 6, 7, 8):
+            assert np.array_equal(g.get(f), ref.get(f)), (variant, kchunk, f)
+    a = mpx.from_workload(w, precision=mpx.F32, fused=True)
+    b = mpx.from_workload(w, precision=mpx.F32, fused=False)
+    a.step(nsteps)
+    b.step(nsteps)
+    for f in (0, 3):
+        assert rel(a.get(f), b.get(f)) < 1e-5
