@@ -120,6 +120,49 @@ def roofline_for(w, esz, kt, dtype_name, fused=True):
     return out
 
 
+def batched_sweep(steps, n_inst, variant=None, kchunk=None):
+    """The bias sweep: n_inst resonator + film instances of uneven size,
+    float32, stepped one after another (each with its own captured graphs)
+    and then as one batch (one fused launch per step over all instances).
+    Both runs start from the same state and the batch's results are bitwise
+    those of the single runs (checked in the GPU tests); returns the
+    throughput of both."""
+    from paper_2510_22221_amd import mpx
+    from synth import workloads as W
+
+    ws = W.c3(nsteps=2 * steps + 40, n=n_inst)
+    cells = sum(w.ncells for w in ws)
+    t0 = time.time()
+    sims = [mpx.from_workload(w, precision=mpx.F32) for w in ws]
+    log(f"  {n_inst} instances, {cells} cells, setup {time.time() - t0:.1f} s")
+    for s in sims:
+        s.step(4)
+    for s in sims:
+        s.sync()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+        s.sync()
+    seq = time.perf_counter() - t0
+    b = mpx.Batch(sims)
+    if variant:
+        b.set_schedule(variant, kchunk or 0)
+    b.step(4)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    bat = time.perf_counter() - t0
+    b.close()
+    for s in sims:
+        s.close()
+    return {"instances": n_inst, "cells": cells, "steps": steps, "dtype": "f32",
+            "sequential_Gcell_s": round(cells * steps / seq / 1e9, 3),
+            "batched_Gcell_s": round(cells * steps / bat / 1e9, 3),
+            "batched_over_sequential": round(seq / bat, 3),
+            "schedule": {"variant": variant or 1, "kchunk": kchunk or 16}}
+
+
 def cpu_baseline(w, nsteps):
     import oracle.oracle as O
     O.build()
@@ -151,6 +194,8 @@ def main():
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
     ap.add_argument("--two-pass", action="store_true", help="separate E and H passes instead of the fused pass")
+    ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
+    ap.add_argument("--sweep-instances", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
@@ -195,6 +240,9 @@ def main():
                              "unit": "Gcell-updates/s", "steps": args.f64_steps,
                              "ms_per_step": round(wall64 / args.f64_steps * 1e3, 5),
                              "roofline": roofline_for(w, 8, kt64, "f64", fused)}]
+    if args.sweep_steps > 0:
+        log(f"batched bias sweep: {args.sweep_instances} instances, {args.sweep_steps} steps")
+        out["batched_sweep"] = batched_sweep(args.sweep_steps, args.sweep_instances)
     if not args.no_cpu:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

@@ -240,6 +240,43 @@ mpx_status mpx_kernel_time(mpx_sim *sim, double *avg_ms, int64_t *launches);
 /* Human-readable description of the last error on this handle. */
 const char *mpx_last_error(const mpx_sim *sim);
 
+/* ---- Batched stepping (many simulations per launch) --------------------
+ *
+ * A batch groups n >= 1 simulation handles of one precision on one device,
+ * each with materials set (and magnetisation initialised where it has
+ * films), typically the same device under different bias fields or
+ * geometries (a parameter sweep).  mpx_batch_step advances every member by
+ * nsteps time steps with one fused stencil launch per step covering all
+ * members' tiles, and one launch each for their film half steps and probes,
+ * so that small grids still fill the chip.  Each member's results are
+ * bitwise identical to stepping it alone with mpx_step under the same tile
+ * variant.  Sources, probes and films of each member behave exactly as for
+ * a lone handle (its probe ring and step counter advance).
+ *
+ * The batch keeps pointers to the handles: they must outlive it and must not
+ * be re-configured (materials, sources, probes, schedule) while it exists;
+ * fields may be read and written between calls.  Work runs on the first
+ * member's stream, ordered after each member's stream on entry and before
+ * it on exit.  Errors: MPX_E_INVALID for null/duplicate handles or mixed
+ * precision/device, MPX_E_STATE for a member not ready to step,
+ * MPX_E_DEVICE for HIP failures (sticky on the batch). */
+typedef struct mpx_batch mpx_batch;
+
+mpx_status mpx_batch_create(mpx_sim *const *sims, int32_t n, mpx_batch **out);
+mpx_status mpx_batch_destroy(mpx_batch *batch);
+
+/* Tile variant 1..4 and z-chunk (0 keeps the current one) of the batched
+ * fused pass; defaults are those of the first member (variant 1 if that
+ * member uses the two-pass schedule). */
+mpx_status mpx_batch_set_schedule(mpx_batch *batch, int32_t variant, int32_t kchunk);
+
+/* Steps per captured HIP graph (rounded up to even; 0 launches directly). */
+mpx_status mpx_batch_set_graph_steps(mpx_batch *batch, int32_t steps);
+
+mpx_status mpx_batch_step(mpx_batch *batch, int64_t nsteps);
+mpx_status mpx_batch_synchronize(mpx_batch *batch);
+const char *mpx_batch_last_error(const mpx_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -217,16 +217,13 @@ __device__ __forceinline__ bool face_is_magnetic(const KParams<T> &p, int c, con
 
 // FROWS rows per thread (blockDim = 64 x 8/FROWS); MINW: minimum waves per
 // SIMD the register allocation must allow
-template <typename T, int FROWS, int MINW>
-__global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
-    k_fused(KParams<T> p, int kchunk, int nxt, int nyt, int ntile) {
+template <typename T, int FROWS>
+__device__ __forceinline__ void fused_body(const KParams<T> &p, int t, int kchunk) {
     constexpr int FBY = FTY / FROWS;
     constexpr int FNT = FTX * FBY;
     constexpr int NSTAGE = (HY_ * HX_ + FNT - 1) / FNT; // staged points per thread
     __shared__ FusedLds<T> L;
-    const int per = (ntile + 7) / 8;
-    const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (t >= ntile) return;
+    const int nxt = (p.n[0] + FTX - 1) / FTX, nyt = (p.n[1] + FTY - 1) / FTY;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * FTX + tx;
     const int i0 = (t % nxt) * FTX;
@@ -412,6 +409,54 @@ __global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
         }
     }
 }
+
+template <typename T, int FROWS, int MINW>
+__global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
+    k_fused(KParams<T> p, int kchunk, int nxt, int nyt, int ntile) {
+    // XCD-aware order: blocks are dealt round-robin to the 8 XCDs; give each
+    // XCD a contiguous run of tiles
+    const int per = (ntile + 7) / 8;
+    const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntile) return;
+    (void)nxt;
+    (void)nyt;
+    fused_body<T, FROWS>(p, t, kchunk);
+}
+
+// batched: work[w] = (instance, tile, z-chunk); the instances' parameters in
+// device memory; the same XCD-aware dealing over the whole work list
+template <typename T, int FROWS, int MINW>
+__global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
+    k_fused_batch(const KParams<T> *plist, const int4 *work, int nwork) {
+    const int per = (nwork + 7) / 8;
+    const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= nwork) return;
+    const int4 wk = work[w];
+    fused_body<T, FROWS>(plist[wk.x], wk.y, wk.z);
+}
+
+template <typename T>
+hipError_t launch_fused_batch(const KParams<T> *plist, const int4 *work, int nwork, int variant, hipStream_t s) {
+    const int nblk = (nwork + 7) / 8 * 8;
+    switch (variant) {
+    case 2:
+        k_fused_batch<T, 2, 4><<<dim3(nblk), dim3(FTX, FTY / 2), 0, s>>>(plist, work, nwork);
+        break;
+    case 3:
+        k_fused_batch<T, 1, 2><<<dim3(nblk), dim3(FTX, FTY), 0, s>>>(plist, work, nwork);
+        break;
+    case 4:
+        k_fused_batch<T, 1, 4><<<dim3(nblk), dim3(FTX, FTY), 0, s>>>(plist, work, nwork);
+        break;
+    default:
+        k_fused_batch<T, 2, 2><<<dim3(nblk), dim3(FTX, FTY / 2), 0, s>>>(plist, work, nwork);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_fused_batch<float>(const KParams<float> *, const int4 *, int, int, hipStream_t);
+template hipError_t launch_fused_batch<double>(const KParams<double> *, const int4 *, int, int, hipStream_t);
 
 // variant: 1 = 2 rows/thread, >= 2 waves/SIMD; 2 = 2 rows, >= 4 waves;
 // 3 = 1 row/thread (512 threads), >= 2 waves; 4 = 1 row, >= 4 waves

@@ -485,10 +485,10 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
 
 // the last step of a call: E pass, first H/M half step (probes), commit
 template <typename T>
-mpx_status run_last(mpx_sim *s, int par) {
+mpx_status run_last(mpx_sim *s, int par, hipStream_t st = nullptr) {
     KParams<T> p;
     fill_params<T>(s, p, MODE_INPLACE, par);
-    hipStream_t st = s->stream;
+    if (!st) st = s->stream;
     CK(launch_epass<T>(p, st));
     CK(launch_film<T>(p, s->nblk, 1, 0, st));
     CK(launch_probes<T>(p, (int)s->probes.size(), st));
@@ -580,6 +580,187 @@ mpx_status upload_probes(mpx_sim *s) {
     for (auto &pr : s->probes) v.push_back(pr.dev);
     CK(hipMalloc(&s->d_probes, v.size() * sizeof(ProbeDev)));
     CK(hipMemcpy(s->d_probes, v.data(), v.size() * sizeof(ProbeDev), hipMemcpyHostToDevice));
+    return MPX_OK;
+}
+
+} // namespace
+
+// ===========================================================================
+// Batched stepping of several simulations
+// ===========================================================================
+struct mpx_batch {
+    std::vector<mpx_sim *> sims;
+    mpx_precision prec = MPX_F64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int variant = 1, kchunk = 16;
+    size_t psize = 0;
+    void *d_pa[2] = {nullptr, nullptr}; // fused-pass parameters, flip 0 / 1
+    void *d_pb[2] = {nullptr, nullptr}; // film / probe parameters after it
+    int4 *d_work = nullptr;
+    int nwork = 0;
+    int2 *d_wfilm = nullptr, *d_wext = nullptr, *d_wprobe = nullptr;
+    int nwfilm = 0, nwext = 0, nwprobe = 0;
+    int *d_tick = nullptr;
+    int ntick = 0;
+    int graph_steps = 64;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    std::vector<hipEvent_t> ev;
+    std::string err;
+    bool dead = false;
+};
+
+namespace {
+
+mpx_status bdev_fail(mpx_batch *b, hipError_t e, const char *what) {
+    b->dead = true;
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    return MPX_E_DEVICE;
+}
+
+#define BCK(call)                                                  \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return bdev_fail(b, _e, #call);      \
+    } while (0)
+
+void batch_drop_graph(mpx_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
+template <typename T>
+mpx_status batch_tables(mpx_batch *b) {
+    // fused tiles: instance by instance, tiles in the single-instance order
+    std::vector<int4> work;
+    std::vector<int2> wfilm, wext, wprobe;
+    std::vector<int> tick;
+    for (int q = 0; q < (int)b->sims.size(); q++) {
+        const mpx_sim *s = b->sims[q];
+        const int nxt = (s->n[0] + 63) / 64, nyt = (s->n[1] + 7) / 8;
+        const int nzc = (s->n[2] + b->kchunk - 1) / b->kchunk;
+        for (int t = 0; t < nxt * nyt * nzc; t++) work.push_back(make_int4(q, t, b->kchunk, 0));
+        for (int k = 0; k < s->nblk; k++) wfilm.push_back(make_int2(q, k));
+        for (int k = 0; k < s->nblk_ext; k++) wext.push_back(make_int2(q, k));
+        for (int k = 0; k < (int)s->probes.size(); k++) wprobe.push_back(make_int2(q, k));
+        if (s->nblk == 0) tick.push_back(q);
+    }
+    (void)hipFree(b->d_work);
+    (void)hipFree(b->d_wfilm);
+    (void)hipFree(b->d_wext);
+    (void)hipFree(b->d_wprobe);
+    (void)hipFree(b->d_tick);
+    b->d_work = nullptr;
+    b->d_wfilm = b->d_wext = b->d_wprobe = nullptr;
+    b->d_tick = nullptr;
+    b->nwork = (int)work.size();
+    b->nwfilm = (int)wfilm.size();
+    b->nwext = (int)wext.size();
+    b->nwprobe = (int)wprobe.size();
+    b->ntick = (int)tick.size();
+    BCK(hipMalloc(&b->d_work, std::max<size_t>(1, work.size()) * sizeof(int4)));
+    if (!work.empty()) BCK(hipMemcpy(b->d_work, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice));
+    auto up2 = [&](int2 **d, std::vector<int2> &v) -> mpx_status {
+        BCK(hipMalloc(d, std::max<size_t>(1, v.size()) * sizeof(int2)));
+        if (!v.empty()) BCK(hipMemcpy(*d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice));
+        return MPX_OK;
+    };
+    mpx_status r;
+    if ((r = up2(&b->d_wfilm, wfilm)) != MPX_OK) return r;
+    if ((r = up2(&b->d_wext, wext)) != MPX_OK) return r;
+    if ((r = up2(&b->d_wprobe, wprobe)) != MPX_OK) return r;
+    BCK(hipMalloc(&b->d_tick, std::max<size_t>(1, tick.size()) * sizeof(int)));
+    if (!tick.empty()) BCK(hipMemcpy(b->d_tick, tick.data(), tick.size() * sizeof(int), hipMemcpyHostToDevice));
+    return MPX_OK;
+}
+
+// the instances' parameters at their current parity (flip 0) and flipped
+template <typename T>
+mpx_status batch_params(mpx_batch *b) {
+    const size_t n = b->sims.size();
+    std::vector<KParams<T>> pa(n), pb(n);
+    for (int f = 0; f < 2; f++) {
+        for (size_t q = 0; q < n; q++) {
+            const mpx_sim *s = b->sims[q];
+            fill_params<T>(s, pa[q], MODE_FUSED, s->parity ^ f);
+            fill_params<T>(s, pb[q], MODE_AFTER_FUSED, s->parity ^ f);
+        }
+        BCK(hipMemcpyAsync(b->d_pa[f], pa.data(), n * sizeof(KParams<T>), hipMemcpyHostToDevice, b->stream));
+        BCK(hipMemcpyAsync(b->d_pb[f], pb.data(), n * sizeof(KParams<T>), hipMemcpyHostToDevice, b->stream));
+    }
+    // the staging vectors must live until the copies are done
+    BCK(hipStreamSynchronize(b->stream));
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status batch_body(mpx_batch *b, int f) {
+    const KParams<T> *pa = (const KParams<T> *)b->d_pa[f];
+    const KParams<T> *pb = (const KParams<T> *)b->d_pb[f];
+    hipStream_t st = b->stream;
+    BCK(launch_fused_batch<T>(pa, b->d_work, b->nwork, b->variant, st));
+    BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
+    BCK(launch_probes_batch<T>(pb, b->d_wprobe, b->nwprobe, st));
+    BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 1, st));
+    BCK(launch_tick_batch<T>(pb, b->d_tick, b->ntick, st));
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status batch_steps(mpx_batch *b, long long nsteps) {
+    hipStream_t st = b->stream;
+    mpx_status r;
+    if ((r = batch_params<T>(b)) != MPX_OK) return r;
+    // bracket half step of every instance
+    for (mpx_sim *s : b->sims) {
+        KParams<T> p;
+        fill_params<T>(s, p, MODE_INPLACE, s->parity);
+        BCK(launch_film<T>(p, s->nblk, 1, 0, st));
+        BCK(launch_commit<T>(p, s->nblk, st));
+        BCK(launch_hbulk<T>(p, 1, 0, st));
+    }
+    long long body = nsteps - 1;
+    int f = 0;
+    const int G = (b->graph_steps + 1) / 2 * 2;
+    if (G > 0 && body >= G) {
+        if (!b->graph_valid) {
+            BCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int n = 0; n < G; n++) {
+                r = batch_body<T>(b, n & 1);
+                if (r != MPX_OK) {
+                    hipGraph_t g;
+                    (void)hipStreamEndCapture(st, &g);
+                    return r;
+                }
+            }
+            BCK(hipStreamEndCapture(st, &b->graph));
+            BCK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            b->graph_valid = true;
+        }
+        while (body >= G) {
+            BCK(hipGraphLaunch(b->gexec, st));
+            body -= G;
+        }
+    }
+    for (long long n = 0; n < body; n++) {
+        if ((r = batch_body<T>(b, f)) != MPX_OK) return r;
+        f ^= 1;
+    }
+    // the flips of the body: every instance changed parity (nsteps - 1) times
+    for (mpx_sim *s : b->sims) s->parity ^= (int)((nsteps - 1) & 1);
+    for (mpx_sim *s : b->sims) {
+        if ((r = run_last<T>(s, s->parity, st)) != MPX_OK) {
+            b->dead = true;
+            b->err = s->err;
+            return r;
+        }
+        s->step += nsteps;
+    }
     return MPX_OK;
 }
 
@@ -1287,5 +1468,126 @@ mpx_status mpx_set_schedule(mpx_sim *s, int32_t fused, int32_t kchunk) {
 }
 
 const char *mpx_last_error(const mpx_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+mpx_status mpx_batch_create(mpx_sim *const *sims, int32_t n, mpx_batch **out) {
+    if (!sims || n < 1 || !out) return MPX_E_INVALID;
+    *out = nullptr;
+    for (int q = 0; q < n; q++) {
+        if (!sims[q] || sims[q]->dead) return MPX_E_INVALID;
+        if (!sims[q]->have_mat || (!sims[q]->films.empty() && !sims[q]->have_u)) return MPX_E_STATE;
+        if (sims[q]->prec != sims[0]->prec || sims[q]->device != sims[0]->device) return MPX_E_INVALID;
+        for (int r = 0; r < q; r++)
+            if (sims[r] == sims[q]) return MPX_E_INVALID;
+    }
+    mpx_batch *b = new mpx_batch();
+    b->sims.assign(sims, sims + n);
+    b->prec = sims[0]->prec;
+    b->device = sims[0]->device;
+    b->stream = sims[0]->stream;
+    b->variant = sims[0]->fused ? sims[0]->fused : 1;
+    b->kchunk = sims[0]->kchunk;
+    (void)hipSetDevice(b->device);
+    b->psize = b->prec == MPX_F64 ? sizeof(KParams<double>) : sizeof(KParams<float>);
+    mpx_status r = MPX_OK;
+    auto setup = [&]() -> mpx_status {
+        for (int f = 0; f < 2; f++) {
+            BCK(hipMalloc(&b->d_pa[f], n * b->psize));
+            BCK(hipMalloc(&b->d_pb[f], n * b->psize));
+        }
+        return b->prec == MPX_F64 ? batch_tables<double>(b) : batch_tables<float>(b);
+    };
+    r = setup();
+    if (r != MPX_OK) {
+        mpx_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return MPX_OK;
+}
+
+mpx_status mpx_batch_destroy(mpx_batch *b) {
+    if (!b) return MPX_OK;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (auto e : b->ev) (void)hipEventDestroy(e);
+    for (int f = 0; f < 2; f++) {
+        (void)hipFree(b->d_pa[f]);
+        (void)hipFree(b->d_pb[f]);
+    }
+    (void)hipFree(b->d_work);
+    (void)hipFree(b->d_wfilm);
+    (void)hipFree(b->d_wext);
+    (void)hipFree(b->d_wprobe);
+    (void)hipFree(b->d_tick);
+    delete b;
+    return MPX_OK;
+}
+
+mpx_status mpx_batch_set_schedule(mpx_batch *b, int32_t variant, int32_t kchunk) {
+    if (!b || variant < 1 || variant > 4 || kchunk < 0) return MPX_E_INVALID;
+    (void)hipSetDevice(b->device);
+    batch_drop_graph(b);
+    b->variant = variant;
+    if (kchunk > 0 && kchunk != b->kchunk) {
+        b->kchunk = kchunk;
+        return b->prec == MPX_F64 ? batch_tables<double>(b) : batch_tables<float>(b);
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_batch_set_graph_steps(mpx_batch *b, int32_t steps) {
+    if (!b || steps < 0) return MPX_E_INVALID;
+    if (steps != b->graph_steps) batch_drop_graph(b);
+    b->graph_steps = steps;
+    return MPX_OK;
+}
+
+mpx_status mpx_batch_step(mpx_batch *b, int64_t nsteps) {
+    if (!b || nsteps < 0) return MPX_E_INVALID;
+    if (b->dead) return MPX_E_DEVICE;
+    for (mpx_sim *s : b->sims)
+        if (s->dead) return MPX_E_DEVICE;
+    if (nsteps == 0) return MPX_OK;
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return bdev_fail(b, e, "hipSetDevice");
+    // order the batch stream after each instance's own stream, and back
+    auto join = [&](hipStream_t from, hipStream_t to) -> mpx_status {
+        if (from == to) return MPX_OK;
+        hipEvent_t ev;
+        BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        BCK(hipEventRecord(ev, from));
+        BCK(hipStreamWaitEvent(to, ev, 0));
+        b->ev.push_back(ev);
+        return MPX_OK;
+    };
+    mpx_status r;
+    for (mpx_sim *s : b->sims)
+        if ((r = join(s->stream, b->stream)) != MPX_OK) return r;
+    r = b->prec == MPX_F64 ? batch_steps<double>(b, nsteps) : batch_steps<float>(b, nsteps);
+    if (r != MPX_OK) return r;
+    for (mpx_sim *s : b->sims)
+        if ((r = join(b->stream, s->stream)) != MPX_OK) return r;
+    if (b->ev.size() > 4096) {
+        BCK(hipStreamSynchronize(b->stream));
+        for (auto ev : b->ev) (void)hipEventDestroy(ev);
+        b->ev.clear();
+    }
+    return MPX_OK;
+}
+
+mpx_status mpx_batch_synchronize(mpx_batch *b) {
+    if (!b) return MPX_E_INVALID;
+    if (b->dead) return MPX_E_DEVICE;
+    BCK(hipStreamSynchronize(b->stream));
+    for (mpx_sim *s : b->sims) {
+        mpx_status r = mpx_synchronize(s);
+        if (r != MPX_OK) return r;
+    }
+    return MPX_OK;
+}
+
+const char *mpx_batch_last_error(const mpx_batch *b) { return b ? b->err.c_str() : "null handle"; }
+
 
 } // extern "C"

@@ -382,8 +382,8 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
 
 // B^ prepass: B^n and B^* of every face of the grown face box
 template <typename T>
-__global__ void __launch_bounds__(256) k_bhat(KParams<T> p, int phase) {
-    const int4 bt = p.blocktab_ext[blockIdx.x];
+__device__ __forceinline__ void bhat_body(const KParams<T> &p, int phase, int blk) {
+    const int4 bt = p.blocktab_ext[blk];
     const int f = bt.x, c = bt.y;
     const FilmDev &F = p.films[f];
     const long long l = (long long)bt.z + threadIdx.x;
@@ -397,10 +397,22 @@ __global__ void __launch_bounds__(256) k_bhat(KParams<T> p, int phase) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase, int inc_step) {
+__global__ void __launch_bounds__(256) k_bhat(KParams<T> p, int phase) {
+    bhat_body(p, phase, blockIdx.x);
+}
+
+// batched: work[b] = (instance, block of that instance)
+template <typename T>
+__global__ void __launch_bounds__(256) k_bhat_batch(const KParams<T> *plist, const int2 *work, int phase) {
+    const int2 wk = work[blockIdx.x];
+    bhat_body(plist[wk.x], phase, wk.y);
+}
+
+template <typename T>
+__device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int inc_step, int blk) {
     __shared__ double red[256];
-    if (inc_step && blockIdx.x == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
-    const int4 bt = p.blocktab[blockIdx.x]; // film, family, first local index
+    if (inc_step && blk == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
+    const int4 bt = p.blocktab[blk]; // film, family, first local index
     const int f = bt.x, c = bt.y;
     const FilmDev &F = p.films[f];
     const long long l = (long long)bt.z + threadIdx.x;
@@ -482,7 +494,18 @@ __global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase, int inc_s
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) p.partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) p.partial[blk] = red[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase, int inc_step) {
+    film_body(p, phase, inc_step, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_film_batch(const KParams<T> *plist, const int2 *work, int phase, int inc_step) {
+    const int2 wk = work[blockIdx.x];
+    film_body(plist[wk.x], phase, inc_step, wk.y);
 }
 
 // copy the scratch of a single (bracket) half step into the state
@@ -528,9 +551,9 @@ __device__ double h_integer_time(const KParams<T> &p, int c, const int *idx) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_probes(KParams<T> p) {
+__device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
     __shared__ double red[256];
-    const ProbeDev &P = p.probes[blockIdx.x];
+    const ProbeDev &P = p.probes[pb];
     const long long step = p.step[0];
     double v[3] = {0.0, 0.0, 0.0};
     if (P.kind == 0) {
@@ -613,6 +636,17 @@ __global__ void __launch_bounds__(256) k_probes(KParams<T> p) {
         }
         if (bad) atomicOr(p.flag, 1);
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_probes(KParams<T> p) {
+    probes_body(p, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_probes_batch(const KParams<T> *plist, const int2 *work) {
+    const int2 wk = work[blockIdx.x];
+    probes_body(plist[wk.x], wk.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -771,6 +805,12 @@ __global__ void k_tick(long long *step) {
     if (threadIdx.x == 0) step[0] = step[0] + 1;
 }
 
+template <typename T>
+__global__ void k_tick_batch(const KParams<T> *plist, const int *inst, int n) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) plist[inst[q]].step[0] = plist[inst[q]].step[0] + 1;
+}
+
 hipError_t launch_tick(long long *step, hipStream_t s) {
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, step);
     return hipGetLastError();
@@ -803,11 +843,38 @@ hipError_t launch_energy(const KParams<T> &p, int nblk, double *part, double *ou
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_film_batch(const KParams<T> *plist, const int2 *work_ext, int n_ext, const int2 *work, int n,
+                             int phase, int inc, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bhat_batch<T>, dim3(n_ext), dim3(256), 0, s, plist, work_ext, phase);
+    hipLaunchKernelGGL(k_film_batch<T>, dim3(n), dim3(256), 0, s, plist, work, phase, inc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probes_batch<T>, dim3(n), dim3(256), 0, s, plist, work);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tick_batch<T>, dim3((n + 63) / 64), dim3(64), 0, s, plist, inst, n);
+    return hipGetLastError();
+}
+
 #define MPX_INSTANTIATE(T)                                                                  \
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);         \
     template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                   \
     template hipError_t launch_film<T>(const KParams<T> &, int, int, int, hipStream_t);     \
     template hipError_t launch_commit<T>(const KParams<T> &, int, hipStream_t);             \
+    template hipError_t launch_film_batch<T>(const KParams<T> *, const int2 *, int, const int2 *, int, int, int, \
+                                             hipStream_t);                                  \
+    template hipError_t launch_probes_batch<T>(const KParams<T> *, const int2 *, int, hipStream_t); \
+    template hipError_t launch_tick_batch<T>(const KParams<T> *, const int *, int, hipStream_t);   \
     template hipError_t launch_probes<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_energy<T>(const KParams<T> &, int, double *, double *, hipStream_t);
 

@@ -119,6 +119,13 @@ template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
 hipError_t launch_tick(long long *step, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_batch(const KParams<T> *plist, const int4 *work, int nwork, int variant, hipStream_t s);
+template <typename T>
+hipError_t launch_film_batch(const KParams<T> *plist, const int2 *work_ext, int n_ext, const int2 *work, int n,
+                             int phase, int inc, hipStream_t s);
+template <typename T> hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, hipStream_t s);
+template <typename T> hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hipStream_t s);
 template <typename T> hipError_t launch_commit(const KParams<T> &p, int nblk, hipStream_t s);
 template <typename T> hipError_t launch_probes(const KParams<T> &p, int nprobe, hipStream_t s);
 template <typename T>

@@ -35,7 +35,8 @@ EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "m
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
            "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
-           "mpx_last_error"]
+           "mpx_last_error", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
+           "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
 
 
 class MpxError(RuntimeError):
@@ -105,6 +106,13 @@ def load(path: str = LIB_PATH):
         "mpx_set_timing": (I32, [P, I32]),
         "mpx_kernel_time": (I32, [P, C.POINTER(D), C.POINTER(I64)]),
         "mpx_last_error": (C.c_char_p, [P]),
+        "mpx_batch_create": (I32, [C.POINTER(P), I32, C.POINTER(P)]),
+        "mpx_batch_destroy": (I32, [P]),
+        "mpx_batch_set_schedule": (I32, [P, I32, I32]),
+        "mpx_batch_set_graph_steps": (I32, [P, I32]),
+        "mpx_batch_step": (I32, [P, I64]),
+        "mpx_batch_synchronize": (I32, [P]),
+        "mpx_batch_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -293,6 +301,52 @@ class Sim:
             self._ck(self._L.mpx_film_box(self._h, f, box, C.byref(nc)), "film_box")
             out.append((tuple(int(v) for v in box), int(nc.value)))
         return out
+
+
+class Batch:
+    """Several simulations of one precision stepped together: one fused
+    stencil launch per time step covers every member's tiles.  Members keep
+    their own fields, probes and step counters; each ends bitwise equal to
+    stepping it alone.  The members must stay alive and unconfigured while
+    the batch exists."""
+
+    def __init__(self, sims):
+        self._L = load()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*(s._h.value for s in self.sims))
+        h = C.c_void_p()
+        rc = self._L.mpx_batch_create(arr, len(self.sims), C.byref(h))
+        if rc != 0:
+            raise MpxError(rc, "mpx_batch_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.mpx_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, rc, what):
+        if rc != 0:
+            raise MpxError(rc, f"{what}: {self._L.mpx_batch_last_error(self._h).decode()}")
+
+    def set_schedule(self, variant=1, kchunk=0):
+        self._ck(self._L.mpx_batch_set_schedule(self._h, int(variant), int(kchunk)), "batch_set_schedule")
+
+    def set_graph_steps(self, n):
+        self._ck(self._L.mpx_batch_set_graph_steps(self._h, int(n)), "batch_set_graph_steps")
+
+    def step(self, n):
+        self._ck(self._L.mpx_batch_step(self._h, int(n)), "batch_step")
+
+    def sync(self):
+        self._ck(self._L.mpx_batch_synchronize(self._h), "batch_synchronize")
 
 
 def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None, fused=None, kchunk=0):

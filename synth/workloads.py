@@ -246,3 +246,55 @@ def random_case(seed: int, nx=13, ny=11, nz=9, bc=(PEC,) * 6, npml=(0,) * 6, fil
     w.m_dir = (0.3, 0.1, 1.0)
     w.sources = [Source(1, (2, 2, 2, 2, 3, 1), 1e9 * np.sin(np.arange(max(nsteps, 1)) * 0.3))]
     return w
+
+
+# --------------------------------------------------------------------------
+# C3: batched bias sweep, 64 resonator + film instances of uneven size
+# --------------------------------------------------------------------------
+
+def c3_instance(nx: int, ny: int, nz: int, h_scale: float, nsteps: int) -> Workload:
+    """C2's stack scaled to (nx, ny, nz): silicon in the lower 40 % of nz, a
+    one-cell PEC layer with a centre strip 12 cells wide (gaps of 8 cells to
+    grounds that run into the y-PML), the strip a half-wave resonator of
+    0.75 nx cells between 2-cell gap capacitors, a 0.6 nx x 12 x 4 film on it,
+    PML 8 on every face, d = (20, 2, 2) um.  H0 along z is h_scale times the
+    field whose perpendicular resonance (mu0 |gamma| H0 / 2 pi, no static
+    demagnetisation) matches the resonator's half-wave estimate."""
+    d = (20e-6, 2e-6, 2e-6)
+    dt = config_dt(0.9, d)
+    npml = 8
+    ids = _empty_ids(nx, ny, nz)
+    kmet = int(0.4 * nz)
+    ids[:kmet] = 1
+    yc = ny // 2
+    sw, gw = 12, 8
+    s0, s1 = yc - sw // 2, yc + sw // 2
+    ids[kmet, : s0 - gw, :] = 2
+    ids[kmet, s1 + gw:, :] = 2
+    lres = int(0.75 * nx)
+    x0 = (nx - lres) // 2
+    ids[kmet, s0:s1, : x0 - 2] = 2
+    ids[kmet, s0:s1, x0:x0 + lres] = 2
+    ids[kmet, s0:s1, x0 + lres + 2:] = 2
+    fl = int(0.6 * nx)
+    fx0 = x0 + (lres - fl) // 2
+    ids[kmet + 1:kmet + 5, s0:s1, fx0:fx0 + fl] = 3
+    f_p = C0 / (2.0 * lres * d[0] * math.sqrt(6.35))
+    H_ac = 2.0 * math.pi * f_p / (4e-7 * math.pi * GAMMA)
+    tp = 1.0 / f_p
+    table = gaussian_pulse(nsteps, dt, 1e6, f_p, tp, 3.0 * tp)
+    srcs = [Source(1, (npml + 1, s0 - gw, kmet, 2, gw, 2), table),
+            Source(1, (npml + 1, s1, kmet, 2, gw, 2), -table)]
+    probes = [Probe("mean_m", film=0), Probe("field", EY, (x0 + 2, s0 - gw // 2, kmet + 1))]
+    return Workload(f"C3 instance {nx}x{ny}x{nz}, H0 = {h_scale:.3f} H_ac", nx, ny, nz, d, dt, 0.9,
+                    bc=(PML,) * 6, npml=(npml,) * 6, ids=ids, H0=(0.0, 0.0, h_scale * H_ac),
+                    m_dir=(0.0, 0.0, 1.0), sources=srcs, probes=probes, nsteps=nsteps)
+
+
+def c3(nsteps: int = 20000, n: int = 64, seed: int = SEED) -> List[Workload]:
+    """The bias sweep: nx = 64 + 16 U{0..8}, ny = 64 + 16 U{0..2}, nz = 64
+    from the seed; H0_i = H_ac (0.8 + 0.4 i/(n-1))."""
+    rng = np.random.default_rng(seed)
+    nxs = 64 + 16 * rng.integers(0, 9, size=n)
+    nys = 64 + 16 * rng.integers(0, 3, size=n)
+    return [c3_instance(int(nxs[i]), int(nys[i]), 64, 0.8 + 0.4 * i / max(1, n - 1), nsteps) for i in range(n)]
