@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
 // device memory; the same XCD-aware dealing over the whole work list
 template <typename T, int FROWS, int MINW>
 __global__ void __launch_bounds__(FTX *(FTY / FROWS), MINW)
-    k_fused_batch(const KParams<T> *plist, const int4 *work, int nwork) {
+    k_fused_batch(const KParams<T> *__restrict__ plist, const int4 *__restrict__ work, int nwork) {
     const int per = (nwork + 7) / 8;
     const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= nwork) return;

@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(256) k_bhat(KParams<T> p, int phase) {
 
 // batched: work[b] = (instance, block of that instance)
 template <typename T>
-__global__ void __launch_bounds__(256) k_bhat_batch(const KParams<T> *plist, const int2 *work, int phase) {
+__global__ void __launch_bounds__(256) k_bhat_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work, int phase) {
     const int2 wk = work[blockIdx.x];
     bhat_body(plist[wk.x], phase, wk.y);
 }
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(256) k_film(KParams<T> p, int phase, int inc_s
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_film_batch(const KParams<T> *plist, const int2 *work, int phase, int inc_step) {
+__global__ void __launch_bounds__(256) k_film_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work, int phase, int inc_step) {
     const int2 wk = work[blockIdx.x];
     film_body(plist[wk.x], phase, inc_step, wk.y);
 }
@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(256) k_probes(KParams<T> p) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_probes_batch(const KParams<T> *plist, const int2 *work) {
+__global__ void __launch_bounds__(256) k_probes_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work) {
     const int2 wk = work[blockIdx.x];
     probes_body(plist[wk.x], wk.y);
 }

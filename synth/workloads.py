@@ -298,3 +298,16 @@ def c3(nsteps: int = 20000, n: int = 64, seed: int = SEED) -> List[Workload]:
     nxs = 64 + 16 * rng.integers(0, 9, size=n)
     nys = 64 + 16 * rng.integers(0, 3, size=n)
     return [c3_instance(int(nxs[i]), int(nys[i]), 64, 0.8 + 0.4 * i / max(1, n - 1), nsteps) for i in range(n)]
+
+
+def scaled_drive(w: Workload, factor: float) -> Workload:
+    """The drive-power variant of a workload: every source table multiplied
+    by `factor` (the excitation-intensity sweep of the paper's nonlinear
+    spectra); all other inputs shared."""
+    import copy
+
+    out = copy.copy(w)
+    out.sources = [Source(s.comp, s.box, np.asarray(s.table) * factor) for s in w.sources]
+    out.probes = list(w.probes)
+    out.name = f"{w.name}, drive x{factor:g}"
+    return out
