@@ -52,7 +52,8 @@ def algorithmic_bytes(w, esz):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fused.hip", "device_common.h", "mpx_internal.h"):
+    for f in ("kernels.hip", "passes.hip", "fused.hip", "sweep.hip", "stencil.h", "device_common.h",
+              "mpx_internal.h"):
         with open(os.path.join(ROOT, "paper_2510_22221_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -74,13 +75,13 @@ def traffic_from_profiles(kernel, dtype):
     return None
 
 
-def run_gpu(w, precision, steps, warmup, every, fused=True):
+def run_gpu(w, precision, steps, warmup, every, schedule=0):
     import torch
     from paper_2510_22221_amd import mpx
 
     stream = torch.cuda.current_stream()
     t0 = time.time()
-    sim = mpx.from_workload(w, precision=precision, stream=stream, fused=fused)
+    sim = mpx.from_workload(w, precision=precision, stream=stream, fused=schedule)
     sim.step(1)
     sim.sync()
     log(f"  setup {time.time() - t0:.1f} s")
@@ -100,7 +101,8 @@ def run_gpu(w, precision, steps, warmup, every, fused=True):
     return sim, wall, kt
 
 
-def roofline_for(w, esz, kt, dtype_name, fused=True):
+def roofline_for(w, esz, kt, dtype_name, schedule=0):
+    fused = schedule != 0
     ab = algorithmic_bytes(w, esz)
     if fused:
         name, ms, nl = "fused", kt[0][0], kt[0][1]
@@ -123,7 +125,7 @@ def roofline_for(w, esz, kt, dtype_name, fused=True):
 def batched_sweep(steps, n_inst, variant=None, kchunk=None):
     """The bias sweep: n_inst resonator + film instances of uneven size,
     float32, stepped one after another (each with its own captured graphs)
-    and then as one batch (one fused launch per step over all instances).
+    and then as one batch (one launch per pass over all instances).
     Both runs start from the same state and the batch's results are bitwise
     those of the single runs (checked in the GPU tests); returns the
     throughput of both."""
@@ -193,7 +195,8 @@ def main():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
-    ap.add_argument("--two-pass", action="store_true", help="separate E and H passes instead of the fused pass")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="0: separate E and H/M passes (default); 1-5: fused pass variants")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
     ap.add_argument("--sweep-instances", type=int, default=64)
     args = ap.parse_args()
@@ -207,11 +210,11 @@ def main():
     w = W.c2(max(args.steps, args.f64_steps) + args.warmup + 2, nx=args.nx, ny=args.ny, nz=args.nz)
     every = args.timing_every or max(1, args.steps // 2000)
     log(f"workload {w.name}: {w.ncells} cells, FP32 {args.steps} steps (+{args.warmup} warmup)")
-    fused = not args.two_pass
-    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every, fused)
+    sched = args.schedule
+    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every, sched)
     del sim
     value = w.ncells * args.steps / wall / 1e9
-    roof = roofline_for(w, 4, kt, "f32", fused)
+    roof = roofline_for(w, 4, kt, "f32", sched)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -228,18 +231,18 @@ def main():
         "config": {"workload": f"single on-chip CPW resonator + film, {w.nx}x{w.ny}x{w.nz} cells, "
                                f"d=(45,2,2) um, PML 10, source + probes, one time step per bench step",
                    "cells": w.ncells, "precision": "f32 fields, f64 magnetisation",
-                   "schedule": "fused E + merged H/M pass" if fused else "separate E and H passes",
+                   "schedule": ("separate E and H/M passes" if sched == 0 else f"fused pass, variant {sched}"),
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
     if not args.no_f64:
         log(f"FP64 {args.f64_steps} steps")
-        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000), fused)
+        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000), sched)
         del sim
         out["secondary"] = [{"dtype": "f64", "value": round(w.ncells * args.f64_steps / wall64 / 1e9, 3),
                              "unit": "Gcell-updates/s", "steps": args.f64_steps,
                              "ms_per_step": round(wall64 / args.f64_steps * 1e3, 5),
-                             "roofline": roofline_for(w, 8, kt64, "f64", fused)}]
+                             "roofline": roofline_for(w, 8, kt64, "f64", sched)}]
     if args.sweep_steps > 0:
         log(f"batched bias sweep: {args.sweep_instances} instances, {args.sweep_steps} steps")
         out["batched_sweep"] = batched_sweep(args.sweep_steps, args.sweep_instances)

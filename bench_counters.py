@@ -9,13 +9,13 @@ Two steps (the counters need rocprofv3 as the outer process):
        rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_write> -o pmc -- \
            python3 bench_counters.py --run [--dtype f32|f64] [--steps N]
      The program runs N time steps of the resonator workload (fused pass)
-     and, after them, a plain device-to-device copy of 1 GiB (a torch copy
-     kernel) whose true traffic is known.
+     and, after them, a plain elementwise kernel (b = a * 2 over 1 GiB of
+     float32: reads 1 GiB, writes 1 GiB) whose true traffic is known.
 
   2. parse:
        python3 bench_counters.py --parse <dir_fetch> <dir_write> [--dtype f32]
      FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  Each is scaled by
-     (known copy bytes / what the same counter reads for the copy kernel), and
+     (known bytes / what the same counter reads for the calibration kernel), and
      the per-launch HBM bytes of the fused pass are written to
      profiles/traffic.json together with a hash of the kernel source, so that
      bench.py reports them only for the kernel version that was measured.
@@ -33,9 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 COPY_BYTES = 1 << 30
+KERNEL = "k_sweep"
 
 
-def run(dtype: str, steps: int, nx: int, ny: int, nz: int):
+def run(dtype: str, steps: int, nx: int, ny: int, nz: int, fused: int = 1):
     import torch
     from paper_2510_22221_amd import mpx
     from synth import workloads as W
@@ -43,16 +44,16 @@ def run(dtype: str, steps: int, nx: int, ny: int, nz: int):
     w = W.c2(steps + 4, nx=nx, ny=ny, nz=nz)
     prec = mpx.F32 if dtype == "f32" else mpx.F64
     stream = torch.cuda.current_stream()
-    sim = mpx.from_workload(w, precision=prec, stream=stream, graph_steps=0)
+    sim = mpx.from_workload(w, precision=prec, stream=stream, graph_steps=0, fused=fused)
     sim.step(steps)
     sim.sync()
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     for _ in range(3):
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
     torch.cuda.synchronize()
-    print(f"ran {steps} steps ({dtype}) and 3 copies of {COPY_BYTES} bytes", flush=True)
+    print(f"ran {steps} steps ({dtype}) and 3 elementwise passes over {COPY_BYTES} bytes", flush=True)
 
 
 def read_counters(d):
@@ -85,8 +86,8 @@ def parse(dfetch, dwrite, dtype):
     res = {}
     for label, d in (("FETCH_SIZE", dfetch), ("WRITE_SIZE", dwrite)):
         c = read_counters(d)
-        fused, nf = pick(c, lambda k: "k_fused" in k)
-        copy, nc = pick(c, lambda k: ("copy" in k.lower() or "elementwise" in k.lower()) and "k_" not in k)
+        fused, nf = pick(c, lambda k: KERNEL in k)
+        copy, nc = pick(c, lambda k: "elementwise" in k and "Mul" in k)
         scale = (COPY_BYTES / 1024.0) / copy   # counter reads KiB
         res[label] = {"fused_kib_per_dispatch": fused, "dispatches": nf, "copy_kib_per_dispatch": copy,
                       "copy_dispatches": nc, "scale": scale, "bytes_per_launch": fused * 1024.0 * scale}
@@ -113,9 +114,10 @@ def main():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
+    ap.add_argument("--fused", type=int, default=1, help="0: separate E and H passes; 1-4: fused tile variant")
     args = ap.parse_args()
     if args.run:
-        run(args.dtype, args.steps, args.nx, args.ny, args.nz)
+        run(args.dtype, args.steps, args.nx, args.ny, args.nz, args.fused)
     elif args.parse:
         parse(args.parse[0], args.parse[1], args.dtype)
     else:

@@ -217,13 +217,15 @@ mpx_status mpx_film_box(const mpx_sim *sim, int32_t film, int32_t box[6], int64_
  * kernel directly). */
 mpx_status mpx_set_graph_steps(mpx_sim *sim, int32_t steps);
 
-/* Step schedule.  fused = 1..4 (default 1): one fused stencil pass per step
- * (E step and the merged H/M half-step pair in one z-marching sweep over
- * ping-pong buffers, z-chunks of `kchunk` planes; 0 keeps the current chunk,
- * default 16); the value picks a tile variant (1: two rows per thread,
- * >= 2 waves per SIMD; 2: two rows, >= 4 waves; 3: one row, >= 2 waves;
- * 4: one row, >= 4 waves).  fused = 0: a separate E pass and H pass, in
- * place.  All give identical results. */
+/* Step schedule.  fused = 0 (default): a separate E pass and H/M pass per
+ * step, each in place with one thread per slot.  fused = 1..5: one fused
+ * stencil pass per step (the E step and the merged H/M half-step pair in one
+ * z-marching sweep over ping-pong buffers, z-chunks of `kchunk` planes; 0
+ * keeps the current chunk, default 16): 1 = register-blocked sweep (64 x 4
+ * columns per block, each thread recomputes the neighbour edges it needs);
+ * 2..5 = LDS-staged sweep over 64 x 8 tiles (2: two rows per thread, >= 2
+ * waves per SIMD; 3: two rows, >= 4 waves; 4: one row, >= 2 waves; 5: one
+ * row, >= 4 waves).  All give bitwise identical results. */
 mpx_status mpx_set_schedule(mpx_sim *sim, int32_t fused, int32_t kchunk);
 
 /* Kernel timing with HIP events on the handle's stream.  With every > 0,
@@ -248,7 +250,8 @@ const char *mpx_last_error(const mpx_sim *sim);
  * geometries (a parameter sweep).  mpx_batch_step advances every member by
  * nsteps time steps with one fused stencil launch per step covering all
  * members' tiles, and one launch each for their film half steps and probes,
- * so that small grids still fill the chip.  Each member's results are
+ * so that small grids still fill the chip (with the separate-pass schedule:
+ * one launch per pass).  Each member's results are
  * bitwise identical to stepping it alone with mpx_step under the same tile
  * variant.  Sources, probes and films of each member behave exactly as for
  * a lone handle (its probe ring and step counter advance).
@@ -265,9 +268,8 @@ typedef struct mpx_batch mpx_batch;
 mpx_status mpx_batch_create(mpx_sim *const *sims, int32_t n, mpx_batch **out);
 mpx_status mpx_batch_destroy(mpx_batch *batch);
 
-/* Tile variant 1..4 and z-chunk (0 keeps the current one) of the batched
- * fused pass; defaults are those of the first member (variant 1 if that
- * member uses the two-pass schedule). */
+/* Schedule 0..5 (as for mpx_set_schedule) and z-chunk (0 keeps the current
+ * one) of the batched step; defaults are those of the first member. */
 mpx_status mpx_batch_set_schedule(mpx_batch *batch, int32_t variant, int32_t kchunk);
 
 /* Steps per captured HIP graph (rounded up to even; 0 launches directly). */

@@ -30,4 +30,27 @@ __device__ __forceinline__ T dif(T hi, T lo, T d, T invd) {
     }
 }
 
+// value of a field at (i, j, k), folded on periodic axes; zero outside the
+// domain (the walls' unstored sites)
+template <typename T>
+__device__ __forceinline__ T ldz(const KParams<T> &p, const T *a, int i, int j, int k) {
+    int ii = fold(i, p.n[0], p.per[0]), jj = fold(j, p.n[1], p.per[1]), kk = fold(k, p.n[2], p.per[2]);
+    if (ii < 0 || jj < 0 || kk < 0) return T(0);
+    return a[p.slot(ii, jj, kk)];
+}
+
+// is the face of family c at slot idx (folded) a magnetic site of a film?
+template <typename T>
+__device__ __forceinline__ bool face_is_magnetic(const KParams<T> &p, int c, const int *idx) {
+    for (int f = 0; f < p.nfilm; f++) {
+        const FilmDev &F = p.films[f];
+        const int r0 = idx[0] - F.b0[0], r1 = idx[1] - F.b0[1], r2 = idx[2] - F.b0[2];
+        if (r0 >= 0 && r0 < F.bn[0] && r1 >= 0 && r1 < F.bn[1] && r2 >= 0 && r2 < F.bn[2]) {
+            const long long l = (long long)r0 + (long long)F.bn[0] * ((long long)r1 + (long long)F.bn[1] * r2);
+            return F.prm[(c * 3) * F.ns + l] > 0.0;
+        }
+    }
+    return false;
+}
+
 } // namespace mpx

@@ -99,14 +99,21 @@ __device__ __forceinline__ T fused_e(const KParams<T> &p, const FusedLds<T> &L, 
             ca = -(sig / 2.0 - eps / p.dt) / den;
             cb = 1.0 / den;
         } else {
-            const float se = float(A0.eps_r) + float(A1.eps_r) + float(A2.eps_r) + float(A3.eps_r);
-            const float ss = float(A0.sigma) + float(A1.sigma) + float(A2.sigma) + float(A3.sigma);
-            const float eps = float(p.eps0) * (se * 0.25f);
-            const float sig = ss * 0.25f;
-            const float ed = eps * float(p.inv_dt);
-            const float rden = 1.0f / (sig * 0.5f + ed);
-            ca = -(sig * 0.5f - ed) * rden;
-            cb = rden;
+            // float32 fields: the float64 sequence rounded once, as in the table
+            double se = 0.0, ss = 0.0;
+            se += A0.eps_r;
+            ss += A0.sigma;
+            se += A1.eps_r;
+            ss += A1.sigma;
+            se += A2.eps_r;
+            ss += A2.sigma;
+            se += A3.eps_r;
+            ss += A3.sigma;
+            const double eps = p.eps0 * (se / 4);
+            const double sig = ss / 4;
+            const double den = sig / 2.0 + eps / p.dt;
+            ca = (float)(-(sig / 2.0 - eps / p.dt) / den);
+            cb = (float)(1.0 / den);
         }
     }
     // curl H, backward differences; the LDS H tile is offset by one in x, y
@@ -202,18 +209,6 @@ __device__ __forceinline__ T fused_h(const KParams<T> &p, const FusedLds<T> &L, 
     return h;
 }
 
-template <typename T>
-__device__ __forceinline__ bool face_is_magnetic(const KParams<T> &p, int c, const int *idx) {
-    for (int f = 0; f < p.nfilm; f++) {
-        const FilmDev &F = p.films[f];
-        const int r0 = idx[0] - F.b0[0], r1 = idx[1] - F.b0[1], r2 = idx[2] - F.b0[2];
-        if (r0 >= 0 && r0 < F.bn[0] && r1 >= 0 && r1 < F.bn[1] && r2 >= 0 && r2 < F.bn[2]) {
-            const long long l = (long long)r0 + (long long)F.bn[0] * ((long long)r1 + (long long)F.bn[1] * r2);
-            return F.prm[(c * 3) * F.ns + l] > 0.0;
-        }
-    }
-    return false;
-}
 
 // FROWS rows per thread (blockDim = 64 x 8/FROWS); MINW: minimum waves per
 // SIMD the register allocation must allow

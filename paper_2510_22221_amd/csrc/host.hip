@@ -63,7 +63,7 @@ struct mpx_sim {
     void *E2[3] = {nullptr, nullptr, nullptr};
     void *H2[3] = {nullptr, nullptr, nullptr};
     int parity = 0;
-    int fused = 1;
+    int fused = 0; // separate passes (the fastest schedule measured on gfx950)
     int kchunk = 16;
     void *d_coef = nullptr;
     // materials
@@ -71,6 +71,7 @@ struct mpx_sim {
     std::vector<mpx_material> mats;
     std::vector<uint8_t> ids; // natural cell order
     uint8_t *d_id = nullptr;
+    uint8_t *d_cls = nullptr; // per slot: the shared id of the 8 cells around it, or 255
     MatDev *d_mat = nullptr;
     // PML
     int nlo[3] = {0, 0, 0}, nhi[3] = {0, 0, 0};
@@ -92,6 +93,7 @@ struct mpx_sim {
     std::vector<SrcHost> srcs;
     std::vector<ProbeHost> probes;
     ProbeDev *d_probes = nullptr;
+    SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     long long *d_step = nullptr;
     int *d_flag = nullptr;
     long long step = 0;
@@ -241,6 +243,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.kf = MU0 * s->dt / 4.0;
     p.dV = s->d[0] * s->d[1] * s->d[2];
     p.id = s->d_id;
+    p.cls = s->d_cls;
     p.mat = s->d_mat;
     p.coef = (const CoefDev<T> *)s->d_coef;
     p.nfilm = (int)s->films.size();
@@ -251,6 +254,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.partial = s->d_partial;
     p.nsrc = (int)s->srcs.size();
     for (int i = 0; i < p.nsrc; i++) p.src[i] = s->srcs[i].dev;
+    p.srcs = s->d_srcs;
     p.probes = s->d_probes;
     p.step = s->d_step;
     p.flag = s->d_flag;
@@ -450,7 +454,10 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
         fill_params<T>(s, pa, MODE_FUSED, par);
         fill_params<T>(s, pb, MODE_AFTER_FUSED, par);
         if ((r = rec(0, 0)) != MPX_OK) return r;
-        CK(launch_fused<T>(pa, s->kchunk, s->fused, st));
+        if (s->fused == 1)
+            CK(launch_sweep<T>(pa, s->kchunk, st));
+        else
+            CK(launch_fused<T>(pa, s->kchunk, s->fused - 1, st));
         if ((r = rec(0, 1)) != MPX_OK) return r;
         if ((r = rec(1, 0)) != MPX_OK) return r; // no second stencil kernel
         if ((r = rec(1, 1)) != MPX_OK) return r;
@@ -597,8 +604,10 @@ struct mpx_batch {
     size_t psize = 0;
     void *d_pa[2] = {nullptr, nullptr}; // fused-pass parameters, flip 0 / 1
     void *d_pb[2] = {nullptr, nullptr}; // film / probe parameters after it
-    int4 *d_work = nullptr;
+    int4 *d_work = nullptr; // fused variants: (instance, tile, z-chunk)
     int nwork = 0;
+    int2 *d_work2 = nullptr; // separate passes: (instance, tile)
+    int nwork2 = 0;
     int2 *d_wfilm = nullptr, *d_wext = nullptr, *d_wprobe = nullptr;
     int nwfilm = 0, nwext = 0, nwprobe = 0;
     int *d_tick = nullptr;
@@ -636,29 +645,36 @@ void batch_drop_graph(mpx_batch *b) {
 
 template <typename T>
 mpx_status batch_tables(mpx_batch *b) {
-    // fused tiles: instance by instance, tiles in the single-instance order
+    // tiles instance by instance, in the single-instance order
     std::vector<int4> work;
-    std::vector<int2> wfilm, wext, wprobe;
+    std::vector<int2> work2, wfilm, wext, wprobe;
     std::vector<int> tick;
     for (int q = 0; q < (int)b->sims.size(); q++) {
         const mpx_sim *s = b->sims[q];
-        const int nxt = (s->n[0] + 63) / 64, nyt = (s->n[1] + 7) / 8;
-        const int nzc = (s->n[2] + b->kchunk - 1) / b->kchunk;
-        for (int t = 0; t < nxt * nyt * nzc; t++) work.push_back(make_int4(q, t, b->kchunk, 0));
+        if (b->variant == 0) {
+            for (int t = 0; t < pass_tiles(s->n); t++) work2.push_back(make_int2(q, t));
+        } else {
+            // tiles of 64 x 4 columns (register sweep) or 64 x 8 (LDS-staged)
+            const int nxt = (s->n[0] + 63) / 64, nyt = b->variant == 1 ? (s->n[1] + 3) / 4 : (s->n[1] + 7) / 8;
+            const int nzc = (s->n[2] + b->kchunk - 1) / b->kchunk;
+            for (int t = 0; t < nxt * nyt * nzc; t++) work.push_back(make_int4(q, t, b->kchunk, 0));
+        }
         for (int k = 0; k < s->nblk; k++) wfilm.push_back(make_int2(q, k));
         for (int k = 0; k < s->nblk_ext; k++) wext.push_back(make_int2(q, k));
         for (int k = 0; k < (int)s->probes.size(); k++) wprobe.push_back(make_int2(q, k));
         if (s->nblk == 0) tick.push_back(q);
     }
     (void)hipFree(b->d_work);
+    (void)hipFree(b->d_work2);
     (void)hipFree(b->d_wfilm);
     (void)hipFree(b->d_wext);
     (void)hipFree(b->d_wprobe);
     (void)hipFree(b->d_tick);
     b->d_work = nullptr;
-    b->d_wfilm = b->d_wext = b->d_wprobe = nullptr;
+    b->d_work2 = b->d_wfilm = b->d_wext = b->d_wprobe = nullptr;
     b->d_tick = nullptr;
     b->nwork = (int)work.size();
+    b->nwork2 = (int)work2.size();
     b->nwfilm = (int)wfilm.size();
     b->nwext = (int)wext.size();
     b->nwprobe = (int)wprobe.size();
@@ -671,6 +687,7 @@ mpx_status batch_tables(mpx_batch *b) {
         return MPX_OK;
     };
     mpx_status r;
+    if ((r = up2(&b->d_work2, work2)) != MPX_OK) return r;
     if ((r = up2(&b->d_wfilm, wfilm)) != MPX_OK) return r;
     if ((r = up2(&b->d_wext, wext)) != MPX_OK) return r;
     if ((r = up2(&b->d_wprobe, wprobe)) != MPX_OK) return r;
@@ -679,7 +696,8 @@ mpx_status batch_tables(mpx_batch *b) {
     return MPX_OK;
 }
 
-// the instances' parameters at their current parity (flip 0) and flipped
+// the instances' parameters at their current parity (flip 0) and flipped;
+// the separate passes work in place (flip 0 only)
 template <typename T>
 mpx_status batch_params(mpx_batch *b) {
     const size_t n = b->sims.size();
@@ -687,8 +705,13 @@ mpx_status batch_params(mpx_batch *b) {
     for (int f = 0; f < 2; f++) {
         for (size_t q = 0; q < n; q++) {
             const mpx_sim *s = b->sims[q];
-            fill_params<T>(s, pa[q], MODE_FUSED, s->parity ^ f);
-            fill_params<T>(s, pb[q], MODE_AFTER_FUSED, s->parity ^ f);
+            if (b->variant == 0) {
+                fill_params<T>(s, pa[q], MODE_INPLACE, s->parity);
+                pb[q] = pa[q];
+            } else {
+                fill_params<T>(s, pa[q], MODE_FUSED, s->parity ^ f);
+                fill_params<T>(s, pb[q], MODE_AFTER_FUSED, s->parity ^ f);
+            }
         }
         BCK(hipMemcpyAsync(b->d_pa[f], pa.data(), n * sizeof(KParams<T>), hipMemcpyHostToDevice, b->stream));
         BCK(hipMemcpyAsync(b->d_pb[f], pb.data(), n * sizeof(KParams<T>), hipMemcpyHostToDevice, b->stream));
@@ -703,7 +726,20 @@ mpx_status batch_body(mpx_batch *b, int f) {
     const KParams<T> *pa = (const KParams<T> *)b->d_pa[f];
     const KParams<T> *pb = (const KParams<T> *)b->d_pb[f];
     hipStream_t st = b->stream;
-    BCK(launch_fused_batch<T>(pa, b->d_work, b->nwork, b->variant, st));
+    if (b->variant == 0) {
+        // E pass, film half steps and probes, then the bulk H pass (which
+        // moves every instance's step counter)
+        BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, st));
+        BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
+        BCK(launch_probes_batch<T>(pa, b->d_wprobe, b->nwprobe, st));
+        BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 0, st));
+        BCK(launch_hbulk_batch<T>(pa, b->d_work2, b->nwork2, 2, 1, st));
+        return MPX_OK;
+    }
+    if (b->variant == 1)
+        BCK(launch_sweep_batch<T>(pa, b->d_work, b->nwork, st));
+    else
+        BCK(launch_fused_batch<T>(pa, b->d_work, b->nwork, b->variant - 1, st));
     BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
     BCK(launch_probes_batch<T>(pb, b->d_wprobe, b->nwprobe, st));
     BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 1, st));
@@ -731,7 +767,7 @@ mpx_status batch_steps(mpx_batch *b, long long nsteps) {
         if (!b->graph_valid) {
             BCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             for (int n = 0; n < G; n++) {
-                r = batch_body<T>(b, n & 1);
+                r = batch_body<T>(b, b->variant == 0 ? 0 : (n & 1));
                 if (r != MPX_OK) {
                     hipGraph_t g;
                     (void)hipStreamEndCapture(st, &g);
@@ -749,10 +785,11 @@ mpx_status batch_steps(mpx_batch *b, long long nsteps) {
     }
     for (long long n = 0; n < body; n++) {
         if ((r = batch_body<T>(b, f)) != MPX_OK) return r;
-        f ^= 1;
+        if (b->variant != 0) f ^= 1;
     }
-    // the flips of the body: every instance changed parity (nsteps - 1) times
-    for (mpx_sim *s : b->sims) s->parity ^= (int)((nsteps - 1) & 1);
+    // the flips of the fused body: every instance changed parity (nsteps - 1) times
+    if (b->variant != 0)
+        for (mpx_sim *s : b->sims) s->parity ^= (int)((nsteps - 1) & 1);
     for (mpx_sim *s : b->sims) {
         if ((r = run_last<T>(s, s->parity, st)) != MPX_OK) {
             b->dead = true;
@@ -839,6 +876,8 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
         CK(hipMalloc(&s->d_coef, 256 * (prec == MPX_F64 ? sizeof(CoefDev<double>) : sizeof(CoefDev<float>))));
         CK(hipMalloc(&s->d_id, s->nslot));
         CK(hipMemset(s->d_id, 0, s->nslot));
+        CK(hipMalloc(&s->d_cls, s->nslot));
+        CK(hipMemset(s->d_cls, 0, s->nslot));
         CK(hipMalloc(&s->d_mat, 256 * sizeof(MatDev)));
         CK(hipMemset(s->d_mat, 0, 256 * sizeof(MatDev)));
         CK(hipMalloc(&s->d_step, sizeof(long long)));
@@ -882,7 +921,9 @@ mpx_status mpx_destroy(mpx_sim *s) {
     for (auto &src : s->srcs) (void)hipFree(src.table);
     for (auto &pr : s->probes) (void)hipFree(pr.dev.data);
     (void)hipFree(s->d_probes);
+    (void)hipFree(s->d_srcs);
     (void)hipFree(s->d_id);
+    (void)hipFree(s->d_cls);
     (void)hipFree(s->d_mat);
     (void)hipFree(s->d_step);
     (void)hipFree(s->d_flag);
@@ -992,6 +1033,8 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             memcpy(&slots[(size_t)s->px * (j + (size_t)s->n[1] * k)], &ids[(size_t)s->n[0] * (j + (size_t)s->n[1] * k)],
                    s->n[0]);
     CK(hipMemcpy(s->d_id, slots.data(), s->nslot, hipMemcpyHostToDevice));
+    CK(launch_classify(s->d_id, s->d_cls, s->n, s->per, s->px, s->stream));
+    CK(hipStreamSynchronize(s->stream));
     std::vector<int4> bt, bte;
     std::vector<FilmDev> fd;
     for (int fi = 0; fi < (int)s->films.size(); fi++) {
@@ -1131,6 +1174,14 @@ mpx_status mpx_add_source(mpx_sim *s, const mpx_source_desc *src, int32_t *id) {
         CK(hipMemcpy(h.table, src->table, src->n_table * sizeof(double), hipMemcpyHostToDevice));
     h.dev.table = h.table;
     s->srcs.push_back(h);
+    {
+        std::vector<SrcDev> v;
+        for (auto &x : s->srcs) v.push_back(x.dev);
+        (void)hipFree(s->d_srcs);
+        s->d_srcs = nullptr;
+        CK(hipMalloc(&s->d_srcs, v.size() * sizeof(SrcDev)));
+        CK(hipMemcpy(s->d_srcs, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice));
+    }
     drop_graph(s);
     if (id) *id = (int32_t)s->srcs.size() - 1;
     return MPX_OK;
@@ -1461,7 +1512,7 @@ mpx_status mpx_kernel_time(mpx_sim *s, double *avg_ms, int64_t *launches) {
 mpx_status mpx_set_schedule(mpx_sim *s, int32_t fused, int32_t kchunk) {
     if (!s || kchunk < 0) return MPX_E_INVALID;
     drop_graph(s);
-    if (fused < 0 || fused > 4) return MPX_E_INVALID;
+    if (fused < 0 || fused > 5) return MPX_E_INVALID;
     s->fused = fused;
     if (kchunk > 0) s->kchunk = kchunk;
     return MPX_OK;
@@ -1484,7 +1535,7 @@ mpx_status mpx_batch_create(mpx_sim *const *sims, int32_t n, mpx_batch **out) {
     b->prec = sims[0]->prec;
     b->device = sims[0]->device;
     b->stream = sims[0]->stream;
-    b->variant = sims[0]->fused ? sims[0]->fused : 1;
+    b->variant = sims[0]->fused;
     b->kchunk = sims[0]->kchunk;
     (void)hipSetDevice(b->device);
     b->psize = b->prec == MPX_F64 ? sizeof(KParams<double>) : sizeof(KParams<float>);
@@ -1516,6 +1567,7 @@ mpx_status mpx_batch_destroy(mpx_batch *b) {
         (void)hipFree(b->d_pb[f]);
     }
     (void)hipFree(b->d_work);
+    (void)hipFree(b->d_work2);
     (void)hipFree(b->d_wfilm);
     (void)hipFree(b->d_wext);
     (void)hipFree(b->d_wprobe);
@@ -1525,14 +1577,13 @@ mpx_status mpx_batch_destroy(mpx_batch *b) {
 }
 
 mpx_status mpx_batch_set_schedule(mpx_batch *b, int32_t variant, int32_t kchunk) {
-    if (!b || variant < 1 || variant > 4 || kchunk < 0) return MPX_E_INVALID;
+    if (!b || variant < 0 || variant > 5 || kchunk < 0) return MPX_E_INVALID;
     (void)hipSetDevice(b->device);
     batch_drop_graph(b);
+    const bool retile = variant != b->variant || (kchunk > 0 && kchunk != b->kchunk);
     b->variant = variant;
-    if (kchunk > 0 && kchunk != b->kchunk) {
-        b->kchunk = kchunk;
-        return b->prec == MPX_F64 ? batch_tables<double>(b) : batch_tables<float>(b);
-    }
+    if (kchunk > 0) b->kchunk = kchunk;
+    if (retile) return b->prec == MPX_F64 ? batch_tables<double>(b) : batch_tables<float>(b);
     return MPX_OK;
 }
 

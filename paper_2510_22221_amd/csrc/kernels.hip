@@ -23,13 +23,6 @@
 
 namespace mpx {
 
-template <typename T>
-__device__ __forceinline__ T ldz(const KParams<T> &p, const T *a, int i, int j, int k) {
-    int ii = fold(i, p.n[0], p.per[0]), jj = fold(j, p.n[1], p.per[1]), kk = fold(k, p.n[2], p.per[2]);
-    if (ii < 0 || jj < 0 || kk < 0) return T(0);
-    return a[p.slot(ii, jj, kk)];
-}
-
 __device__ __forceinline__ int cell_id(const int *n, const int *per, int px, const uint8_t *id, int i, int j,
                                        int k) {
     int ii = fold(i, n[0], per[0]), jj = fold(j, n[1], per[1]), kk = fold(k, n[2], per[2]);
@@ -53,229 +46,6 @@ __device__ __forceinline__ int film_of_site(const KParams<T> &p, int c, const in
         }
     }
     return -1;
-}
-
-// ---------------------------------------------------------------------------
-// Two-pass schedule: a bulk H/M pass for non-magnetic faces and a separate E
-// pass, both in place, one thread per (i, j, k) slot and all three
-// components unrolled at compile time.
-// ---------------------------------------------------------------------------
-
-// slot of the +1 / -1 neighbour along axis A (wrapping on a periodic axis);
-// -1 when it lies outside the domain
-template <typename T, int A>
-__device__ __forceinline__ long long nb_up(const KParams<T> &p, const int *idx, long long q) {
-    if (idx[A] + 1 < p.n[A]) return q + (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
-    if (!p.per[A]) return -1;
-    return q - (long long)(p.n[A] - 1) * (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
-}
-
-template <typename T, int A>
-__device__ __forceinline__ long long nb_dn(const KParams<T> &p, const int *idx, long long q) {
-    if (idx[A] > 0) return q - (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
-    if (!p.per[A]) return -1;
-    return q + (long long)(p.n[A] - 1) * (A == 0 ? 1LL : A == 1 ? (long long)p.px : (long long)p.px * p.n[1]);
-}
-
-template <typename T>
-__device__ __forceinline__ T ldq(const T *a, long long q) {
-    return q >= 0 ? a[q] : T(0);
-}
-
-template <typename T>
-__device__ __forceinline__ bool slab(const KParams<T> &p, int a, int x) {
-    return x < p.nlo[a] || x >= p.n[a] - p.nhi[a];
-}
-
-// block-uniform: does the (x, y) tile of this block at plane k touch a CPML
-// slab / a film's face box?
-template <typename T>
-__device__ __forceinline__ void tile_flags(const KParams<T> &p, int i0, int j0, int tx, int ty, int k, bool &tpml,
-                                           bool &tfilm) {
-    const int lo[3] = {i0, j0, k}, hi[3] = {i0 + tx - 1, j0 + ty - 1, k};
-    tpml = false;
-    for (int a = 0; a < 3; a++) {
-        if (p.nlo[a] > 0 && lo[a] < p.nlo[a]) tpml = true;
-        if (p.nhi[a] > 0 && hi[a] >= p.n[a] - p.nhi[a]) tpml = true;
-    }
-    tfilm = false;
-    for (int f = 0; f < p.nfilm; f++) {
-        const FilmDev &F = p.films[f];
-        bool in = true;
-        for (int a = 0; a < 3; a++)
-            if (F.b0[a] + F.bn[a] <= lo[a] || F.b0[a] > hi[a]) in = false;
-        if (in) tfilm = true;
-    }
-}
-
-template <typename T, int NHALF, int C>
-__device__ __forceinline__ void hbulk_comp(const KParams<T> &p, const int *idx, long long q, bool tpml, bool tfilm) {
-    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-    if (tfilm && film_of_site(p, C, idx) >= 0) return;
-    const T e2a = p.E[C2][q];
-    const T e2b = ldq(p.E[C2], nb_up<T, C1>(p, idx, q));
-    const T e1a = p.E[C1][q];
-    const T e1b = ldq(p.E[C1], nb_up<T, C2>(p, idx, q));
-    const T d1r = dif(e2b, e2a, p.dT[C1], p.invd[C1]);
-    const T d2r = dif(e1b, e1a, p.dT[C2], p.invd[C2]);
-    // H_C sits at half positions along C1 and C2
-    const int a1 = idx[C1], a2 = idx[C2];
-    bool s1 = false, s2 = false;
-    long long q1 = 0, q2 = 0;
-    T ps1 = T(0), ps2 = T(0);
-    if (tpml) {
-        s1 = p.psiH[C][C1] && slab(p, C1, a1);
-        s2 = p.psiH[C][C2] && slab(p, C2, a2);
-        if (s1) {
-            q1 = p.psi_index(C1, idx);
-            ps1 = p.psiH[C][C1][q1];
-        }
-        if (s2) {
-            q2 = p.psi_index(C2, idx);
-            ps2 = p.psiH[C][C2][q2];
-        }
-    }
-    T h = p.H[C][q];
-#pragma unroll
-    for (int hs = 0; hs < NHALF; hs++) {
-        T d1 = d1r, d2 = d2r;
-        if (s1) {
-            ps1 = p.bH[C1][a1] * ps1 + p.cH[C1][a1] * d1;
-            d1 += ps1;
-        }
-        if (s2) {
-            ps2 = p.bH[C2][a2] * ps2 + p.cH[C2][a2] * d2;
-            d2 += ps2;
-        }
-        h = h - p.hc * (d1 - d2);
-    }
-    p.H[C][q] = h;
-    if (s1) p.psiH[C][C1][q1] = ps1;
-    if (s2) p.psiH[C][C2][q2] = ps2;
-}
-
-// NHALF consecutive half steps with the same E (1 = a bracket half step,
-// 2 = the merged pair around an integer time)
-template <typename T, int NHALF>
-__global__ void __launch_bounds__(256) k_hbulk(KParams<T> p, int inc_step) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (inc_step && i == 0 && j == 0 && k == 0) p.step[0] = p.step[0] + 1;
-    bool tpml, tfilm;
-    tile_flags(p, blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockDim.x, blockDim.y, k, tpml, tfilm);
-    if (i >= p.n[0] || j >= p.n[1]) return;
-    const long long q = p.slot(i, j, k);
-    const int idx[3] = {i, j, k};
-    hbulk_comp<T, NHALF, 0>(p, idx, q, tpml, tfilm);
-    hbulk_comp<T, NHALF, 1>(p, idx, q, tpml, tfilm);
-    hbulk_comp<T, NHALF, 2>(p, idx, q, tpml, tfilm);
-}
-
-// E update of component C at slot q; the coefficient table of single-id
-// edges is in LDS
-template <typename T, int C>
-__device__ __forceinline__ void epass_comp(const KParams<T> &p, const int *idx, long long q, bool tpml, long long step,
-                                           const T *sca, const T *scb, const uint8_t *spec) {
-    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-    // tangential to a non-periodic wall: held at zero
-    if ((!p.per[C1] && idx[C1] == 0) || (!p.per[C2] && idx[C2] == 0)) return;
-    const long long qd1 = nb_dn<T, C1>(p, idx, q), qd2 = nb_dn<T, C2>(p, idx, q);
-    // the four cells sharing the edge, (C1, C2) offsets (-1,-1),(-1,0),(0,-1),(0,0)
-    const long long qd12 = qd1 >= 0 ? nb_dn<T, C2>(p, idx, qd1) : -1;
-    const int m0 = p.id[qd12], m1 = p.id[qd1], m2 = p.id[qd2], m3 = p.id[q];
-    T ca, cb;
-    if (m0 == m1 && m0 == m2 && m0 == m3) {
-        if (spec[m0]) return;
-        ca = sca[m0];
-        cb = scb[m0];
-    } else {
-        const MatDev &A0 = p.mat[m0], &A1 = p.mat[m1], &A2 = p.mat[m2], &A3 = p.mat[m3];
-        if (A0.is_pec || A1.is_pec || A2.is_pec || A3.is_pec) return;
-        if constexpr (sizeof(T) == 8) {
-            double se = 0.0, ss = 0.0;
-            se += A0.eps_r;
-            ss += A0.sigma;
-            se += A1.eps_r;
-            ss += A1.sigma;
-            se += A2.eps_r;
-            ss += A2.sigma;
-            se += A3.eps_r;
-            ss += A3.sigma;
-            const double eps = p.eps0 * (se / 4);
-            const double sig = ss / 4;
-            const double den = sig / 2.0 + eps / p.dt;
-            ca = -(sig / 2.0 - eps / p.dt) / den;
-            cb = 1.0 / den;
-        } else {
-            const float se = float(A0.eps_r) + float(A1.eps_r) + float(A2.eps_r) + float(A3.eps_r);
-            const float ss = float(A0.sigma) + float(A1.sigma) + float(A2.sigma) + float(A3.sigma);
-            const float eps = float(p.eps0) * (se * 0.25f);
-            const float sig = ss * 0.25f;
-            const float ed = eps * float(p.inv_dt);
-            const float rden = 1.0f / (sig * 0.5f + ed);
-            ca = -(sig * 0.5f - ed) * rden;
-            cb = rden;
-        }
-    }
-    const T h2a = p.H[C2][q];
-    const T h2b = ldq(p.H[C2], qd1);
-    const T h1a = p.H[C1][q];
-    const T h1b = ldq(p.H[C1], qd2);
-    T d1 = dif(h2a, h2b, p.dT[C1], p.invd[C1]);
-    T d2 = dif(h1a, h1b, p.dT[C2], p.invd[C2]);
-    if (tpml) {
-        // E_C sits at integer positions along C1 and C2
-        const int a1 = idx[C1], a2 = idx[C2];
-        if (p.psiE[C][C1] && slab(p, C1, a1)) {
-            const long long qq = p.psi_index(C1, idx);
-            const T ps = p.bE[C1][a1] * p.psiE[C][C1][qq] + p.cE[C1][a1] * d1;
-            p.psiE[C][C1][qq] = ps;
-            d1 += ps;
-        }
-        if (p.psiE[C][C2] && slab(p, C2, a2)) {
-            const long long qq = p.psi_index(C2, idx);
-            const T ps = p.bE[C2][a2] * p.psiE[C][C2][qq] + p.cE[C2][a2] * d2;
-            p.psiE[C][C2][qq] = ps;
-            d2 += ps;
-        }
-    }
-    double J = 0.0;
-    for (int s = 0; s < p.nsrc; s++) {
-        const SrcDev &S = p.src[s];
-        if (S.comp != C) continue;
-        if (idx[0] < S.box[0] || idx[0] >= S.box[0] + S.box[3] || idx[1] < S.box[1] || idx[1] >= S.box[1] + S.box[4] ||
-            idx[2] < S.box[2] || idx[2] >= S.box[2] + S.box[5])
-            continue;
-        if (step < S.n) J += S.table[step];
-    }
-    p.E[C][q] = ca * p.E[C][q] + cb * ((d1 - d2) - T(J));
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_epass(KParams<T> p) {
-    __shared__ T sca[256], scb[256];
-    __shared__ uint8_t spec[256];
-    const int t = threadIdx.x + blockDim.x * threadIdx.y;
-    {
-        const CoefDev<T> cf = p.coef[t];
-        sca[t] = cf.ca;
-        scb[t] = cf.cb;
-        spec[t] = (uint8_t)cf.pec;
-    }
-    __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    bool tpml, tfilm;
-    tile_flags(p, blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockDim.x, blockDim.y, k, tpml, tfilm);
-    if (i >= p.n[0] || j >= p.n[1]) return;
-    const long long q = p.slot(i, j, k);
-    const int idx[3] = {i, j, k};
-    const long long step = p.step[0];
-    epass_comp<T, 0>(p, idx, q, tpml, step, sca, scb, spec);
-    epass_comp<T, 1>(p, idx, q, tpml, step, sca, scb, spec);
-    epass_comp<T, 2>(p, idx, q, tpml, step, sca, scb, spec);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,23 +547,6 @@ __global__ void k_sum(const double *part, long long n, double *out) {
 // host-side launchers (explicit instantiation for float and double)
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s) {
-    dim3 blk(64, 4, 1), grd((p.n[0] + 63) / 64, (p.n[1] + 3) / 4, p.n[2]);
-    if (nhalf == 2)
-        k_hbulk<T, 2><<<grd, blk, 0, s>>>(p, inc);
-    else
-        k_hbulk<T, 1><<<grd, blk, 0, s>>>(p, inc);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_epass(const KParams<T> &p, hipStream_t s) {
-    dim3 blk(64, 4, 1), grd((p.n[0] + 63) / 64, (p.n[1] + 3) / 4, p.n[2]);
-    hipLaunchKernelGGL(k_epass<T>, grd, blk, 0, s, p);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s) {
     if (nblk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bhat<T>, dim3(p.nblk_ext), dim3(256), 0, s, p, phase);
@@ -867,8 +620,6 @@ hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hi
 }
 
 #define MPX_INSTANTIATE(T)                                                                  \
-    template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);         \
-    template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                   \
     template hipError_t launch_film<T>(const KParams<T> &, int, int, int, hipStream_t);     \
     template hipError_t launch_commit<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_film_batch<T>(const KParams<T> *, const int2 *, int, const int2 *, int, int, int, \

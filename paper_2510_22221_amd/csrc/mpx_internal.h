@@ -80,6 +80,7 @@ struct KParams {
     T *psiEb[3][3];
     const CoefDev<T> *coef;
     const uint8_t *id;
+    const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
     const MatDev *mat;
     int nlo[3], nhi[3];
     const T *bE[3];
@@ -96,6 +97,7 @@ struct KParams {
     double *partial;
     int nsrc;
     SrcDev src[kMaxSources];
+    const SrcDev *srcs; // the same sources in device memory
     const ProbeDev *probes;
     long long *step;
     int *flag;
@@ -116,8 +118,19 @@ struct KParams {
 
 template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s);
 template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
+template <typename T>
+hipError_t launch_epass_batch(const KParams<T> *plist, const int2 *work, int nwork, hipStream_t s);
+template <typename T>
+hipError_t launch_hbulk_batch(const KParams<T> *plist, const int2 *work, int nwork, int nhalf, int inc,
+                              hipStream_t s);
+int pass_tiles(const int *n);
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
+template <typename T> hipError_t launch_sweep(const KParams<T> &p, int kchunk, hipStream_t s);
+template <typename T>
+hipError_t launch_sweep_batch(const KParams<T> *plist, const int4 *work, int nwork, hipStream_t s);
+int sweep_tiles(const int *n, int kchunk);
+hipError_t launch_classify(const uint8_t *id, uint8_t *cls, const int *n, const int *per, int px, hipStream_t s);
 hipError_t launch_tick(long long *step, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_batch(const KParams<T> *plist, const int4 *work, int nwork, int variant, hipStream_t s);

@@ -219,8 +219,8 @@ class Sim:
         self._ck(self._L.mpx_synchronize(self._h), "synchronize")
 
     def set_schedule(self, fused=True, kchunk=0):
-        """fused: False/0 = separate E and H passes; True/1..4 = fused pass
-        (the integer picks the tile variant)."""
+        """fused: False/0 = separate E and H passes (the default); True/1 =
+        register-blocked fused sweep; 2..5 = LDS-staged fused tile variants."""
         v = int(fused) if not isinstance(fused, bool) else (1 if fused else 0)
         self._ck(self._L.mpx_set_schedule(self._h, v, int(kchunk)), "set_schedule")
 
@@ -336,7 +336,8 @@ class Batch:
         if rc != 0:
             raise MpxError(rc, f"{what}: {self._L.mpx_batch_last_error(self._h).decode()}")
 
-    def set_schedule(self, variant=1, kchunk=0):
+    def set_schedule(self, variant=0, kchunk=0):
+        """0: separate passes; 1..5: fused variants (as for Sim)."""
         self._ck(self._L.mpx_batch_set_schedule(self._h, int(variant), int(kchunk)), "batch_set_schedule")
 
     def set_graph_steps(self, n):

@@ -1,8 +1,8 @@
 """Schedule autotuner for the fused step pass.
 
-The fused pass has four tile variants (rows per thread x minimum waves per
-SIMD) and a z-chunk length; which is fastest depends on the grid shape, the
-share of CPML and film tiles, and the precision.  ``tune`` builds scratch
+A step runs as two separate passes (schedule 0) or as one fused pass in one
+of five tile variants with a z-chunk length; which is fastest depends on
+the grid shape, the share of CPML and film tiles, and the precision.  ``tune`` builds scratch
 simulations of the caller's workload (the caller's own handles are never
 stepped), times every candidate with captured graphs, and caches the winner
 in a JSON file keyed by grid, boundary and precision.  All candidates give
@@ -19,14 +19,14 @@ import numpy as np
 
 from . import mpx
 
-VARIANTS = (1, 2, 3, 4)
+VARIANTS = (0, 1, 2, 3, 4, 5)
 KCHUNKS = (8, 16, 32)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def candidates(nz: int) -> List[Tuple[int, int]]:
-    out = []
-    for v in VARIANTS:
+    out = [(0, 16)]  # the separate passes have no z-chunk
+    for v in VARIANTS[1:]:
         for kc in KCHUNKS:
             if kc <= max(8, nz):
                 out.append((v, kc))

@@ -39,8 +39,8 @@ def state(sim, w):
     return out
 
 
-@pytest.mark.parametrize("prec,variant,kchunk", [(mpx.F64, 1, 16), (mpx.F32, 1, 16), (mpx.F64, 2, 5),
-                                                 (mpx.F32, 3, 7)])
+@pytest.mark.parametrize("prec,variant,kchunk", [(mpx.F64, 0, 16), (mpx.F32, 0, 16), (mpx.F64, 1, 16),
+                                                 (mpx.F32, 1, 16), (mpx.F64, 2, 5), (mpx.F32, 3, 7)])
 def test_batch_bitwise_equals_single(prec, variant, kchunk):
     nsteps = sum(CALLS) + 2
     ws = members(nsteps)
