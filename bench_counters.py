@@ -8,15 +8,16 @@ Two steps (the counters need rocprofv3 as the outer process):
            python3 bench_counters.py --run [--dtype f32|f64] [--steps N]
        rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_write> -o pmc -- \
            python3 bench_counters.py --run [--dtype f32|f64] [--steps N]
-     The program runs N time steps of the resonator workload (fused pass)
-     and, after them, a plain elementwise kernel (b = a * 2 over 1 GiB of
+     The program runs N time steps of the resonator workload (schedule
+     --fused, default 0: the separate E and H/M passes) and, after them, a
+     plain elementwise kernel (b = a * 2 over 1 GiB of
      float32: reads 1 GiB, writes 1 GiB) whose true traffic is known.
 
   2. parse:
        python3 bench_counters.py --parse <dir_fetch> <dir_write> [--dtype f32]
      FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  Each is scaled by
      (known bytes / what the same counter reads for the calibration kernel), and
-     the per-launch HBM bytes of the fused pass are written to
+     the per-launch HBM bytes of each stencil kernel found are written to
      profiles/traffic.json together with a hash of the kernel source, so that
      bench.py reports them only for the kernel version that was measured.
 """
@@ -33,10 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 COPY_BYTES = 1 << 30
-KERNEL = "k_sweep"
 
 
-def run(dtype: str, steps: int, nx: int, ny: int, nz: int, fused: int = 1):
+def run(dtype: str, steps: int, nx: int, ny: int, nz: int, fused: int = 0):
     import torch
     from paper_2510_22221_amd import mpx
     from synth import workloads as W
@@ -78,31 +78,46 @@ def pick(counters, key):
     return sum(vals) / len(vals), len(vals)
 
 
+# kernels whose traffic is recorded: the bench's roofline key and a
+# predicate on the rocprofv3 kernel name
+KERNELS = {"e_pass": lambda k: "k_epass<" in k and "batch" not in k,
+           "h_pass": lambda k: "k_hbulk<" in k and ", 2>" in k and "batch" not in k,
+           "fused": lambda k: ("k_sweep<" in k or "k_fused<" in k) and "batch" not in k}
+
+
 def parse(dfetch, dwrite, dtype):
     import bench
 
     from synth import workloads as W
 
-    res = {}
-    for label, d in (("FETCH_SIZE", dfetch), ("WRITE_SIZE", dwrite)):
-        c = read_counters(d)
-        fused, nf = pick(c, lambda k: KERNEL in k)
-        copy, nc = pick(c, lambda k: "elementwise" in k and "Mul" in k)
-        scale = (COPY_BYTES / 1024.0) / copy   # counter reads KiB
-        res[label] = {"fused_kib_per_dispatch": fused, "dispatches": nf, "copy_kib_per_dispatch": copy,
-                      "copy_dispatches": nc, "scale": scale, "bytes_per_launch": fused * 1024.0 * scale}
+    cf, cw = read_counters(dfetch), read_counters(dwrite)
+    # calibration: b = a * 2 over 1 GiB reads 1 GiB and writes 1 GiB
+    cal = {}
+    for label, c in (("FETCH_SIZE", cf), ("WRITE_SIZE", cw)):
+        kib, n = pick(c, lambda k: "elementwise" in k and "Mul" in k)
+        cal[label] = {"calibration_kib_per_dispatch": kib, "calibration_dispatches": n,
+                      "scale": (COPY_BYTES / 1024.0) / kib}
     w = W.c2(10)
     esz = 4 if dtype == "f32" else 8
-    alg = bench.algorithmic_bytes(w, esz)["fused"]
-    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    alg = bench.algorithmic_bytes(w, esz)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
-    data[f"fused:{dtype}"] = {"source_hash": bench.kernel_source_hash(), "bytes_per_launch": round(total),
-                              "algorithmic_bytes_per_launch": alg, "ratio_to_algorithmic": round(total / alg, 4),
-                              "counters": res}
+    for name, pred in KERNELS.items():
+        if not any(pred(k) for k in cf):
+            continue
+        res = {}
+        for label, c in (("FETCH_SIZE", cf), ("WRITE_SIZE", cw)):
+            kib, n = pick(c, pred)
+            res[label] = {"kib_per_dispatch": kib, "dispatches": n, "scale": cal[label]["scale"],
+                          "bytes_per_launch": kib * 1024.0 * cal[label]["scale"]}
+        total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+        data[f"{name}:{dtype}"] = {"source_hash": bench.kernel_source_hash(), "bytes_per_launch": round(total),
+                                   "algorithmic_bytes_per_launch": alg[name],
+                                   "ratio_to_algorithmic": round(total / alg[name], 4),
+                                   "counters": res, "calibration": cal}
+        print(name, json.dumps(data[f"{name}:{dtype}"], indent=1))
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
-    print(json.dumps(data[f"fused:{dtype}"], indent=1))
 
 
 def main():
@@ -114,7 +129,7 @@ def main():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=128)
-    ap.add_argument("--fused", type=int, default=1, help="0: separate E and H passes; 1-4: fused tile variant")
+    ap.add_argument("--fused", type=int, default=0, help="0: separate E and H/M passes; 1-5: fused variants")
     args = ap.parse_args()
     if args.run:
         run(args.dtype, args.steps, args.nx, args.ny, args.nz, args.fused)

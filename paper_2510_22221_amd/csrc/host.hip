@@ -94,6 +94,9 @@ struct mpx_sim {
     std::vector<ProbeHost> probes;
     ProbeDev *d_probes = nullptr;
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
+    uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
+    int4 *d_mixed = nullptr;     // slots whose eight cells do not share one id
+    int nmixed = 0;
     long long *d_step = nullptr;
     int *d_flag = nullptr;
     long long step = 0;
@@ -255,6 +258,9 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.nsrc = (int)s->srcs.size();
     for (int i = 0; i < p.nsrc; i++) p.src[i] = s->srcs[i].dev;
     p.srcs = s->d_srcs;
+    p.pflags = s->d_pflags;
+    p.mixed = s->d_mixed;
+    p.nmixed = s->nmixed;
     p.probes = s->d_probes;
     p.step = s->d_step;
     p.flag = s->d_flag;
@@ -579,6 +585,43 @@ mpx_status check_live(mpx_sim *s) {
     return MPX_OK;
 }
 
+// per-tile flags of the separate passes (64 x 4 slots of one plane, with a
+// one-slot halo): 1 = touches a CPML slab, 2 = a source box, 4 = a film's
+// face box; with a periodic axis every tile may see index 0 through the wrap
+mpx_status update_pass_flags(mpx_sim *s) {
+    const int nxt = (s->n[0] + kPassTX - 1) / kPassTX, nyt = (s->n[1] + kPassTY - 1) / kPassTY;
+    const int nt = pass_tiles(s->n);
+    std::vector<uint8_t> fl(nt, 0);
+    const bool wrap = s->per[0] || s->per[1] || s->per[2];
+    for (int t = 0; t < nt; t++) {
+        const int i0 = (t % nxt) * kPassTX, j0 = ((t / nxt) % nyt) * kPassTY, k = t / (nxt * nyt);
+        const int lo[3] = {i0 - 1, j0 - 1, k - 1}, hi[3] = {i0 + kPassTX, j0 + kPassTY, k + 1};
+        uint8_t f = 0;
+        for (int a = 0; a < 3; a++) {
+            if (s->nlo[a] > 0 && lo[a] < s->nlo[a]) f |= 1;
+            if (s->nhi[a] > 0 && hi[a] >= s->n[a] - s->nhi[a]) f |= 1;
+        }
+        for (auto &src : s->srcs) {
+            bool in = true;
+            for (int a = 0; a < 3; a++)
+                if (src.dev.box[a] + src.dev.box[3 + a] <= lo[a] || src.dev.box[a] > hi[a]) in = false;
+            if (in || wrap) f |= 2;
+        }
+        for (auto &fm : s->films) {
+            bool in = true;
+            for (int a = 0; a < 3; a++)
+                if (fm.b0[a] + fm.bn[a] <= lo[a] || fm.b0[a] > hi[a]) in = false;
+            if (in || wrap) f |= 4;
+        }
+        fl[t] = f;
+    }
+    (void)hipFree(s->d_pflags);
+    s->d_pflags = nullptr;
+    CK(hipMalloc(&s->d_pflags, std::max(1, nt)));
+    CK(hipMemcpy(s->d_pflags, fl.data(), nt, hipMemcpyHostToDevice));
+    return MPX_OK;
+}
+
 mpx_status upload_probes(mpx_sim *s) {
     (void)hipFree(s->d_probes);
     s->d_probes = nullptr;
@@ -606,8 +649,10 @@ struct mpx_batch {
     void *d_pb[2] = {nullptr, nullptr}; // film / probe parameters after it
     int4 *d_work = nullptr; // fused variants: (instance, tile, z-chunk)
     int nwork = 0;
-    int2 *d_work2 = nullptr; // separate passes: (instance, tile)
+    int4 *d_work2 = nullptr; // separate passes: (instance, x tile, y tile, plane)
     int nwork2 = 0;
+    int2 *d_wmixed = nullptr; // mixed-slot blocks: (instance, first entry)
+    int nwmixed = 0;
     int2 *d_wfilm = nullptr, *d_wext = nullptr, *d_wprobe = nullptr;
     int nwfilm = 0, nwext = 0, nwprobe = 0;
     int *d_tick = nullptr;
@@ -646,13 +691,17 @@ void batch_drop_graph(mpx_batch *b) {
 template <typename T>
 mpx_status batch_tables(mpx_batch *b) {
     // tiles instance by instance, in the single-instance order
-    std::vector<int4> work;
-    std::vector<int2> work2, wfilm, wext, wprobe;
+    std::vector<int4> work, work2;
+    std::vector<int2> wmixed, wfilm, wext, wprobe;
     std::vector<int> tick;
     for (int q = 0; q < (int)b->sims.size(); q++) {
         const mpx_sim *s = b->sims[q];
         if (b->variant == 0) {
-            for (int t = 0; t < pass_tiles(s->n); t++) work2.push_back(make_int2(q, t));
+            const int nxt = (s->n[0] + kPassTX - 1) / kPassTX, nyt = (s->n[1] + kPassTY - 1) / kPassTY;
+            for (int k = 0; k < s->n[2]; k++)
+                for (int by = 0; by < nyt; by++)
+                    for (int bx = 0; bx < nxt; bx++) work2.push_back(make_int4(q, bx, by, k));
+            for (int m = 0; m < s->nmixed; m += 256) wmixed.push_back(make_int2(q, m));
         } else {
             // tiles of 64 x 4 columns (register sweep) or 64 x 8 (LDS-staged)
             const int nxt = (s->n[0] + 63) / 64, nyt = b->variant == 1 ? (s->n[1] + 3) / 4 : (s->n[1] + 7) / 8;
@@ -666,28 +715,35 @@ mpx_status batch_tables(mpx_batch *b) {
     }
     (void)hipFree(b->d_work);
     (void)hipFree(b->d_work2);
+    (void)hipFree(b->d_wmixed);
     (void)hipFree(b->d_wfilm);
     (void)hipFree(b->d_wext);
     (void)hipFree(b->d_wprobe);
     (void)hipFree(b->d_tick);
     b->d_work = nullptr;
-    b->d_work2 = b->d_wfilm = b->d_wext = b->d_wprobe = nullptr;
+    b->d_work2 = nullptr;
+    b->d_wmixed = nullptr;
+    b->d_wfilm = b->d_wext = b->d_wprobe = nullptr;
     b->d_tick = nullptr;
     b->nwork = (int)work.size();
     b->nwork2 = (int)work2.size();
+    b->nwmixed = (int)wmixed.size();
     b->nwfilm = (int)wfilm.size();
     b->nwext = (int)wext.size();
     b->nwprobe = (int)wprobe.size();
     b->ntick = (int)tick.size();
     BCK(hipMalloc(&b->d_work, std::max<size_t>(1, work.size()) * sizeof(int4)));
     if (!work.empty()) BCK(hipMemcpy(b->d_work, work.data(), work.size() * sizeof(int4), hipMemcpyHostToDevice));
+    BCK(hipMalloc(&b->d_work2, std::max<size_t>(1, work2.size()) * sizeof(int4)));
+    if (!work2.empty())
+        BCK(hipMemcpy(b->d_work2, work2.data(), work2.size() * sizeof(int4), hipMemcpyHostToDevice));
     auto up2 = [&](int2 **d, std::vector<int2> &v) -> mpx_status {
         BCK(hipMalloc(d, std::max<size_t>(1, v.size()) * sizeof(int2)));
         if (!v.empty()) BCK(hipMemcpy(*d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice));
         return MPX_OK;
     };
     mpx_status r;
-    if ((r = up2(&b->d_work2, work2)) != MPX_OK) return r;
+    if ((r = up2(&b->d_wmixed, wmixed)) != MPX_OK) return r;
     if ((r = up2(&b->d_wfilm, wfilm)) != MPX_OK) return r;
     if ((r = up2(&b->d_wext, wext)) != MPX_OK) return r;
     if ((r = up2(&b->d_wprobe, wprobe)) != MPX_OK) return r;
@@ -729,7 +785,7 @@ mpx_status batch_body(mpx_batch *b, int f) {
     if (b->variant == 0) {
         // E pass, film half steps and probes, then the bulk H pass (which
         // moves every instance's step counter)
-        BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, st));
+        BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, b->d_wmixed, b->nwmixed, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
         BCK(launch_probes_batch<T>(pa, b->d_wprobe, b->nwprobe, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 0, st));
@@ -922,6 +978,8 @@ mpx_status mpx_destroy(mpx_sim *s) {
     for (auto &pr : s->probes) (void)hipFree(pr.dev.data);
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_srcs);
+    (void)hipFree(s->d_pflags);
+    (void)hipFree(s->d_mixed);
     (void)hipFree(s->d_id);
     (void)hipFree(s->d_cls);
     (void)hipFree(s->d_mat);
@@ -1018,6 +1076,7 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             cd[q].ca = -(sig / 2.0 - eps / s->dt) / den;
             cd[q].cb = 1.0 / den;
             cd[q].pec = mats[q].is_pec ? 1 : 0;
+            if (cd[q].pec) cd[q].ca = cd[q].cb = 0.0; // a PEC edge stays zero
             cf[q].ca = (float)cd[q].ca;
             cf[q].cb = (float)cd[q].cb;
             cf[q].pec = cd[q].pec;
@@ -1034,7 +1093,25 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
                    s->n[0]);
     CK(hipMemcpy(s->d_id, slots.data(), s->nslot, hipMemcpyHostToDevice));
     CK(launch_classify(s->d_id, s->d_cls, s->n, s->per, s->px, s->stream));
-    CK(hipStreamSynchronize(s->stream));
+    {
+        // the list of mixed slots (count, then fill)
+        int *cnt = nullptr;
+        CK(hipMalloc(&cnt, sizeof(int)));
+        CK(hipMemsetAsync(cnt, 0, sizeof(int), s->stream));
+        CK(launch_list_mixed(s->d_cls, s->n, s->px, cnt, nullptr, s->stream));
+        int nm = 0;
+        CK(hipMemcpyAsync(&nm, cnt, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        CK(hipStreamSynchronize(s->stream));
+        (void)hipFree(s->d_mixed);
+        s->d_mixed = nullptr;
+        CK(hipMalloc(&s->d_mixed, std::max(1, nm) * sizeof(int4)));
+        CK(hipMemsetAsync(cnt, 0, sizeof(int), s->stream));
+        if (nm > 0) CK(launch_list_mixed(s->d_cls, s->n, s->px, cnt, s->d_mixed, s->stream));
+        CK(hipStreamSynchronize(s->stream));
+        (void)hipFree(cnt);
+        s->nmixed = nm;
+    }
+    if ((r = update_pass_flags(s)) != MPX_OK) return r;
     std::vector<int4> bt, bte;
     std::vector<FilmDev> fd;
     for (int fi = 0; fi < (int)s->films.size(); fi++) {
@@ -1182,6 +1259,7 @@ mpx_status mpx_add_source(mpx_sim *s, const mpx_source_desc *src, int32_t *id) {
         CK(hipMalloc(&s->d_srcs, v.size() * sizeof(SrcDev)));
         CK(hipMemcpy(s->d_srcs, v.data(), v.size() * sizeof(SrcDev), hipMemcpyHostToDevice));
     }
+    if ((r = update_pass_flags(s)) != MPX_OK) return r;
     drop_graph(s);
     if (id) *id = (int32_t)s->srcs.size() - 1;
     return MPX_OK;
@@ -1568,6 +1646,7 @@ mpx_status mpx_batch_destroy(mpx_batch *b) {
     }
     (void)hipFree(b->d_work);
     (void)hipFree(b->d_work2);
+    (void)hipFree(b->d_wmixed);
     (void)hipFree(b->d_wfilm);
     (void)hipFree(b->d_wext);
     (void)hipFree(b->d_wprobe);

@@ -81,6 +81,9 @@ struct KParams {
     const CoefDev<T> *coef;
     const uint8_t *id;
     const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
+    const uint8_t *pflags; // per separate-pass tile: 1 CPML, 2 source, 4 film within reach
+    const int4 *mixed;     // slots whose eight cells do not share one id (i, j, k, -)
+    int nmixed;
     const MatDev *mat;
     int nlo[3], nhi[3];
     const T *bE[3];
@@ -119,11 +122,15 @@ struct KParams {
 template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s);
 template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
 template <typename T>
-hipError_t launch_epass_batch(const KParams<T> *plist, const int2 *work, int nwork, hipStream_t s);
+hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
+                              hipStream_t s);
+hipError_t launch_list_mixed(const uint8_t *cls, const int *n, int px, int *count, int4 *list, hipStream_t s);
 template <typename T>
-hipError_t launch_hbulk_batch(const KParams<T> *plist, const int2 *work, int nwork, int nhalf, int inc,
+hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwork, int nhalf, int inc,
                               hipStream_t s);
 int pass_tiles(const int *n);
+constexpr int kPassTX = 64, kPassTY = 4; // separate-pass tile: 64 x 4 slots of one plane
+
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
 template <typename T> hipError_t launch_sweep(const KParams<T> &p, int kchunk, hipStream_t s);

@@ -11,14 +11,14 @@
 // load (a scalar resource per array whose base is the block's lowest plane,
 // a 32-bit byte offset per lane, and the neighbour plane as a scalar offset),
 // so the address work per load is one or two integer operations; blocks at a
-// boundary use folded, zero-filled loads.  Blocks are dealt to the XCDs in
-// contiguous runs, so the neighbour rows and the neighbour plane a block
-// reads were fetched into the same L2 by the blocks just before it.
+// boundary use folded, zero-filled loads.  Per-tile CPML / source / film
+// flags come from a host table; edge coefficients come from the material
+// table by the slot's class byte (no per-block staging).
 #include "stencil.h"
 
 namespace mpx {
 
-constexpr int PTX = 64, PTY = 4;
+constexpr int PTX = kPassTX, PTY = kPassTY;
 constexpr int kRsrcWord3 = 0x00020000; // raw buffer resource, gfx9 family
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, long long bytes) {
@@ -33,250 +33,290 @@ __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-// block-uniform flags of a one-plane tile with its +-1 halo: CPML slab,
-// source box, film face box within reach
+// block-uniform flags of a one-plane tile with its +-1 halo (CPML slab,
+// source box, film face box within reach), tabulated by the host
 template <typename T>
-__device__ __forceinline__ void pass_flags(const KParams<T> &p, int i0, int j0, int k, bool &tpml, bool &tsrc,
-                                           bool &tfilm) {
-    const int lo[3] = {i0 - 1, j0 - 1, k - 1}, hi[3] = {i0 + PTX, j0 + PTY, k + 1};
-    tpml = tsrc = tfilm = false;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (p.nlo[a] > 0 && lo[a] < p.nlo[a]) tpml = true;
-        if (p.nhi[a] > 0 && hi[a] >= p.n[a] - p.nhi[a]) tpml = true;
-    }
-    for (int s = 0; s < p.nsrc; s++) {
-        const SrcDev &S = p.srcs[s];
-        bool in = true;
-        for (int a = 0; a < 3; a++)
-            if (S.box[a] + S.box[3 + a] <= lo[a] || S.box[a] > hi[a]) in = false;
-        if (in) tsrc = true;
-    }
-    for (int f = 0; f < p.nfilm; f++) {
-        const FilmDev &F = p.films[f];
-        bool in = true;
-        for (int a = 0; a < 3; a++)
-            if (F.b0[a] + F.bn[a] <= lo[a] || F.b0[a] > hi[a]) in = false;
-        if (in) tfilm = true;
-    }
-    // a periodic wrap brings index 0 next to the far side
-    if (p.per[0] || p.per[1] || p.per[2]) {
-        if (p.nsrc) tsrc = true;
-        if (p.nfilm) tfilm = true;
-    }
+__device__ __forceinline__ void pass_flags(const KParams<T> &p, int t, bool &tpml, bool &tsrc, bool &tfilm) {
+    const int f = p.pflags[t];
+    tpml = f & 1;
+    tsrc = f & 2;
+    tfilm = f & 4;
 }
+
+constexpr int kOOB = 0x7ffffff0; // a byte offset past every resource: the load returns 0
 
 // ---------------------------------------------------------------------------
 // E pass: E_c <- ca E_c + cb ((curl H)_c - J_c) on the three edges of slot
-// (i, j, k); reads H at the slot and at its -x, -y, -z neighbours
+// (i, j, k); reads H at the slot and at its -x, -y, -z neighbours.  One path
+// for every tile: a -1 neighbour wraps on a periodic axis and is, at a wall,
+// any in-range value (only edges held at zero would read it); lanes past the
+// domain (partial tiles) compute nothing that is stored.  Slots whose eight
+// cells do not share one id are skipped: the mixed-slot kernel updates them
+// afterwards from the same old values.
 // ---------------------------------------------------------------------------
-template <typename T, bool WALL>
-__device__ __forceinline__ void epass_tile(const KParams<T> &p, const CoefLds<T> &L, int i0, int j0, int k, bool tpml,
-                                           bool tsrc) {
+template <typename T>
+__device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tsrc) {
+    const CoefMem<T> L{p.coef};
     const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
-    if (WALL && (i >= p.n[0] || j >= p.n[1])) return;
+    const bool inside = i < p.n[0] && j < p.n[1];
+    const int ic = min(i, p.n[0] - 1), jc = min(j, p.n[1] - 1);
     const long long sz = (long long)p.px * p.n[1];
-    const int o = i + p.px * j;
-    T hx0, hy0, hz0, hx_km, hy_km, hz_xm, hy_xm, hz_ym, hx_ym;
-    int c0;
-    if constexpr (!WALL) {
-        const long long base = (long long)(k - 1) * sz;
-        const long long nb = 2 * sz * (long long)sizeof(T);
-        const int P = (int)(sz * (long long)sizeof(T));
-        const int vo = o * (int)sizeof(T), vxm = vo - (int)sizeof(T), vym = vo - p.px * (int)sizeof(T);
-        const auto rx = make_rsrc(p.H[0] + base, nb), ry = make_rsrc(p.H[1] + base, nb),
-                   rz = make_rsrc(p.H[2] + base, nb);
-        hx0 = bld<T>(rx, vo, P);
-        hx_km = bld<T>(rx, vo, 0);
-        hx_ym = bld<T>(rx, vym, P);
-        hy0 = bld<T>(ry, vo, P);
-        hy_km = bld<T>(ry, vo, 0);
-        hy_xm = bld<T>(ry, vxm, P);
-        hz0 = bld<T>(rz, vo, P);
-        hz_xm = bld<T>(rz, vxm, P);
-        hz_ym = bld<T>(rz, vym, P);
-        c0 = (p.cls + (long long)k * sz)[o];
-    } else {
-        hx0 = ldz(p, p.H[0], i, j, k);
-        hx_km = ldz(p, p.H[0], i, j, k - 1);
-        hx_ym = ldz(p, p.H[0], i, j - 1, k);
-        hy0 = ldz(p, p.H[1], i, j, k);
-        hy_km = ldz(p, p.H[1], i, j, k - 1);
-        hy_xm = ldz(p, p.H[1], i - 1, j, k);
-        hz0 = ldz(p, p.H[2], i, j, k);
-        hz_xm = ldz(p, p.H[2], i - 1, j, k);
-        hz_ym = ldz(p, p.H[2], i, j - 1, k);
-        c0 = (p.cls + (long long)k * sz)[o];
-    }
-    T *ex = p.E[0] + (long long)k * sz, *ey = p.E[1] + (long long)k * sz, *ez = p.E[2] + (long long)k * sz;
+    const long long pb = sz * (long long)sizeof(T);
+    const int es = (int)sizeof(T), rowb = p.px * es;
+    const int o = ic + p.px * jc, vo = o * es;
+    const int vxm = ic > 0 ? vo - es : (p.per[0] ? vo + (p.n[0] - 1) * es : vo);
+    const int vym = jc > 0 ? vo - rowb : (p.per[1] ? vo + (p.n[1] - 1) * rowb : vo);
+    const int kb = k > 0 ? k - 1 : (p.per[2] ? p.n[2] - 1 : k);
+    const auto rx = make_rsrc(p.H[0] + k * sz, pb), ry = make_rsrc(p.H[1] + k * sz, pb),
+               rz = make_rsrc(p.H[2] + k * sz, pb);
+    const auto bx = make_rsrc(p.H[0] + kb * sz, pb), by = make_rsrc(p.H[1] + kb * sz, pb);
+    const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
+    const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
+    const T hz0 = bld<T>(rz, vo, 0), hz_xm = bld<T>(rz, vxm, 0), hz_ym = bld<T>(rz, vym, 0);
+    const int c0 = (p.cls + k * sz)[o];
+    T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
+    const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
     const long long step = tsrc ? p.step[0] : 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
-    const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
-    ex[o] = e_upd<T, 0, WALL, true>(p, L, i, j, k, c0, e0, dif(hz0, hz_ym, dy, iy), dif(hy0, hy_km, dz, iz), tpml,
-                                    tsrc, step, true);
-    ey[o] = e_upd<T, 1, WALL, true>(p, L, i, j, k, c0, e1, dif(hx0, hx_km, dz, iz), dif(hz0, hz_xm, dx, ix), tpml,
-                                    tsrc, step, true);
-    ez[o] = e_upd<T, 2, WALL, true>(p, L, i, j, k, c0, e2, dif(hy0, hy_xm, dx, ix), dif(hx0, hx_ym, dy, iy), tpml,
-                                    tsrc, step, true);
+    // every load of the thread before any store: CPML state of the three edges
+    int q0[3], q1[3], q2[3];
+    const bool v0 = inside && e_site<T, 0, true>(p, i, j, k, q0), v1 = inside && e_site<T, 1, true>(p, i, j, k, q1),
+               v2 = inside && e_site<T, 2, true>(p, i, j, k, q2);
+    Psi2<T> r0, r1, r2;
+    if (tpml) {
+        if (v0) r0 = psi_load<T, 0, true>(p, q0);
+        if (v1) r1 = psi_load<T, 1, true>(p, q1);
+        if (v2) r2 = psi_load<T, 2, true>(p, q2);
+    }
+    if (!inside || c0 == kMixed) return;
+    const T n0 = v0 ? e_apply<T, 0, CoefMem<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy),
+                                                       dif(hy0, hy_km, dz, iz), r0, tsrc, step)
+                    : T(0);
+    const T n1 = v1 ? e_apply<T, 1, CoefMem<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz),
+                                                       dif(hz0, hz_xm, dx, ix), r1, tsrc, step)
+                    : T(0);
+    const T n2 = v2 ? e_apply<T, 2, CoefMem<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix),
+                                                       dif(hx0, hx_ym, dy, iy), r2, tsrc, step)
+                    : T(0);
+    ex[o] = n0;
+    ey[o] = n1;
+    ez[o] = n2;
+    if (tpml) {
+        psi_store<T, 0>(p.psiE[0], r0);
+        psi_store<T, 1>(p.psiE[1], r1);
+        psi_store<T, 2>(p.psiE[2], r2);
+    }
 }
 
+// a block: the 64 x 4 slots (bx, by) of plane k
 template <typename T>
-__device__ __forceinline__ void epass_body(const KParams<T> &p, int t) {
-    __shared__ CoefLds<T> L;
-    stage_coef(p, L, threadIdx.y * PTX + threadIdx.x, PTX * PTY);
-    __syncthreads();
+__device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + PTX - 1) / PTX, nyt = (p.n[1] + PTY - 1) / PTY;
-    const int i0 = (t % nxt) * PTX, j0 = ((t / nxt) % nyt) * PTY, k = t / (nxt * nyt);
     bool tpml, tsrc, tfilm;
-    pass_flags(p, i0, j0, k, tpml, tsrc, tfilm);
-    // the E pass reads the -x, -y, -z neighbours
-    const bool wall = i0 == 0 || j0 == 0 || k == 0 || i0 + PTX > p.n[0] || j0 + PTY > p.n[1];
-    if (wall)
-        epass_tile<T, true>(p, L, i0, j0, k, tpml, tsrc);
-    else
-        epass_tile<T, false>(p, L, i0, j0, k, tpml, tsrc);
+    pass_flags(p, bx + nxt * (by + nyt * k), tpml, tsrc, tfilm);
+    epass_tile<T>(p, bx * PTX, by * PTY, k, tpml, tsrc);
+}
+
+// the mixed slots, one thread each: the general path (folded loads, edge
+// coefficients from the four cell ids), in place after the E pass
+template <typename T>
+__device__ __forceinline__ void emixed_slot(const KParams<T> &p, int m) {
+    const CoefMem<T> L{p.coef};
+    const int4 s = p.mixed[m];
+    const int i = s.x, j = s.y, k = s.z;
+    const T hx0 = ldz(p, p.H[0], i, j, k), hx_km = ldz(p, p.H[0], i, j, k - 1), hx_ym = ldz(p, p.H[0], i, j - 1, k);
+    const T hy0 = ldz(p, p.H[1], i, j, k), hy_km = ldz(p, p.H[1], i, j, k - 1), hy_xm = ldz(p, p.H[1], i - 1, j, k);
+    const T hz0 = ldz(p, p.H[2], i, j, k), hz_xm = ldz(p, p.H[2], i - 1, j, k), hz_ym = ldz(p, p.H[2], i, j - 1, k);
+    const long long q = p.slot(i, j, k);
+    const bool tpml = true, tsrc = p.nsrc > 0;
+    const long long step = tsrc ? p.step[0] : 0;
+    const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
+    const T e0 = p.E[0][q], e1 = p.E[1][q], e2 = p.E[2][q];
+    const T n0 = e_upd<T, 0, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e0, dif(hz0, hz_ym, dy, iy),
+                                                   dif(hy0, hy_km, dz, iz), tpml, tsrc, step, true);
+    const T n1 = e_upd<T, 1, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e1, dif(hx0, hx_km, dz, iz),
+                                                   dif(hz0, hz_xm, dx, ix), tpml, tsrc, step, true);
+    const T n2 = e_upd<T, 2, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e2, dif(hy0, hy_xm, dx, ix),
+                                                   dif(hx0, hx_ym, dy, iy), tpml, tsrc, step, true);
+    p.E[0][q] = n0;
+    p.E[1][q] = n1;
+    p.E[2][q] = n2;
 }
 
 // ---------------------------------------------------------------------------
 // H/M pass: NHALF half steps of the non-magnetic faces of slot (i, j, k);
-// reads E at the slot and at its +x, +y, +z neighbours
+// reads E at the slot and at its +x, +y, +z neighbours.  A +1 neighbour wraps
+// on a periodic axis and reads zero at a wall (the E there is tangential to
+// it); lanes past the domain store nothing.
 // ---------------------------------------------------------------------------
-template <typename T, int NHALF, bool WALL>
+template <typename T, int NHALF>
 __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tfilm) {
     const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
-    if (WALL && (i >= p.n[0] || j >= p.n[1])) return;
+    const bool inside = i < p.n[0] && j < p.n[1];
+    const int ic = min(i, p.n[0] - 1), jc = min(j, p.n[1] - 1);
     const long long sz = (long long)p.px * p.n[1];
-    const int o = i + p.px * j;
-    T ex0, ey0, ez0, ex_yp, ex_kp, ey_xp, ey_kp, ez_xp, ez_yp;
-    if constexpr (!WALL) {
-        const long long base = (long long)k * sz;
-        const long long nb = 2 * sz * (long long)sizeof(T);
-        const int P = (int)(sz * (long long)sizeof(T));
-        const int vo = o * (int)sizeof(T), vxp = vo + (int)sizeof(T), vyp = vo + p.px * (int)sizeof(T);
-        const auto rx = make_rsrc(p.E[0] + base, nb), ry = make_rsrc(p.E[1] + base, nb),
-                   rz = make_rsrc(p.E[2] + base, nb);
-        ex0 = bld<T>(rx, vo, 0);
-        ex_yp = bld<T>(rx, vyp, 0);
-        ex_kp = bld<T>(rx, vo, P);
-        ey0 = bld<T>(ry, vo, 0);
-        ey_xp = bld<T>(ry, vxp, 0);
-        ey_kp = bld<T>(ry, vo, P);
-        ez0 = bld<T>(rz, vo, 0);
-        ez_xp = bld<T>(rz, vxp, 0);
-        ez_yp = bld<T>(rz, vyp, 0);
-    } else {
-        ex0 = ldz(p, p.E[0], i, j, k);
-        ex_yp = ldz(p, p.E[0], i, j + 1, k);
-        ex_kp = ldz(p, p.E[0], i, j, k + 1);
-        ey0 = ldz(p, p.E[1], i, j, k);
-        ey_xp = ldz(p, p.E[1], i + 1, j, k);
-        ey_kp = ldz(p, p.E[1], i, j, k + 1);
-        ez0 = ldz(p, p.E[2], i, j, k);
-        ez_xp = ldz(p, p.E[2], i + 1, j, k);
-        ez_yp = ldz(p, p.E[2], i, j + 1, k);
-    }
+    const long long pb = sz * (long long)sizeof(T);
+    const int es = (int)sizeof(T), rowb = p.px * es;
+    const int o = ic + p.px * jc, vo = o * es;
+    const int vxp = ic + 1 < p.n[0] ? vo + es : (p.per[0] ? vo - (p.n[0] - 1) * es : kOOB);
+    const int vyp = jc + 1 < p.n[1] ? vo + rowb : (p.per[1] ? vo - (p.n[1] - 1) * rowb : kOOB);
+    const int ka = k + 1 < p.n[2] ? k + 1 : (p.per[2] ? 0 : -1);
+    const auto rx = make_rsrc(p.E[0] + k * sz, pb), ry = make_rsrc(p.E[1] + k * sz, pb),
+               rz = make_rsrc(p.E[2] + k * sz, pb);
+    // the plane above; none (every load zero) above a wall
+    const auto ax = make_rsrc(p.E[0] + (ka < 0 ? 0 : ka) * sz, ka < 0 ? 0 : pb),
+               ay = make_rsrc(p.E[1] + (ka < 0 ? 0 : ka) * sz, ka < 0 ? 0 : pb);
+    const auto gx = make_rsrc(p.H[0] + k * sz, pb), gy = make_rsrc(p.H[1] + k * sz, pb),
+               gz = make_rsrc(p.H[2] + k * sz, pb);
+    const T ex0 = bld<T>(rx, vo, 0), ex_yp = bld<T>(rx, vyp, 0), ex_kp = bld<T>(ax, vo, 0);
+    const T ey0 = bld<T>(ry, vo, 0), ey_xp = bld<T>(ry, vxp, 0), ey_kp = bld<T>(ay, vo, 0);
+    const T ez0 = bld<T>(rz, vo, 0), ez_xp = bld<T>(rz, vxp, 0), ez_yp = bld<T>(rz, vyp, 0);
+    const T h0 = bld<T>(gx, vo, 0), h1 = bld<T>(gy, vo, 0), h2 = bld<T>(gz, vo, 0);
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
-    T *hx = p.H[0] + (long long)k * sz, *hy = p.H[1] + (long long)k * sz, *hz = p.H[2] + (long long)k * sz;
-    const int idx[3] = {i, j, k};
+    const int idx[3] = {ic, jc, k};
+    Psi2<T> r0, r1, r2;
+    if (tpml && inside) {
+        r0 = psi_load<T, 0, false>(p, idx);
+        r1 = psi_load<T, 1, false>(p, idx);
+        r2 = psi_load<T, 2, false>(p, idx);
+    }
     bool mag[3] = {false, false, false};
-    if (tfilm) {
+    if (tfilm && inside) {
         mag[0] = face_is_magnetic(p, 0, idx);
         mag[1] = face_is_magnetic(p, 1, idx);
         mag[2] = face_is_magnetic(p, 2, idx);
     }
-    if (!mag[0]) hx[o] = h_upd<T, 0, NHALF>(p, idx, hx[o], dif(ez_yp, ez0, dy, iy), dif(ey_kp, ey0, dz, iz), tpml);
-    if (!mag[1]) hy[o] = h_upd<T, 1, NHALF>(p, idx, hy[o], dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), tpml);
-    if (!mag[2]) hz[o] = h_upd<T, 2, NHALF>(p, idx, hz[o], dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), tpml);
+    if (!inside) return;
+    const T n0 = h_apply<T, 0, NHALF>(p, h0, dif(ez_yp, ez0, dy, iy), dif(ey_kp, ey0, dz, iz), r0);
+    const T n1 = h_apply<T, 1, NHALF>(p, h1, dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), r1);
+    const T n2 = h_apply<T, 2, NHALF>(p, h2, dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), r2);
+    T *hx = p.H[0] + k * sz, *hy = p.H[1] + k * sz, *hz = p.H[2] + k * sz;
+    if (!mag[0]) hx[o] = n0;
+    if (!mag[1]) hy[o] = n1;
+    if (!mag[2]) hz[o] = n2;
+    if (tpml) {
+        if (!mag[0]) psi_store<T, 0>(p.psiH[0], r0);
+        if (!mag[1]) psi_store<T, 1>(p.psiH[1], r1);
+        if (!mag[2]) psi_store<T, 2>(p.psiH[2], r2);
+    }
 }
 
 template <typename T, int NHALF>
-__device__ __forceinline__ void hpass_body(const KParams<T> &p, int t) {
+__device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + PTX - 1) / PTX, nyt = (p.n[1] + PTY - 1) / PTY;
-    const int i0 = (t % nxt) * PTX, j0 = ((t / nxt) % nyt) * PTY, k = t / (nxt * nyt);
     bool tpml, tsrc, tfilm;
-    pass_flags(p, i0, j0, k, tpml, tsrc, tfilm);
-    // the H pass reads the +x, +y, +z neighbours
-    const bool wall = i0 + PTX >= p.n[0] || j0 + PTY >= p.n[1] || k + 1 >= p.n[2];
-    if (wall)
-        hpass_tile<T, NHALF, true>(p, i0, j0, k, tpml, tfilm);
-    else
-        hpass_tile<T, NHALF, false>(p, i0, j0, k, tpml, tfilm);
+    pass_flags(p, bx + nxt * (by + nyt * k), tpml, tsrc, tfilm);
+    hpass_tile<T, NHALF>(p, bx * PTX, by * PTY, k, tpml, tfilm);
 }
 
-__device__ __forceinline__ int xcd_tile(int ntile) {
-    const int per = (ntile + 7) / 8;
-    return (blockIdx.x % 8) * per + blockIdx.x / 8;
-}
-
+// grid (x tiles, y tiles, planes) in natural order: the blocks resident at
+// one time cover a few consecutive planes, so neighbour rows and planes are
+// cache hits, and no block decodes its tile with divisions
 template <typename T>
-__global__ void __launch_bounds__(PTX *PTY) k_epass(KParams<T> p, int ntile) {
-    const int t = xcd_tile(ntile);
-    if (t >= ntile) return;
-    epass_body<T>(p, t);
+__global__ void __launch_bounds__(PTX *PTY) k_epass(KParams<T> p) {
+    epass_block<T>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int NHALF>
-__global__ void __launch_bounds__(PTX *PTY) k_hbulk(KParams<T> p, int ntile, int inc_step) {
-    if (inc_step && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step[0] = p.step[0] + 1;
-    const int t = xcd_tile(ntile);
-    if (t >= ntile) return;
-    hpass_body<T, NHALF>(p, t);
+__global__ void __launch_bounds__(PTX *PTY) k_hbulk(KParams<T> p, int inc_step) {
+    if (inc_step && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0)
+        p.step[0] = p.step[0] + 1;
+    hpass_block<T, NHALF>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// batched: work[w] = (instance, tile)
+template <typename T>
+__global__ void __launch_bounds__(256) k_emixed(KParams<T> p) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m < p.nmixed) emixed_slot<T>(p, m);
+}
+
+// batched: work[w] = (instance, x tile, y tile, plane)
 template <typename T>
 __global__ void __launch_bounds__(PTX *PTY)
-    k_epass_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work, int nwork) {
-    const int w = xcd_tile(nwork);
+    k_epass_batch(const KParams<T> *__restrict__ plist, const int4 *__restrict__ work, int nwork) {
+    const int w = blockIdx.x;
     if (w >= nwork) return;
-    const int2 wk = work[w];
-    epass_body<T>(plist[wk.x], wk.y);
+    const int4 wk = work[w];
+    epass_block<T>(plist[wk.x], wk.y, wk.z, wk.w);
 }
 
-// the step counter of each instance moves with its tile 0 (inc_step)
-template <typename T, int NHALF>
-__global__ void __launch_bounds__(PTX *PTY)
-    k_hbulk_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work, int nwork, int inc_step) {
-    const int w = xcd_tile(nwork);
+// work[w] = (instance, first list entry of a 256-entry block)
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_emixed_batch(const KParams<T> *__restrict__ plist, const int2 *__restrict__ work, int nwork) {
+    const int w = blockIdx.x;
     if (w >= nwork) return;
     const int2 wk = work[w];
     const KParams<T> &p = plist[wk.x];
-    if (inc_step && wk.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step[0] = p.step[0] + 1;
-    hpass_body<T, NHALF>(p, wk.y);
+    const int m = wk.y + threadIdx.x;
+    if (m < p.nmixed) emixed_slot<T>(p, m);
+}
+
+// the step counter of each instance moves with its first block (inc_step)
+template <typename T, int NHALF>
+__global__ void __launch_bounds__(PTX *PTY)
+    k_hbulk_batch(const KParams<T> *__restrict__ plist, const int4 *__restrict__ work, int nwork, int inc_step) {
+    const int w = blockIdx.x;
+    if (w >= nwork) return;
+    const int4 wk = work[w];
+    const KParams<T> &p = plist[wk.x];
+    if (inc_step && wk.y == 0 && wk.z == 0 && wk.w == 0 && threadIdx.x == 0 && threadIdx.y == 0)
+        p.step[0] = p.step[0] + 1;
+    hpass_block<T, NHALF>(p, wk.y, wk.z, wk.w);
+}
+
+// the slots whose class byte says "mixed", in any order (each is updated
+// independently); count only when list is null
+__global__ void __launch_bounds__(256) k_list_mixed(const uint8_t *__restrict__ cls, int nx, int ny, int px,
+                                                     int *count, int4 *list) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i >= nx) return;
+    if (cls[(long long)i + (long long)px * ((long long)j + (long long)ny * k)] != kMixed) return;
+    const int m = atomicAdd(count, 1);
+    if (list) list[m] = make_int4(i, j, k, 0);
+}
+
+hipError_t launch_list_mixed(const uint8_t *cls, const int *n, int px, int *count, int4 *list, hipStream_t s) {
+    k_list_mixed<<<dim3((n[0] + 255) / 256, n[1], n[2]), dim3(256), 0, s>>>(cls, n[0], n[1], px, count, list);
+    return hipGetLastError();
 }
 
 int pass_tiles(const int *n) { return ((n[0] + PTX - 1) / PTX) * ((n[1] + PTY - 1) / PTY) * n[2]; }
 
+static dim3 pass_grid(const int *n) { return dim3((n[0] + PTX - 1) / PTX, (n[1] + PTY - 1) / PTY, n[2]); }
+
+// the E pass and then its mixed slots
 template <typename T>
 hipError_t launch_epass(const KParams<T> &p, hipStream_t s) {
-    const int ntile = pass_tiles(p.n);
-    k_epass<T><<<dim3((ntile + 7) / 8 * 8), dim3(PTX, PTY), 0, s>>>(p, ntile);
+    k_epass<T><<<pass_grid(p.n), dim3(PTX, PTY), 0, s>>>(p);
+    if (p.nmixed > 0) k_emixed<T><<<dim3((p.nmixed + 255) / 256), dim3(256), 0, s>>>(p);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s) {
-    const int ntile = pass_tiles(p.n);
-    const dim3 g((ntile + 7) / 8 * 8), b(PTX, PTY);
+    const dim3 g = pass_grid(p.n), b(PTX, PTY);
     if (nhalf == 1)
-        k_hbulk<T, 1><<<g, b, 0, s>>>(p, ntile, inc);
+        k_hbulk<T, 1><<<g, b, 0, s>>>(p, inc);
     else
-        k_hbulk<T, 2><<<g, b, 0, s>>>(p, ntile, inc);
+        k_hbulk<T, 2><<<g, b, 0, s>>>(p, inc);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_epass_batch(const KParams<T> *plist, const int2 *work, int nwork, hipStream_t s) {
-    if (nwork == 0) return hipSuccess;
-    k_epass_batch<T><<<dim3((nwork + 7) / 8 * 8), dim3(PTX, PTY), 0, s>>>(plist, work, nwork);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_hbulk_batch(const KParams<T> *plist, const int2 *work, int nwork, int nhalf, int inc,
+hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
                               hipStream_t s) {
     if (nwork == 0) return hipSuccess;
-    const dim3 g((nwork + 7) / 8 * 8), b(PTX, PTY);
+    k_epass_batch<T><<<dim3(nwork), dim3(PTX, PTY), 0, s>>>(plist, work, nwork);
+    if (nmwork > 0) k_emixed_batch<T><<<dim3(nmwork), dim3(256), 0, s>>>(plist, mwork, nmwork);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwork, int nhalf, int inc,
+                              hipStream_t s) {
+    if (nwork == 0) return hipSuccess;
+    const dim3 g(nwork), b(PTX, PTY);
     if (nhalf == 1)
         k_hbulk_batch<T, 1><<<g, b, 0, s>>>(plist, work, nwork, inc);
     else
@@ -287,8 +327,9 @@ hipError_t launch_hbulk_batch(const KParams<T> *plist, const int2 *work, int nwo
 #define MPX_PASSES(T)                                                                                      \
     template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                                 \
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);                       \
-    template hipError_t launch_epass_batch<T>(const KParams<T> *, const int2 *, int, hipStream_t);        \
-    template hipError_t launch_hbulk_batch<T>(const KParams<T> *, const int2 *, int, int, int, hipStream_t);
+    template hipError_t launch_epass_batch<T>(const KParams<T> *, const int4 *, int, const int2 *, int,   \
+                                              hipStream_t);                                               \
+    template hipError_t launch_hbulk_batch<T>(const KParams<T> *, const int4 *, int, int, int, hipStream_t);
 MPX_PASSES(float)
 MPX_PASSES(double)
 

@@ -20,6 +20,21 @@ constexpr int kMixed = 255;
 template <typename T>
 struct CoefLds {
     T ca[256], cb[256];
+    __device__ __forceinline__ void get(int cls, T &a, T &b) const {
+        a = ca[cls];
+        b = cb[cls];
+    }
+};
+
+// the same table read straight from device memory (the host stores PEC
+// entries as ca = cb = 0)
+template <typename T>
+struct CoefMem {
+    const CoefDev<T> *c;
+    __device__ __forceinline__ void get(int cls, T &a, T &b) const {
+        a = c[cls].ca;
+        b = c[cls].cb;
+    }
 };
 
 template <typename T>
@@ -98,52 +113,101 @@ __device__ __noinline__ CaCb<T> mixed_coef(const uint8_t *gid, const MatDev *gma
     return r;
 }
 
-// E^{n+1} of component C at raw position (gi, gj, gk) (possibly one past the
-// domain on a periodic axis), given E^n, the class byte of its slot and the
-// two raw curl differences d1 (along C1) and d2 (along C2).  `own`: this
-// thread owns the edge and writes its E-type psi.
-// PSI_INPLACE: the E-type psi live in one buffer (separate-pass schedule)
-template <typename T, int C, bool WALL, bool PSI_INPLACE = false>
-__device__ __forceinline__ T e_upd(const KParams<T> &p, const CoefLds<T> &L, int gi, int gj, int gk, int cls,
-                                   T eold, T d1, T d2, bool tpml, bool tsrc, long long step, bool own) {
+// CPML state of one component at one site for its two derivative axes:
+// slab membership, slab-compact index, psi and the recursion coefficients.
+// Loaded before any store of a pass (so every load of a thread is in flight
+// at once), applied, then stored.
+template <typename T>
+struct Psi2 {
+    bool s1 = false, s2 = false, upd = false;
+    long long q1 = 0, q2 = 0;
+    T ps1 = T(0), ps2 = T(0), b1 = T(0), c1 = T(0), b2 = T(0), c2 = T(0);
+};
+
+// E: the E-type psi (E = true) or H-type psi of component C at the folded
+// site idx
+template <typename T, int C, bool E>
+__device__ __forceinline__ Psi2<T> psi_load(const KParams<T> &p, const int *idx) {
     constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-    int idx[3] = {gi, gj, gk};
+    Psi2<T> r;
+    T *const *arr = E ? p.psiE[C] : p.psiH[C];
+    const T *const *bt = E ? p.bE : p.bH;
+    const T *const *ct = E ? p.cE : p.cH;
+    const int a1 = idx[C1], a2 = idx[C2];
+    r.s1 = arr[C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]);
+    r.s2 = arr[C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
+    if (r.s1) {
+        r.q1 = p.psi_index(C1, idx);
+        r.ps1 = arr[C1][r.q1];
+        r.b1 = bt[C1][a1];
+        r.c1 = ct[C1][a1];
+    }
+    if (r.s2) {
+        r.q2 = p.psi_index(C2, idx);
+        r.ps2 = arr[C2][r.q2];
+        r.b2 = bt[C2][a2];
+        r.c2 = ct[C2][a2];
+    }
+    return r;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void psi_store(T *const *arr, const Psi2<T> &r) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    if (!r.upd) return;
+    if (r.s1) arr[C1][r.q1] = r.ps1;
+    if (r.s2) arr[C2][r.q2] = r.ps2;
+}
+
+// the E edge of component C at raw position (gi, gj, gk) (possibly one past
+// the domain on a periodic axis): false when it lies on a wall (held at
+// zero) or beyond a partial tile; idx receives the folded position
+template <typename T, int C, bool WALL>
+__device__ __forceinline__ bool e_site(const KParams<T> &p, int gi, int gj, int gk, int *idx) {
+    idx[0] = gi;
+    idx[1] = gj;
+    idx[2] = gk;
     if constexpr (WALL) {
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             if (p.per[a]) {
-                if (idx[a] > p.n[a]) return T(0); // beyond a partial tile; never stored
+                if (idx[a] > p.n[a]) return false; // beyond a partial tile; never stored
                 if (idx[a] == p.n[a]) idx[a] = 0;
             } else {
-                if (a != C && idx[a] == 0) return T(0); // tangential to a wall
-                if (idx[a] >= p.n[a]) return T(0);      // on the far wall (not stored)
+                if (a != C && idx[a] == 0) return false; // tangential to a wall
+                if (idx[a] >= p.n[a]) return false;      // on the far wall (not stored)
             }
         }
     }
+    return true;
+}
+
+// E^{n+1} of component C at the folded site idx (a valid edge), given E^n,
+// the class byte of its slot, the two raw curl differences d1 (along C1) and
+// d2 (along C2) and its loaded CPML state (advanced here; r.upd tells the
+// caller to store it: a PEC edge, cb = 0, stays zero and keeps its psi)
+// (MIXED = false: the caller guarantees a uniform class, no mixed path)
+template <typename T, int C, class TAB, bool MIXED = true>
+__device__ __forceinline__ T e_apply(const KParams<T> &p, const TAB &L, const int *idx, int cls, T eold, T d1, T d2,
+                                     Psi2<T> &r, bool tsrc, long long step) {
     T ca, cb;
-    if (cls != kMixed) {
-        ca = L.ca[cls];
-        cb = L.cb[cls];
+    if (!MIXED || cls != kMixed) {
+        L.get(cls, ca, cb);
     } else {
-        const CaCb<T> r = mixed_coef<T, C>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.px, p.per[0], p.per[1], p.per[2],
+        const CaCb<T> m = mixed_coef<T, C>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.px, p.per[0], p.per[1], p.per[2],
                                            p.eps0, p.dt, p.inv_dt, idx[0], idx[1], idx[2]);
-        ca = r.pec ? T(0) : r.ca;
-        cb = r.pec ? T(0) : r.cb;
+        ca = m.pec ? T(0) : m.ca;
+        cb = m.pec ? T(0) : m.cb;
     }
-    // a PEC edge (cb = 0) stays zero and keeps its psi
-    if (tpml && cb != T(0)) {
-        const int a1 = idx[C1], a2 = idx[C2];
-        if (p.psiE[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1])) {
-            const long long qq = p.psi_index(C1, idx);
-            const T ps = p.bE[C1][a1] * p.psiE[C][C1][qq] + p.cE[C1][a1] * d1;
-            if (own) (PSI_INPLACE ? p.psiE : p.psiEb)[C][C1][qq] = ps;
-            d1 += ps;
+    r.upd = cb != T(0);
+    if (r.upd) {
+        if (r.s1) {
+            r.ps1 = r.b1 * r.ps1 + r.c1 * d1;
+            d1 += r.ps1;
         }
-        if (p.psiE[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2])) {
-            const long long qq = p.psi_index(C2, idx);
-            const T ps = p.bE[C2][a2] * p.psiE[C][C2][qq] + p.cE[C2][a2] * d2;
-            if (own) (PSI_INPLACE ? p.psiE : p.psiEb)[C][C2][qq] = ps;
-            d2 += ps;
+        if (r.s2) {
+            r.ps2 = r.b2 * r.ps2 + r.c2 * d2;
+            d2 += r.ps2;
         }
     }
     T x = d1 - d2;
@@ -163,43 +227,50 @@ __device__ __forceinline__ T e_upd(const KParams<T> &p, const CoefLds<T> &L, int
     return ca * eold + cb * x;
 }
 
+// the whole E update of one edge (load psi, apply, store psi).
+// PSI_INPLACE: the E-type psi live in one buffer (separate-pass schedule);
+// `own`: this thread owns the edge and writes its psi.
+template <typename T, int C, bool WALL, bool PSI_INPLACE = false, class TAB = CoefLds<T>>
+__device__ __forceinline__ T e_upd(const KParams<T> &p, const TAB &L, int gi, int gj, int gk, int cls,
+                                   T eold, T d1, T d2, bool tpml, bool tsrc, long long step, bool own) {
+    int idx[3];
+    if (!e_site<T, C, WALL>(p, gi, gj, gk, idx)) return T(0);
+    Psi2<T> r;
+    if (tpml) r = psi_load<T, C, true>(p, idx);
+    const T e = e_apply<T, C>(p, L, idx, cls, eold, d1, d2, r, tsrc, step);
+    if (own) psi_store<T, C>(PSI_INPLACE ? p.psiE[C] : p.psiEb[C], r);
+    return e;
+}
+
 // NHALF consecutive H/M half steps with the same E (2: the merged pair
-// around an integer time, 1: a bracket half step) of component C at the
-// owned slot idx (folded), given the raw differences of E
-template <typename T, int C, int NHALF = 2>
-__device__ __forceinline__ T h_upd(const KParams<T> &p, const int *idx, T h, T d1r, T d2r, bool tpml) {
-    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-    bool s1 = false, s2 = false;
-    long long q1 = 0, q2 = 0;
-    T ps1 = T(0), ps2 = T(0);
-    const int a1 = idx[C1], a2 = idx[C2];
-    if (tpml) {
-        s1 = p.psiH[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]);
-        s2 = p.psiH[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
-        if (s1) {
-            q1 = p.psi_index(C1, idx);
-            ps1 = p.psiH[C][C1][q1];
-        }
-        if (s2) {
-            q2 = p.psi_index(C2, idx);
-            ps2 = p.psiH[C][C2][q2];
-        }
-    }
+// around an integer time, 1: a bracket half step) of component C, given the
+// raw differences of E and its loaded CPML state (advanced here)
+template <typename T, int C, int NHALF>
+__device__ __forceinline__ T h_apply(const KParams<T> &p, T h, T d1r, T d2r, Psi2<T> &r) {
 #pragma unroll
     for (int hs = 0; hs < NHALF; hs++) {
         T d1 = d1r, d2 = d2r;
-        if (s1) {
-            ps1 = p.bH[C1][a1] * ps1 + p.cH[C1][a1] * d1;
-            d1 += ps1;
+        if (r.s1) {
+            r.ps1 = r.b1 * r.ps1 + r.c1 * d1;
+            d1 += r.ps1;
         }
-        if (s2) {
-            ps2 = p.bH[C2][a2] * ps2 + p.cH[C2][a2] * d2;
-            d2 += ps2;
+        if (r.s2) {
+            r.ps2 = r.b2 * r.ps2 + r.c2 * d2;
+            d2 += r.ps2;
         }
         h = h - p.hc * (d1 - d2);
     }
-    if (s1) p.psiH[C][C1][q1] = ps1;
-    if (s2) p.psiH[C][C2][q2] = ps2;
+    r.upd = true;
+    return h;
+}
+
+// the whole H update of one owned face (folded idx)
+template <typename T, int C, int NHALF = 2>
+__device__ __forceinline__ T h_upd(const KParams<T> &p, const int *idx, T h, T d1r, T d2r, bool tpml) {
+    Psi2<T> r;
+    if (tpml) r = psi_load<T, C, false>(p, idx);
+    h = h_apply<T, C, NHALF>(p, h, d1r, d2r, r);
+    psi_store<T, C>(p.psiH[C], r);
     return h;
 }
 
