@@ -162,7 +162,7 @@ def batched_sweep(steps, n_inst, variant=None, kchunk=None):
             "sequential_Gcell_s": round(cells * steps / seq / 1e9, 3),
             "batched_Gcell_s": round(cells * steps / bat / 1e9, 3),
             "batched_over_sequential": round(seq / bat, 3),
-            "schedule": {"variant": variant or 1, "kchunk": kchunk or 16}}
+            "schedule": ("separate E and H/M passes" if not variant else f"fused pass, variant {variant}")}
 
 
 def cpu_baseline(w, nsteps):
