@@ -242,6 +242,35 @@ mpx_status mpx_kernel_time(mpx_sim *sim, double *avg_ms, int64_t *launches);
 /* Human-readable description of the last error on this handle. */
 const char *mpx_last_error(const mpx_sim *sim);
 
+/* ---- Gradients by the discrete adjoint ----------------------------------
+ *
+ * Runs nsteps time steps forward from the current state (like mpx_step) and
+ * returns the loss L = dt * sum over steps n = loss_from+1 .. nsteps of the
+ * EM energy of film `film` at integer time n (the film-energy probe's sum:
+ * over the film's magnetic cells, 1/2 eps0 eps_r times the mean over its four
+ * edges of E_c^2 plus 1/2 mu0 times the mean over its two faces of H_c^2,
+ * summed over c, times the cell volume), together with its exact gradients
+ * by reverse time stepping of the discrete scheme (the transposes of the E
+ * step, of the H/M half steps and of the closed-form trapezoidal LLG solve,
+ * with the CPML recursions; Methods, "Numerical Model"):
+ *   dL_dH0[3]  with respect to the uniform bias H0 (A/m),
+ *   dL_deps    with respect to eps_r of each cell of eps_box (i0, j0, k0,
+ *              ni, nj, nk; x fastest), every cell taken as its own parameter,
+ *   dL_dMs     with respect to Ms of each cell of ms_box (x fastest): through
+ *              the face values Ms_s (mean over the face's cells) in the LLG
+ *              solve and, when the run starts at step 0, through the initial
+ *              magnetisation M0 = Ms_s u.
+ * The forward states are recomputed from checkpoints taken every
+ * `checkpoint_every` steps (0: ceil(sqrt(nsteps))), so memory is about
+ * (2 sqrt(nsteps) + 10) field states.  On return the handle holds the state
+ * after nsteps (step counter advanced, probes recorded as by mpx_step).
+ * Host output buffers; boxes must lie inside the grid.  Synchronous.
+ * Errors: MPX_E_INVALID (arguments), MPX_E_STATE (materials / magnetisation
+ * not set), MPX_E_NOMEM / MPX_E_DEVICE. */
+mpx_status mpx_adjoint(mpx_sim *sim, int64_t nsteps, int64_t loss_from, int32_t film, int32_t checkpoint_every,
+                       const int32_t eps_box[6], const int32_t ms_box[6], double *loss, double *dL_dH0,
+                       double *dL_deps, double *dL_dMs);
+
 /* ---- Batched stepping (many simulations per launch) --------------------
  *
  * A batch groups n >= 1 simulation handles of one precision on one device,

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpx.so")
-SOURCES = ["kernels.hip", "passes.hip", "fused.hip", "sweep.hip", "host.hip"]
+SOURCES = ["kernels.hip", "passes.hip", "fused.hip", "sweep.hip", "adjoint.hip", "host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the float64 path evaluates every value with the same

@@ -1,0 +1,680 @@
+// adjoint.hip -- reverse-mode (discrete adjoint) kernels of the coupled step.
+//
+// The forward step (arXiv:2510.22221, Methods, "Numerical Model") is
+//   HALF1(E^n): H/M half step (eq. iterate_H; LLG eqs. llg_tra4-llg_tra6 at
+//               magnetic faces, solved in closed form and normalised),
+//   ESTEP(H):   the E update after eq. iterate_H, with CPML and the source,
+//   HALF2(E^{n+1}),
+// and the adjoint runs the transposes of these maps in reverse order.  Given
+// the adjoint state lambda of the state after a map and the map's input
+// state (recomputed from checkpoints), a kernel here returns lambda of the
+// input state and accumulates the parameter gradients:
+//   * non-magnetic faces and E edges are linear: transposed curls and
+//     transposed CPML recursions;
+//   * a magnetic face's update M' = Ms X/|X|, X = (b + (a.b)a - a x b) /
+//     (1 + |a|^2), a = -(k P + (alpha/Ms) M), b = M - k M x Q, with P, Q the
+//     site's B^* and B^ (own component, and the mean of four neighbouring
+//     faces of each other family) plus H0, is differentiated by hand; H0, Ms
+//     of each face and the edge coefficients ca, cb collect gradients.
+// One thread per slot or per film face; every sum a thread forms is a gather
+// (no atomics), so results do not depend on scheduling.
+#include "device_common.h"
+
+namespace mpx {
+
+__device__ __forceinline__ void cross3a(const double *a, const double *b, double *r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3a(const double *a, const double *b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// local index of face idx (folded) in the film's face box, -1 outside
+__device__ __forceinline__ long long film_local_idx(const FilmDev &F, const int *idx) {
+    const int r0 = idx[0] - F.b0[0], r1 = idx[1] - F.b0[1], r2 = idx[2] - F.b0[2];
+    if (r0 < 0 || r0 >= F.bn[0] || r1 < 0 || r1 >= F.bn[1] || r2 < 0 || r2 >= F.bn[2]) return -1;
+    return (long long)r0 + (long long)F.bn[0] * ((long long)r1 + (long long)F.bn[1] * r2);
+}
+
+// the magnetic face of family c at idx: (film, local index) or (-1, -1)
+template <typename T>
+__device__ __forceinline__ int mag_site(const KParams<T> &p, int c, const int *idx, long long &l) {
+    for (int f = 0; f < p.nfilm; f++) {
+        const FilmDev &F = p.films[f];
+        const long long q = film_local_idx(F, idx);
+        if (q >= 0) {
+            if (F.prm[(c * 3) * F.ns + q] > 0.0) {
+                l = q;
+                return f;
+            }
+            return -1;
+        }
+    }
+    l = -1;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// magnetic faces: lambda of (M', H'_c) -> lambda of M (direct), P, Q; the
+// prepass (B^n, B^* of the input state) must have run
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_film(AdjParams<T> A) {
+    const KParams<T> &p = A.p;
+    const int4 bt = p.blocktab[blockIdx.x];
+    const int f = bt.x, c = bt.y;
+    const FilmDev &F = p.films[f];
+    const AdjFilmDev &G = A.af[f];
+    const long long l = (long long)bt.z + threadIdx.x;
+    if (l >= F.ns) return;
+    const double ms = F.prm[(c * 3 + 0) * F.ns + l];
+    const double al = F.prm[(c * 3 + 1) * F.ns + l];
+    const double ga = F.prm[(c * 3 + 2) * F.ns + l];
+    if (!(ms > 0.0)) return;
+    int idx[3];
+    idx[0] = F.b0[0] + (int)(l % F.bn[0]);
+    idx[1] = F.b0[1] + (int)((l / F.bn[0]) % F.bn[1]);
+    idx[2] = F.b0[2] + (int)(l / ((long long)F.bn[0] * F.bn[1]));
+    auto ext = [&](const int *q) -> long long {
+        const int r0 = q[0] - F.e0[0], r1 = q[1] - F.e0[1], r2 = q[2] - F.e0[2];
+        if (r0 < 0 || r0 >= F.en[0] || r1 < 0 || r1 >= F.en[1] || r2 < 0 || r2 >= F.en[2]) return -1;
+        return (long long)r0 + (long long)F.en[0] * ((long long)r1 + (long long)F.en[1] * r2);
+    };
+    // the forward quantities (as the film kernel computes them)
+    const long long le = ext(idx);
+    double P[3], Q[3], M[3];
+    P[c] = le >= 0 ? F.Bs[c * F.nse + le] : 0.0;
+    Q[c] = le >= 0 ? F.Bn[c * F.nse + le] : 0.0;
+    for (int cp = 0; cp < 3; cp++) {
+        if (cp == c) continue;
+        double vn[2][2], vs[2][2];
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int q[3] = {idx[0], idx[1], idx[2]};
+                q[c] += u - 1;
+                q[cp] += v;
+                for (int a = 0; a < 3; a++) q[a] = fold(q[a], p.n[a], p.per[a]);
+                const long long lq = ext(q);
+                vn[u][v] = lq >= 0 ? F.Bn[cp * F.nse + lq] : 0.0;
+                vs[u][v] = lq >= 0 ? F.Bs[cp * F.nse + lq] : 0.0;
+            }
+        Q[cp] = ((vn[0][0] + vn[1][0]) + (vn[0][1] + vn[1][1])) * 0.25;
+        P[cp] = ((vs[0][0] + vs[1][0]) + (vs[0][1] + vs[1][1])) * 0.25;
+    }
+    for (int w = 0; w < 3; w++) {
+        P[w] += p.H0[w];
+        Q[w] += p.H0[w];
+        M[w] = F.M[(c * 3 + w) * F.ns + l];
+    }
+    const double kk = p.kf * ga;
+    double MxQ[3], b[3], a[3];
+    cross3a(M, Q, MxQ);
+    for (int w = 0; w < 3; w++) b[w] = M[w] - kk * MxQ[w];
+    for (int w = 0; w < 3; w++) a[w] = -(kk * P[w] + (al / ms) * M[w]);
+    double axb[3], X[3];
+    cross3a(a, b, axb);
+    const double ab = dot3a(a, b), aa = dot3a(a, a);
+    const double D = 1.0 + aa;
+    for (int w = 0; w < 3; w++) X[w] = (b[w] + ab * a[w] - axb[w]) / D;
+    const double nx = sqrt(dot3a(X, X));
+    double u[3];
+    for (int w = 0; w < 3; w++) u[w] = X[w] / nx;
+
+    // lambda of M' (the face's H' = B^*_c - M'_c contributes -lambda H'_c)
+    const long long sl = p.slot(idx[0], idx[1], idx[2]);
+    double lMt[3];
+    for (int w = 0; w < 3; w++) lMt[w] = G.lM[(c * 3 + w) * F.ns + l];
+    lMt[c] -= (double)A.lH[c][sl];
+    // M' = Ms u, u = X/|X|
+    const double ul = dot3a(u, lMt);
+    double gms = ul;
+    double lX[3];
+    for (int w = 0; w < 3; w++) lX[w] = ms * (lMt[w] - u[w] * ul) / nx;
+    // X = N / D, N = b + (a.b) a - a x b, D = 1 + a.a
+    double lN[3];
+    for (int w = 0; w < 3; w++) lN[w] = lX[w] / D;
+    const double lD = -dot3a(lX, X) / D;
+    const double alN = dot3a(a, lN);
+    double lNxb[3], lNxa[3];
+    cross3a(lN, b, lNxb);
+    cross3a(lN, a, lNxa);
+    double la[3], lb[3];
+    for (int w = 0; w < 3; w++) {
+        la[w] = 2.0 * a[w] * lD + b[w] * alN + ab * lN[w] + lNxb[w];
+        lb[w] = lN[w] + a[w] * alN - lNxa[w];
+    }
+    // a = -(k P + (alpha/Ms) M);  b = M - k M x Q
+    double lP[3], lQ[3], lMd[3], Qxlb[3], lbxM[3];
+    cross3a(Q, lb, Qxlb);
+    cross3a(lb, M, lbxM);
+    for (int w = 0; w < 3; w++) {
+        lP[w] = -kk * la[w];
+        lQ[w] = -kk * lbxM[w];
+        lMd[w] = -(al / ms) * la[w] + lb[w] - kk * Qxlb[w];
+    }
+    gms += (al / (ms * ms)) * dot3a(M, la);
+    for (int w = 0; w < 3; w++) {
+        G.lp[(c * 3 + w) * F.ns + l] = lP[w];
+        G.lq[(c * 3 + w) * F.ns + l] = lQ[w];
+        G.lMout[(c * 3 + w) * F.ns + l] = lMd[w];
+        G.gH0[(c * 3 + w) * F.ns + l] += lP[w] + lQ[w];
+    }
+    G.gMs[c * F.ns + l] += gms;
+}
+
+// ---------------------------------------------------------------------------
+// every face: lambda of H' (and psi') -> lambda of H (and psi), the face's
+// curl-part adjoints aD, and for magnetic faces lambda of M from B^
+// ---------------------------------------------------------------------------
+template <typename T, int C>
+__device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, int k) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const KParams<T> &p = A.p;
+    const int idx[3] = {i, j, k};
+    const long long q = p.slot(i, j, k);
+    const T lHp = A.lH[C][q];
+    long long lm;
+    const int fm = p.nfilm ? mag_site(p, C, idx, lm) : -1;
+    // CPML face (never next to a film)
+    const int a1 = idx[C1], a2 = idx[C2];
+    const bool s1 = p.psiH[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]);
+    const bool s2 = p.psiH[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
+    if (fm < 0 && (s1 || s2)) {
+        const T g1 = -p.hc * lHp, g2 = p.hc * lHp; // d H' / d (d1 + psi1'), d (d2 + psi2')
+        T ad1 = g1, ad2 = g2;
+        if (s1) {
+            const long long qq = p.psi_index(C1, idx);
+            const T aps = A.lpsiH[C][C1][qq] + g1;
+            A.lpsiH[C][C1][qq] = p.bH[C1][a1] * aps;
+            ad1 = g1 + p.cH[C1][a1] * aps;
+        }
+        if (s2) {
+            const long long qq = p.psi_index(C2, idx);
+            const T aps = A.lpsiH[C][C2][qq] + g2;
+            A.lpsiH[C][C2][qq] = p.bH[C2][a2] * aps;
+            ad2 = g2 + p.cH[C2][a2] * aps;
+        }
+        A.aD[C][0][q] = ad1;
+        A.aD[C][1][q] = ad2;
+        return; // lambda H unchanged (dH'/dH = 1)
+    }
+    // lambda of B^* and B^ of this face: from the face's own update and from
+    // the solves of magnetic faces that read it (P, Q of the film kernel)
+    double lbs_f = 0.0, lbn = 0.0;
+    if (fm >= 0) {
+        const FilmDev &F = p.films[fm];
+        const AdjFilmDev &G = A.af[fm];
+        lbs_f += G.lp[(C * 3 + C) * F.ns + lm];
+        lbn += G.lq[(C * 3 + C) * F.ns + lm];
+    }
+    // transverse reads: the magnetic faces s of each other family cs with this
+    // face in their four-face mean: s = t + a e_cs - b e_C, a, b in {0, 1}
+    if (p.nfilm) {
+#pragma unroll
+        for (int cs = 0; cs < 3; cs++) {
+            if (cs == C) continue;
+            for (int aa = 0; aa < 2; aa++)
+                for (int bb = 0; bb < 2; bb++) {
+                    int s[3] = {i, j, k};
+                    s[cs] += aa;
+                    s[C] -= bb;
+                    bool ok = true;
+                    for (int ax = 0; ax < 3; ax++) {
+                        s[ax] = fold(s[ax], p.n[ax], p.per[ax]);
+                        if (s[ax] < 0) ok = false;
+                    }
+                    if (!ok) continue;
+                    long long ls;
+                    const int fs = mag_site(p, cs, s, ls);
+                    if (fs < 0) continue;
+                    const FilmDev &F = p.films[fs];
+                    const AdjFilmDev &G = A.af[fs];
+                    lbs_f += 0.25 * G.lp[(cs * 3 + C) * F.ns + ls];
+                    lbn += 0.25 * G.lq[(cs * 3 + C) * F.ns + ls];
+                }
+        }
+    }
+    if (fm >= 0) {
+        // magnetic face: H' = B^*_C - M'_C, B^* = B^ - hc (d1 - d2) in float64,
+        // B^ = H + M_C
+        const double lbs = (double)lHp + lbs_f;
+        const double lbt = lbn + lbs;
+        A.lH[C][q] = (T)lbt;
+        const FilmDev &F = p.films[fm];
+        const AdjFilmDev &G = A.af[fm];
+        G.lMout[(C * 3 + C) * F.ns + lm] += lbt;
+        A.aD[C][0][q] = (T)(-p.hcd * lbs);
+        A.aD[C][1][q] = (T)(p.hcd * lbs);
+    } else {
+        // bulk face: H' = H - hc (d1 - d2) in the field precision; its B^ and
+        // B^* as read by the solves are H and H - hc (d1 - d2) in float64
+        A.lH[C][q] = (T)((double)lHp + lbn + lbs_f);
+        A.aD[C][0][q] = (T)(-(double)p.hc * (double)lHp - p.hcd * lbs_f);
+        A.aD[C][1][q] = (T)((double)p.hc * (double)lHp + p.hcd * lbs_f);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_face(AdjParams<T> A) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
+    adj_face<T, 0>(A, i, j, k);
+    adj_face<T, 1>(A, i, j, k);
+    adj_face<T, 2>(A, i, j, k);
+}
+
+// magnetic faces: lambda of M before the map (the face kernel has added the
+// B^ part); copies lMout -> lM
+__global__ void __launch_bounds__(256) k_adj_film_commit(const int4 *blocktab, const FilmDev *films,
+                                                         const AdjFilmDev *af) {
+    const int4 bt = blocktab[blockIdx.x];
+    const FilmDev &F = films[bt.x];
+    const AdjFilmDev &G = af[bt.x];
+    const int c = bt.y;
+    const long long l = (long long)bt.z + threadIdx.x;
+    if (l >= F.ns || !(F.prm[(c * 3) * F.ns + l] > 0.0)) return;
+    for (int w = 0; w < 3; w++) G.lM[(c * 3 + w) * F.ns + l] = G.lMout[(c * 3 + w) * F.ns + l];
+}
+
+// face adjoints of a slot (folded; zero outside)
+template <typename T>
+__device__ __forceinline__ T ldD(const KParams<T> &p, const T *a, int i, int j, int k) {
+    return ldz(p, a, i, j, k);
+}
+
+// lambda E += (transposed curl of E) applied to the faces' aD
+template <typename T, int C>
+__device__ __forceinline__ void adj_curlE(const AdjParams<T> &A, int i, int j, int k) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const KParams<T> &p = A.p;
+    // family C+1 (= C1): E_C enters its d1 along C2 ; family C+2 (= C2): its d2 along C1
+    int u1[3] = {i, j, k}, u2[3] = {i, j, k};
+    u1[C2] -= 1;
+    u2[C1] -= 1;
+    const T a1 = ldD(p, A.aD[C1][0], u1[0], u1[1], u1[2]) - ldD(p, A.aD[C1][0], i, j, k);
+    const T a2 = ldD(p, A.aD[C2][1], u2[0], u2[1], u2[2]) - ldD(p, A.aD[C2][1], i, j, k);
+    const long long q = p.slot(i, j, k);
+    A.lE[C][q] = A.lE[C][q] + (dif(a1, T(0), p.dT[C2], p.invd[C2]) + dif(a2, T(0), p.dT[C1], p.invd[C1]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_curlE(AdjParams<T> A) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
+    adj_curlE<T, 0>(A, i, j, k);
+    adj_curlE<T, 1>(A, i, j, k);
+    adj_curlE<T, 2>(A, i, j, k);
+}
+
+// ---------------------------------------------------------------------------
+// E step: lambda E' (and psi') -> lambda E (and psi), the edge's curl-part
+// adjoints eD, and dL/dca, dL/dcb
+// ---------------------------------------------------------------------------
+template <typename T, int C>
+__device__ __forceinline__ void adj_edge(const AdjParams<T> &A, int i, int j, int k, long long step) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const KParams<T> &p = A.p;
+    const long long q = p.slot(i, j, k);
+    int idx[3] = {i, j, k};
+    // coefficients (zero for a PEC or wall edge: E' = 0 does not depend on anything)
+    bool valid = true;
+    for (int a = 0; a < 3; a++)
+        if (!p.per[a] && a != C && idx[a] == 0) valid = false;
+    double ca = 0.0, cb = 0.0;
+    if (valid) {
+        int m[4];
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int cc[3] = {i, j, k};
+                cc[C1] -= 1 - u;
+                cc[C2] -= 1 - v;
+                for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                m[2 * u + v] = p.id[p.slot(cc[0], cc[1], cc[2])];
+            }
+        const MatDev &M0 = p.mat[m[0]], &M1 = p.mat[m[1]], &M2 = p.mat[m[2]], &M3 = p.mat[m[3]];
+        if (M0.is_pec || M1.is_pec || M2.is_pec || M3.is_pec) {
+            valid = false;
+        } else {
+            double se = 0.0, ss = 0.0;
+            se += M0.eps_r;
+            ss += M0.sigma;
+            se += M1.eps_r;
+            ss += M1.sigma;
+            se += M2.eps_r;
+            ss += M2.sigma;
+            se += M3.eps_r;
+            ss += M3.sigma;
+            const double eps = p.eps0 * (se / 4), sig = ss / 4;
+            const double den = sig / 2.0 + eps / p.dt;
+            ca = -(sig / 2.0 - eps / p.dt) / den;
+            cb = 1.0 / den;
+        }
+    }
+    if (!valid) {
+        A.lE[C][q] = T(0);
+        A.eD[C][0][q] = T(0);
+        A.eD[C][1][q] = T(0);
+        return;
+    }
+    // forward quantities: raw curl parts of H, psi', the source
+    int d1i[3] = {i, j, k}, d2i[3] = {i, j, k};
+    d1i[C1] -= 1;
+    d2i[C2] -= 1;
+    T d1 = dif(ldz(p, p.H[C2], i, j, k), ldz(p, p.H[C2], d1i[0], d1i[1], d1i[2]), p.dT[C1], p.invd[C1]);
+    T d2 = dif(ldz(p, p.H[C1], i, j, k), ldz(p, p.H[C1], d2i[0], d2i[1], d2i[2]), p.dT[C2], p.invd[C2]);
+    const int a1 = idx[C1], a2 = idx[C2];
+    const bool s1 = p.psiE[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]);
+    const bool s2 = p.psiE[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
+    long long q1 = 0, q2 = 0;
+    T b1 = T(0), c1 = T(0), b2 = T(0), c2 = T(0);
+    if (s1) {
+        q1 = p.psi_index(C1, idx);
+        b1 = p.bE[C1][a1];
+        c1 = p.cE[C1][a1];
+        d1 += b1 * p.psiE[C][C1][q1] + c1 * d1;
+    }
+    if (s2) {
+        q2 = p.psi_index(C2, idx);
+        b2 = p.bE[C2][a2];
+        c2 = p.cE[C2][a2];
+        d2 += b2 * p.psiE[C][C2][q2] + c2 * d2;
+    }
+    double J = 0.0;
+    for (int s = 0; s < p.nsrc; s++) {
+        const SrcDev &S = p.srcs[s];
+        if (S.comp != C) continue;
+        if (idx[0] < S.box[0] || idx[0] >= S.box[0] + S.box[3] || idx[1] < S.box[1] || idx[1] >= S.box[1] + S.box[4] ||
+            idx[2] < S.box[2] || idx[2] >= S.box[2] + S.box[5])
+            continue;
+        if (step < S.n) J += S.table[step];
+    }
+    const double x = (double)(d1 - d2) - J;
+    const T lEp = A.lE[C][q];
+    A.gca[C][q] += (double)lEp * (double)p.E[C][q];
+    A.gcb[C][q] += (double)lEp * x;
+    const T lx = (T)cb * lEp;
+    A.lE[C][q] = (T)ca * lEp;
+    // x = (d1 + psi1') - (d2 + psi2') - J, psi' = b psi + c d
+    T ad1 = lx, ad2 = -lx;
+    if (s1) {
+        const T aps = A.lpsiE[C][C1][q1] + lx;
+        A.lpsiE[C][C1][q1] = b1 * aps;
+        ad1 = lx + c1 * aps;
+    }
+    if (s2) {
+        const T aps = A.lpsiE[C][C2][q2] - lx;
+        A.lpsiE[C][C2][q2] = b2 * aps;
+        ad2 = -lx + c2 * aps;
+    }
+    A.eD[C][0][q] = ad1;
+    A.eD[C][1][q] = ad2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_estep(AdjParams<T> A) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
+    const long long step = A.p.step[0];
+    adj_edge<T, 0>(A, i, j, k, step);
+    adj_edge<T, 1>(A, i, j, k, step);
+    adj_edge<T, 2>(A, i, j, k, step);
+}
+
+// lambda H += (transposed curl of H) applied to the edges' eD
+template <typename T, int C>
+__device__ __forceinline__ void adj_curlH(const AdjParams<T> &A, int i, int j, int k) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const KParams<T> &p = A.p;
+    // H_C is the H_{C2} of edges E_{C1} (their d1, along C2) and the H_{C1} of
+    // edges E_{C2} (their d2, along C1)
+    int u1[3] = {i, j, k}, u2[3] = {i, j, k};
+    u1[C2] += 1;
+    u2[C1] += 1;
+    const T a1 = ldz(p, A.eD[C1][0], i, j, k) - ldz(p, A.eD[C1][0], u1[0], u1[1], u1[2]);
+    const T a2 = ldz(p, A.eD[C2][1], i, j, k) - ldz(p, A.eD[C2][1], u2[0], u2[1], u2[2]);
+    const long long q = p.slot(i, j, k);
+    A.lH[C][q] = A.lH[C][q] + (dif(a1, T(0), p.dT[C2], p.invd[C2]) + dif(a2, T(0), p.dT[C1], p.invd[C1]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_curlH(AdjParams<T> A) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
+    adj_curlH<T, 0>(A, i, j, k);
+    adj_curlH<T, 1>(A, i, j, k);
+    adj_curlH<T, 2>(A, i, j, k);
+}
+
+// ---------------------------------------------------------------------------
+// the loss: scale * (film EM energy of film f) of the current state -> its
+// gradient added to lambda E, lambda H
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool film_cell(const KParams<T> &p, const FilmDev &F, int i, int j, int k, double &eps) {
+    if (i < F.cb[0] || i >= F.cb[0] + F.cb[3] || j < F.cb[1] || j >= F.cb[1] + F.cb[4] || k < F.cb[2] ||
+        k >= F.cb[2] + F.cb[5])
+        return false;
+    const MatDev &m = p.mat[p.id[p.slot(i, j, k)]];
+    eps = m.eps_r;
+    return m.Ms > 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_loss(AdjParams<T> A, int film, double scale) {
+    const KParams<T> &p = A.p;
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= p.n[0] || j >= p.n[1]) return;
+    const FilmDev &F = p.films[film];
+    const long long q = p.slot(i, j, k);
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        // E_C at the slot: the cells at (C1, C2) offsets -1 / 0
+        double se = 0.0;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int cc[3] = {i, j, k};
+                cc[C1] -= u;
+                cc[C2] -= v;
+                double eps;
+                if (film_cell(p, F, cc[0], cc[1], cc[2], eps)) se += eps;
+            }
+        if (se != 0.0) A.lE[C][q] += (T)(scale * p.dV * p.eps0 * se * 0.25 * (double)p.E[C][q]);
+        // H_C at the slot: the cells at C offsets -1 / 0
+        int nc = 0;
+        for (int u = 0; u < 2; u++) {
+            int cc[3] = {i, j, k};
+            cc[C] -= u;
+            double eps;
+            if (film_cell(p, F, cc[0], cc[1], cc[2], eps)) nc++;
+        }
+        if (nc) A.lH[C][q] += (T)(scale * p.dV * p.mu0 * 0.5 * nc * (double)p.H[C][q]);
+    }
+}
+
+// lambda M of the initial magnetisation M0 = Ms u at every magnetic face ->
+// dL/dMs of the face
+__global__ void __launch_bounds__(256) k_adj_init_ms(const int4 *blocktab, const FilmDev *films,
+                                                     const AdjFilmDev *af, double u0, double u1, double u2) {
+    const int4 bt = blocktab[blockIdx.x];
+    const FilmDev &F = films[bt.x];
+    const AdjFilmDev &G = af[bt.x];
+    const int c = bt.y;
+    const long long l = (long long)bt.z + threadIdx.x;
+    if (l >= F.ns || !(F.prm[(c * 3) * F.ns + l] > 0.0)) return;
+    G.gMs[c * F.ns + l] += G.lM[(c * 3 + 0) * F.ns + l] * u0 + G.lM[(c * 3 + 1) * F.ns + l] * u1 +
+                           G.lM[(c * 3 + 2) * F.ns + l] * u2;
+}
+
+// dL/d eps_r of the cells of a box from the accumulated dL/dca, dL/dcb of
+// the twelve edges around each cell (eps of an edge: eps0 x the mean over
+// its four cells)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_eps(AdjParams<T> A, int4 b0, int4 bn, double *out) {
+    const KParams<T> &p = A.p;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long ncell = (long long)bn.x * bn.y * bn.z;
+    if (t >= ncell) return;
+    const int ci = b0.x + (int)(t % bn.x), cj = b0.y + (int)((t / bn.x) % bn.y), ck = b0.z + (int)(t / ((long long)bn.x * bn.y));
+    double g = 0.0;
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int e[3] = {ci, cj, ck};
+                e[C1] += u;
+                e[C2] += v;
+                for (int a = 0; a < 3; a++) e[a] = fold(e[a], p.n[a], p.per[a]);
+                if (e[0] < 0 || e[1] < 0 || e[2] < 0) continue;
+                bool valid = true;
+                for (int a = 0; a < 3; a++)
+                    if (!p.per[a] && a != C && e[a] == 0) valid = false;
+                if (!valid) continue;
+                int m[4];
+                for (int uu = 0; uu < 2; uu++)
+                    for (int vv = 0; vv < 2; vv++) {
+                        int cc[3] = {e[0], e[1], e[2]};
+                        cc[C1] -= 1 - uu;
+                        cc[C2] -= 1 - vv;
+                        for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                        m[2 * uu + vv] = p.id[p.slot(cc[0], cc[1], cc[2])];
+                    }
+                const MatDev &M0 = p.mat[m[0]], &M1 = p.mat[m[1]], &M2 = p.mat[m[2]], &M3 = p.mat[m[3]];
+                if (M0.is_pec || M1.is_pec || M2.is_pec || M3.is_pec) continue;
+                const double eps = p.eps0 * ((M0.eps_r + M1.eps_r + M2.eps_r + M3.eps_r) / 4);
+                const double sig = (M0.sigma + M1.sigma + M2.sigma + M3.sigma) / 4;
+                const double den = sig / 2.0 + eps / p.dt;
+                // ca = (eps/dt - sig/2)/den, cb = 1/den
+                const double dca = (sig / p.dt) / (den * den), dcb = -(1.0 / p.dt) / (den * den);
+                const long long q = p.slot(e[0], e[1], e[2]);
+                g += (A.gca[C][q] * dca + A.gcb[C][q] * dcb) * (p.eps0 / 4.0);
+            }
+    }
+    out[t] = g;
+}
+
+// the film EM energy of film f in the current state (the film-energy probe's
+// sum): per-block partials, summed on the host in block order
+template <typename T>
+__global__ void __launch_bounds__(256) k_film_energy(KParams<T> p, int film, double *part) {
+    __shared__ double red[256];
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    double w = 0.0;
+    const FilmDev &F = p.films[film];
+    double eps;
+    if (i < p.n[0] && j < p.n[1] && film_cell(p, F, i, j, k, eps)) {
+        const int cc[3] = {i, j, k};
+        double we = 0.0, wh = 0.0;
+        for (int c = 0; c < 3; c++) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            double e2 = 0.0;
+            for (int u = 0; u < 2; u++)
+                for (int v = 0; v < 2; v++) {
+                    int q[3] = {cc[0], cc[1], cc[2]};
+                    q[c1] += u;
+                    q[c2] += v;
+                    const double e = (double)ldz(p, p.E[c], q[0], q[1], q[2]);
+                    e2 += e * e;
+                }
+            we += e2 / 4.0;
+            double h2 = 0.0;
+            for (int u = 0; u < 2; u++) {
+                int q[3] = {cc[0], cc[1], cc[2]};
+                q[c] += u;
+                const double h = (double)ldz(p, p.H[c], q[0], q[1], q[2]);
+                h2 += h * h;
+            }
+            wh += h2 / 2.0;
+        }
+        w = (0.5 * p.eps0 * eps * we + 0.5 * p.mu0 * wh) * p.dV;
+    }
+    red[tid] = w;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = red[0];
+}
+
+__global__ void k_set_step(long long *step, long long v) {
+    if (threadIdx.x == 0) step[0] = v;
+}
+
+// acc += scale * (sum of the partials in order), one thread: deterministic
+__global__ void k_accum(const double *part, int n, double *acc, double scale) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int q = 0; q < n; q++) s += part[q];
+    acc[0] += scale * s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static dim3 slot_grid(const int *n) { return dim3((n[0] + 63) / 64, (n[1] + 3) / 4, n[2]); }
+
+// lambda of the state before a half step from lambda after it; the B^
+// prepass of the input state must have run (launch_film phase-1 prepass)
+template <typename T>
+hipError_t launch_adj_half(const AdjParams<T> &A, int nblk, hipStream_t s) {
+    if (nblk) k_adj_film<T><<<dim3(nblk), dim3(256), 0, s>>>(A);
+    k_adj_face<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    if (nblk) k_adj_film_commit<<<dim3(nblk), dim3(256), 0, s>>>(A.p.blocktab, A.p.films, A.af);
+    k_adj_curlE<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_estep(const AdjParams<T> &A, hipStream_t s) {
+    k_adj_estep<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    k_adj_curlH<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_loss(const AdjParams<T> &A, int film, double scale, hipStream_t s) {
+    k_adj_loss<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A, film, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_init_ms(const int4 *blocktab, int nblk, const FilmDev *films, const AdjFilmDev *af,
+                              const double *u, hipStream_t s) {
+    if (nblk) k_adj_init_ms<<<dim3(nblk), dim3(256), 0, s>>>(blocktab, films, af, u[0], u[1], u[2]);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_film_energy(const KParams<T> &p, int film, double *part, double *acc, double scale, hipStream_t s) {
+    const dim3 g = slot_grid(p.n);
+    k_film_energy<T><<<g, dim3(64, 4), 0, s>>>(p, film, part);
+    k_accum<<<dim3(1), dim3(64), 0, s>>>(part, (int)(g.x * g.y * g.z), acc, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(long long *step, long long v, hipStream_t s) {
+    k_set_step<<<dim3(1), dim3(64), 0, s>>>(step, v);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hipStream_t s) {
+    const long long nc = (long long)box[3] * box[4] * box[5];
+    if (nc == 0) return hipSuccess;
+    k_adj_eps<T><<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s>>>(
+        A, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), out);
+    return hipGetLastError();
+}
+
+#define MPX_ADJ(T)                                                                              \
+    template hipError_t launch_adj_half<T>(const AdjParams<T> &, int, hipStream_t);            \
+    template hipError_t launch_adj_estep<T>(const AdjParams<T> &, hipStream_t);                \
+    template hipError_t launch_adj_loss<T>(const AdjParams<T> &, int, double, hipStream_t);    \
+    template hipError_t launch_adj_eps<T>(const AdjParams<T> &, const int *, double *, hipStream_t);      \
+    template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t);
+MPX_ADJ(float)
+MPX_ADJ(double)
+
+} // namespace mpx

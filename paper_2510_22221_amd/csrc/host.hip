@@ -860,6 +860,358 @@ mpx_status batch_steps(mpx_batch *b, long long nsteps) {
 } // namespace
 
 // ===========================================================================
+// Adjoint: reverse-mode gradients of a film-energy loss
+// ===========================================================================
+namespace {
+
+size_t psi_count(const mpx_sim *s, int a) {
+    const int S = s->nlo[a] + s->nhi[a];
+    return a == 0 ? (size_t)S * s->n[1] * s->n[2]
+                  : a == 1 ? (size_t)s->px * S * s->n[2] : (size_t)s->px * s->n[1] * S;
+}
+
+// a full state at an integer time (the current buffer set of a handle)
+struct Snap {
+    void *E[3] = {}, *H[3] = {}, *psiE[3][3] = {}, *psiH[3][3] = {};
+    std::vector<double *> M;
+    long long step = 0;
+};
+
+void snap_free(Snap &z) {
+    for (int c = 0; c < 3; c++) {
+        (void)hipFree(z.E[c]);
+        (void)hipFree(z.H[c]);
+        for (int a = 0; a < 3; a++) {
+            (void)hipFree(z.psiE[c][a]);
+            (void)hipFree(z.psiH[c][a]);
+        }
+    }
+    for (double *m : z.M) (void)hipFree(m);
+    z = Snap();
+}
+
+mpx_status snap_alloc(mpx_sim *s, Snap &z) {
+    for (int c = 0; c < 3; c++) {
+        CK(hipMalloc(&z.E[c], s->nslot * s->esz));
+        CK(hipMalloc(&z.H[c], s->nslot * s->esz));
+        for (int a = 0; a < 3; a++)
+            if (s->psiE[c][a]) {
+                CK(hipMalloc(&z.psiE[c][a], psi_count(s, a) * s->esz));
+                CK(hipMalloc(&z.psiH[c][a], psi_count(s, a) * s->esz));
+            }
+    }
+    for (auto &f : s->films) {
+        double *m = nullptr;
+        CK(hipMalloc(&m, 9 * f.ns * sizeof(double)));
+        z.M.push_back(m);
+    }
+    return MPX_OK;
+}
+
+// save (handle -> snapshot) or load (snapshot -> handle); e_only: E and its
+// psi only
+mpx_status snap_copy(mpx_sim *s, Snap &z, bool save, bool e_only = false) {
+    hipStream_t st = s->stream;
+    const size_t fb = s->nslot * s->esz;
+    auto cp = [&](void *handle, void *snap, size_t bytes) -> mpx_status {
+        CK(hipMemcpyAsync(save ? snap : handle, save ? handle : snap, bytes, hipMemcpyDeviceToDevice, st));
+        return MPX_OK;
+    };
+    mpx_status r;
+    for (int c = 0; c < 3; c++) {
+        if ((r = cp(Eset(s, s->parity)[c], z.E[c], fb)) != MPX_OK) return r;
+        for (int a = 0; a < 3; a++)
+            if (s->psiE[c][a])
+                if ((r = cp(psiEset(s, s->parity, c, a), z.psiE[c][a], psi_count(s, a) * s->esz)) != MPX_OK) return r;
+    }
+    if (e_only) return MPX_OK;
+    for (int c = 0; c < 3; c++) {
+        if ((r = cp(Hset(s, s->parity)[c], z.H[c], fb)) != MPX_OK) return r;
+        for (int a = 0; a < 3; a++)
+            if (s->psiH[c][a])
+                if ((r = cp(s->psiH[c][a], z.psiH[c][a], psi_count(s, a) * s->esz)) != MPX_OK) return r;
+    }
+    for (size_t f = 0; f < s->films.size(); f++)
+        if ((r = cp(s->films[f].M, z.M[f], 9 * s->films[f].ns * sizeof(double))) != MPX_OK) return r;
+    if (save) {
+        z.step = s->step;
+    } else {
+        s->step = z.step;
+        CK(launch_set_step(s->d_step, z.step, st));
+    }
+    return MPX_OK;
+}
+
+// adjoint arrays
+struct AdjHost {
+    void *lE[3] = {}, *lH[3] = {}, *lpsiE[3][3] = {}, *lpsiH[3][3] = {};
+    void *aD[3][2] = {}, *eD[3][2] = {};
+    double *gca[3] = {}, *gcb[3] = {};
+    std::vector<AdjFilmDev> af;
+    AdjFilmDev *d_af = nullptr;
+    double *d_part = nullptr, *d_loss = nullptr, *d_out = nullptr;
+};
+
+void adj_free(AdjHost &h) {
+    for (int c = 0; c < 3; c++) {
+        (void)hipFree(h.lE[c]);
+        (void)hipFree(h.lH[c]);
+        (void)hipFree(h.gca[c]);
+        (void)hipFree(h.gcb[c]);
+        for (int a = 0; a < 3; a++) {
+            (void)hipFree(h.lpsiE[c][a]);
+            (void)hipFree(h.lpsiH[c][a]);
+        }
+        for (int w = 0; w < 2; w++) {
+            (void)hipFree(h.aD[c][w]);
+            (void)hipFree(h.eD[c][w]);
+        }
+    }
+    for (auto &g : h.af) {
+        (void)hipFree(g.lM);
+        (void)hipFree(g.lMout);
+        (void)hipFree(g.lp);
+        (void)hipFree(g.lq);
+        (void)hipFree(g.gMs);
+        (void)hipFree(g.gH0);
+    }
+    (void)hipFree(h.d_af);
+    (void)hipFree(h.d_part);
+    (void)hipFree(h.d_loss);
+    (void)hipFree(h.d_out);
+    h = AdjHost();
+}
+
+mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout) {
+    const size_t fb = s->nslot * s->esz;
+    auto z = [&](void **p, size_t bytes) -> mpx_status {
+        CK(hipMalloc(p, std::max<size_t>(bytes, 8)));
+        CK(hipMemsetAsync(*p, 0, std::max<size_t>(bytes, 8), s->stream));
+        return MPX_OK;
+    };
+    mpx_status r;
+    for (int c = 0; c < 3; c++) {
+        if ((r = z(&h.lE[c], fb)) != MPX_OK || (r = z(&h.lH[c], fb)) != MPX_OK) return r;
+        if ((r = z((void **)&h.gca[c], s->nslot * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&h.gcb[c], s->nslot * sizeof(double))) != MPX_OK) return r;
+        for (int w = 0; w < 2; w++)
+            if ((r = z(&h.aD[c][w], fb)) != MPX_OK || (r = z(&h.eD[c][w], fb)) != MPX_OK) return r;
+        for (int a = 0; a < 3; a++)
+            if (s->psiE[c][a]) {
+                if ((r = z(&h.lpsiE[c][a], psi_count(s, a) * s->esz)) != MPX_OK) return r;
+                if ((r = z(&h.lpsiH[c][a], psi_count(s, a) * s->esz)) != MPX_OK) return r;
+            }
+    }
+    for (auto &f : s->films) {
+        AdjFilmDev g{};
+        if ((r = z((void **)&g.lM, 9 * f.ns * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&g.lMout, 9 * f.ns * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&g.lp, 9 * f.ns * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&g.lq, 9 * f.ns * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&g.gMs, 3 * f.ns * sizeof(double))) != MPX_OK) return r;
+        if ((r = z((void **)&g.gH0, 9 * f.ns * sizeof(double))) != MPX_OK) return r;
+        h.af.push_back(g);
+    }
+    if (!h.af.empty()) {
+        CK(hipMalloc(&h.d_af, h.af.size() * sizeof(AdjFilmDev)));
+        CK(hipMemcpy(h.d_af, h.af.data(), h.af.size() * sizeof(AdjFilmDev), hipMemcpyHostToDevice));
+    }
+    const long long nb = (long long)((s->n[0] + 63) / 64) * ((s->n[1] + 3) / 4) * s->n[2];
+    if ((r = z((void **)&h.d_part, nb * sizeof(double))) != MPX_OK) return r;
+    if ((r = z((void **)&h.d_loss, sizeof(double))) != MPX_OK) return r;
+    if ((r = z((void **)&h.d_out, std::max<long long>(1, nout) * sizeof(double))) != MPX_OK) return r;
+    return MPX_OK;
+}
+
+template <typename T>
+void adj_params(const mpx_sim *s, const AdjHost &h, AdjParams<T> &A) {
+    fill_params<T>(s, A.p, MODE_INPLACE, s->parity);
+    for (int c = 0; c < 3; c++) {
+        A.lE[c] = (T *)h.lE[c];
+        A.lH[c] = (T *)h.lH[c];
+        A.gca[c] = h.gca[c];
+        A.gcb[c] = h.gcb[c];
+        for (int a = 0; a < 3; a++) {
+            A.lpsiE[c][a] = (T *)h.lpsiE[c][a];
+            A.lpsiH[c][a] = (T *)h.lpsiH[c][a];
+        }
+        for (int w = 0; w < 2; w++) {
+            A.aD[c][w] = (T *)h.aD[c][w];
+            A.eD[c][w] = (T *)h.eD[c][w];
+        }
+    }
+    A.af = h.d_af;
+}
+
+// the bracket half step of the step driver (first H/M half step, in place)
+template <typename T>
+mpx_status half_step_inplace(mpx_sim *s) {
+    KParams<T> p;
+    fill_params<T>(s, p, MODE_INPLACE, s->parity);
+    CK(launch_film<T>(p, s->nblk, 1, 0, s->stream));
+    CK(launch_commit<T>(p, s->nblk, s->stream));
+    CK(launch_hbulk<T>(p, 1, 0, s->stream));
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, int K, const int *eps_box,
+                       const int *ms_box, double *loss, double *gH0, double *geps, double *gms) {
+    hipStream_t st = s->stream;
+    const int saved_fused = s->fused;
+    s->fused = 0; // one step at a time, in place
+    const long long step0 = s->step;
+    const int ncp = (int)((N + K - 1) / K);
+    std::vector<Snap> cp(ncp), seg(K);
+    Snap fin;
+    AdjHost h;
+    const long long neps = (long long)eps_box[3] * eps_box[4] * eps_box[5];
+    mpx_status r = MPX_OK;
+    auto body = [&]() -> mpx_status {
+        mpx_status q;
+        if ((q = adj_alloc(s, h, neps)) != MPX_OK) return q;
+        for (auto &z : cp)
+            if ((q = snap_alloc(s, z)) != MPX_OK) return q;
+        for (int m = 1; m < K; m++)
+            if ((q = snap_alloc(s, seg[m])) != MPX_OK) return q;
+        if ((q = snap_alloc(s, fin)) != MPX_OK) return q;
+        const double dt = s->dt;
+        // forward with checkpoints and the loss
+        for (long long n = 0; n < N; n++) {
+            if (n % K == 0 && (q = snap_copy(s, cp[n / K], true)) != MPX_OK) return q;
+            if ((q = enqueue_steps<T>(s, 1)) != MPX_OK) return q;
+            s->step += 1;
+            if (n + 1 > loss_from) {
+                KParams<T> p;
+                fill_params<T>(s, p, MODE_INPLACE, s->parity);
+                CK(launch_film_energy<T>(p, film, h.d_part, h.d_loss, dt, st));
+            }
+        }
+        if ((q = snap_copy(s, fin, true)) != MPX_OK) return q;
+        CK(hipMemcpyAsync(loss, h.d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        // The adjoint is linear in its seed: seed it with S dL/d(state), S a
+        // power of two near 1/L, so that the adjoint fields sit near unit
+        // scale instead of at the loss's SI magnitude (a float32 run would
+        // otherwise underflow), and divide the gradients by S at the end.
+        // In float64 the scaling is exact.
+        double S = 1.0;
+        if (std::isfinite(*loss) && *loss > 0.0) S = std::ldexp(1.0, -std::ilogb(*loss));
+        // reverse, segment by segment
+        for (int g = ncp - 1; g >= 0; g--) {
+            const long long c0 = (long long)g * K, c1 = std::min<long long>(c0 + K, N);
+            if ((q = snap_copy(s, cp[g], false)) != MPX_OK) return q;
+            for (long long m = 1; m < c1 - c0; m++) {
+                if ((q = enqueue_steps<T>(s, 1)) != MPX_OK) return q;
+                s->step += 1;
+                if ((q = snap_copy(s, seg[m], true)) != MPX_OK) return q;
+            }
+            for (long long n = c1 - 1; n >= c0; n--) {
+                Snap &Sn = n == c0 ? cp[g] : seg[n - c0];
+                Snap &Sp = n + 1 < c1 ? seg[n + 1 - c0] : (g + 1 < ncp ? cp[g + 1] : fin);
+                AdjParams<T> A;
+                if (n + 1 > loss_from) {
+                    if ((q = snap_copy(s, Sp, false)) != MPX_OK) return q;
+                    adj_params<T>(s, h, A);
+                    CK(launch_adj_loss<T>(A, film, dt * S, st));
+                }
+                // the step's intermediate states
+                if ((q = snap_copy(s, Sn, false)) != MPX_OK) return q;
+                if ((q = half_step_inplace<T>(s)) != MPX_OK) return q;
+                {
+                    KParams<T> p;
+                    fill_params<T>(s, p, MODE_INPLACE, s->parity);
+                    CK(launch_epass<T>(p, st));
+                }
+                // second half step: input (E^{n+1}, H^{n+1/2}, M^{n+1/2})
+                adj_params<T>(s, h, A);
+                CK(launch_bhat<T>(A.p, 1, st));
+                CK(launch_adj_half<T>(A, s->nblk, st));
+                // E step: input H^{n+1/2}, E^n and its psi
+                if ((q = snap_copy(s, Sn, false, true)) != MPX_OK) return q;
+                adj_params<T>(s, h, A);
+                CK(launch_adj_estep<T>(A, st));
+                // first half step: input S_n
+                if ((q = snap_copy(s, Sn, false)) != MPX_OK) return q;
+                adj_params<T>(s, h, A);
+                CK(launch_bhat<T>(A.p, 1, st));
+                CK(launch_adj_half<T>(A, s->nblk, st));
+            }
+        }
+        // the initial magnetisation M0 = Ms u
+        if (step0 == 0 && s->have_u)
+            CK(launch_adj_init_ms(s->d_blocktab, s->nblk, s->d_films, h.d_af, s->u, st));
+        // dL/d eps_r over the box
+        {
+            AdjParams<T> A;
+            adj_params<T>(s, h, A);
+            CK(launch_adj_eps<T>(A, eps_box, h.d_out, st));
+            if (neps > 0) CK(hipMemcpyAsync(geps, h.d_out, neps * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        CK(hipStreamSynchronize(st));
+        for (long long t = 0; t < neps; t++) geps[t] /= S;
+        // dL/dH0 and dL/dMs per cell from the films' per-face sums
+        gH0[0] = gH0[1] = gH0[2] = 0.0;
+        std::vector<std::vector<double>> gf(s->films.size());
+        for (size_t f = 0; f < s->films.size(); f++) {
+            const FilmHost &F = s->films[f];
+            std::vector<double> v(9 * F.ns);
+            CK(hipMemcpy(v.data(), h.af[f].gH0, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (int c = 0; c < 3; c++)
+                for (int w = 0; w < 3; w++)
+                    for (long long l = 0; l < F.ns; l++) gH0[w] += v[(c * 3 + w) * F.ns + l] / S;
+            gf[f].resize(3 * F.ns);
+            CK(hipMemcpy(gf[f].data(), h.af[f].gMs, gf[f].size() * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        const long long nms = (long long)ms_box[3] * ms_box[4] * ms_box[5];
+        for (long long t = 0; t < nms; t++) {
+            const int cc[3] = {ms_box[0] + (int)(t % ms_box[3]), ms_box[1] + (int)((t / ms_box[3]) % ms_box[4]),
+                               ms_box[2] + (int)(t / ((long long)ms_box[3] * ms_box[4]))};
+            double g = 0.0;
+            // the cell's two faces of each family: Ms of a face is the mean over
+            // its in-domain cells
+            for (int c = 0; c < 3; c++)
+                for (int u = 0; u < 2; u++) {
+                    int fi[3] = {cc[0], cc[1], cc[2]};
+                    fi[c] += u;
+                    if (fi[c] >= s->n[c]) {
+                        if (!s->per[c]) continue;
+                        fi[c] -= s->n[c];
+                    }
+                    for (size_t f = 0; f < s->films.size(); f++) {
+                        const FilmHost &F = s->films[f];
+                        const int r0 = fi[0] - F.b0[0], r1 = fi[1] - F.b0[1], r2 = fi[2] - F.b0[2];
+                        if (r0 < 0 || r0 >= F.bn[0] || r1 < 0 || r1 >= F.bn[1] || r2 < 0 || r2 >= F.bn[2]) continue;
+                        const long long l = r0 + (long long)F.bn[0] * (r1 + (long long)F.bn[1] * r2);
+                        int cnt = 0;
+                        for (int uu = -1; uu <= 0; uu++) {
+                            int q3[3] = {fi[0], fi[1], fi[2]};
+                            q3[c] += uu;
+                            if (cell_id_h(s, q3[0], q3[1], q3[2]) >= 0) cnt++;
+                        }
+                        if (cnt) g += gf[f][c * F.ns + l] / cnt;
+                        break;
+                    }
+                }
+            gms[t] = g / S;
+        }
+        // leave the handle at the end of the forward run
+        if ((q = snap_copy(s, fin, false)) != MPX_OK) return q;
+        CK(hipStreamSynchronize(st));
+        return MPX_OK;
+    };
+    r = body();
+    s->fused = saved_fused;
+    adj_free(h);
+    for (auto &z : cp) snap_free(z);
+    for (auto &z : seg) snap_free(z);
+    snap_free(fin);
+    return r;
+}
+
+} // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -1597,6 +1949,32 @@ mpx_status mpx_set_schedule(mpx_sim *s, int32_t fused, int32_t kchunk) {
 }
 
 const char *mpx_last_error(const mpx_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+mpx_status mpx_adjoint(mpx_sim *s, int64_t nsteps, int64_t loss_from, int32_t film, int32_t checkpoint_every,
+                       const int32_t eps_box[6], const int32_t ms_box[6], double *loss, double *dL_dH0,
+                       double *dL_deps, double *dL_dMs) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "adjoint before set_materials");
+    if (!s->films.empty() && !s->have_u) return fail(s, MPX_E_STATE, "adjoint before init_magnetization");
+    if (nsteps < 1 || loss_from < 0 || loss_from >= nsteps || film < 0 || film >= (int)s->films.size() ||
+        checkpoint_every < 0 || !eps_box || !ms_box || !loss || !dL_dH0)
+        return fail(s, MPX_E_INVALID, "adjoint arguments");
+    for (int a = 0; a < 3; a++)
+        if (eps_box[3 + a] < 0 || ms_box[3 + a] < 0 || eps_box[a] < 0 || ms_box[a] < 0 ||
+            eps_box[a] + eps_box[3 + a] > s->n[a] || ms_box[a] + ms_box[3 + a] > s->n[a])
+            return fail(s, MPX_E_INVALID, "adjoint box outside the grid");
+    if ((long long)eps_box[3] * eps_box[4] * eps_box[5] > 0 && !dL_deps) return fail(s, MPX_E_INVALID, "dL_deps");
+    if ((long long)ms_box[3] * ms_box[4] * ms_box[5] > 0 && !dL_dMs) return fail(s, MPX_E_INVALID, "dL_dMs");
+    int K = checkpoint_every;
+    if (K == 0) K = std::max(1, (int)std::ceil(std::sqrt((double)nsteps)));
+    K = (int)std::min<int64_t>(K, nsteps);
+    drop_graph(s);
+    r = s->prec == MPX_F64 ? run_adjoint<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
+                           : run_adjoint<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
+    return r;
+}
+
 
 mpx_status mpx_batch_create(mpx_sim *const *sims, int32_t n, mpx_batch **out) {
     if (!sims || n < 1 || !out) return MPX_E_INVALID;

@@ -546,6 +546,14 @@ __global__ void k_sum(const double *part, long long n, double *out) {
 // ---------------------------------------------------------------------------
 // host-side launchers (explicit instantiation for float and double)
 // ---------------------------------------------------------------------------
+// the B^ prepass alone (the adjoint's view of a half step's input)
+template <typename T>
+hipError_t launch_bhat(const KParams<T> &p, int phase, hipStream_t s) {
+    if (p.nblk_ext == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bhat<T>, dim3(p.nblk_ext), dim3(256), 0, s, p, phase);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s) {
     if (nblk == 0) return hipSuccess;
@@ -620,6 +628,7 @@ hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hi
 }
 
 #define MPX_INSTANTIATE(T)                                                                  \
+    template hipError_t launch_bhat<T>(const KParams<T> &, int, hipStream_t);               \
     template hipError_t launch_film<T>(const KParams<T> &, int, int, int, hipStream_t);     \
     template hipError_t launch_commit<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_film_batch<T>(const KParams<T> *, const int2 *, int, const int2 *, int, int, int, \

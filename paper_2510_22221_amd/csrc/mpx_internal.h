@@ -119,6 +119,37 @@ struct KParams {
     }
 };
 
+// adjoint arrays of one film (layouts of FilmDev::M)
+struct AdjFilmDev {
+    double *lM;    // [family][component][site] lambda of M (in: after the map)
+    double *lMout; // [family][component][site] lambda of M before the map
+    double *lp;    // [family][component][site] lambda of P (own and transverse)
+    double *lq;    // the same for Q
+    double *gMs;   // [family][site] accumulated dL/dMs of the face
+    double *gH0;   // [family][component][site] accumulated dL/dH0 parts
+};
+
+template <typename T>
+struct AdjParams {
+    KParams<T> p;          // the map's input state (E, H, psi, film M, prepass)
+    T *lE[3], *lH[3];      // lambda of E and H (in place: after -> before)
+    T *lpsiE[3][3], *lpsiH[3][3];
+    T *aD[3][2];           // per face: lambda of the two curl parts of E
+    T *eD[3][2];           // per edge: lambda of the two curl parts of H
+    double *gca[3], *gcb[3]; // per edge: accumulated dL/dca, dL/dcb
+    const AdjFilmDev *af;
+};
+
+template <typename T> hipError_t launch_adj_half(const AdjParams<T> &A, int nblk, hipStream_t s);
+template <typename T> hipError_t launch_adj_estep(const AdjParams<T> &A, hipStream_t s);
+template <typename T> hipError_t launch_adj_loss(const AdjParams<T> &A, int film, double scale, hipStream_t s);
+template <typename T> hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_film_energy(const KParams<T> &p, int film, double *part, double *acc, double scale, hipStream_t s);
+hipError_t launch_set_step(long long *step, long long v, hipStream_t s);
+template <typename T> hipError_t launch_bhat(const KParams<T> &p, int phase, hipStream_t s);
+hipError_t launch_adj_init_ms(const int4 *blocktab, int nblk, const FilmDev *films, const AdjFilmDev *af,
+                              const double *u, hipStream_t s);
 template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s);
 template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
 template <typename T>

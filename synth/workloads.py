@@ -311,3 +311,58 @@ def scaled_drive(w: Workload, factor: float) -> Workload:
     out.probes = list(w.probes)
     out.name = f"{w.name}, drive x{factor:g}"
     return out
+
+
+# --------------------------------------------------------------------------
+# C4: the adjoint workload (film-energy loss, gradients w.r.t. H0, eps_r of a
+# substrate patch and the film's top-layer Ms)
+# --------------------------------------------------------------------------
+
+def c4_instance(nx: int = 128, ny: int = 64, nz: int = 64, nsteps: int = 20000, npml: int = 8) -> Workload:
+    """C2's stack at (nx, ny, nz), d = (40, 2, 2) um: silicon below k = 20 nz/64,
+    a PEC layer at that height with a 12-cell centre strip (gaps of 8 cells to
+    grounds), the strip a half-wave resonator of 0.75 nx cells, a film of
+    0.5 nx x 12 x 4 cells on it, and an eps_r patch of 0.25 nx x 16 x 4 cells
+    in the substrate under the film centre (its own material id, eps_r 11.7,
+    so that its cells can be perturbed one by one).  H0 along z at the
+    resonator's perpendicular-FMR estimate; a pulse on the feed gaps."""
+    d = (40e-6, 2e-6, 2e-6)
+    dt = config_dt(0.9, d)
+    ids = _empty_ids(nx, ny, nz)
+    kmet = 20 * nz // 64
+    ids[:kmet] = 1
+    yc = ny // 2
+    sw, gw = 12, 8
+    s0, s1 = yc - sw // 2, yc + sw // 2
+    ids[kmet, : s0 - gw, :] = 2
+    ids[kmet, s1 + gw:, :] = 2
+    lres = int(0.75 * nx)
+    x0 = (nx - lres) // 2
+    ids[kmet, s0:s1, : x0 - 2] = 2
+    ids[kmet, s0:s1, x0:x0 + lres] = 2
+    ids[kmet, s0:s1, x0 + lres + 2:] = 2
+    fl = nx // 2
+    fx0 = (nx - fl) // 2
+    ids[kmet + 1:kmet + 5, s0:s1, fx0:fx0 + fl] = 3
+    pw, ph = nx // 4, 16
+    px0, py0 = (nx - pw) // 2, yc - ph // 2
+    ids[kmet - 4:kmet, py0:py0 + ph, px0:px0 + pw] = 4
+    mats = [VACUUM, (11.7, 0.0, 0, 0.0, 0.0, 0.0), PEC_METAL, (1.0, 0.0, 0, 1.4e5, 1e-4, GAMMA),
+            (11.7, 0.0, 0, 0.0, 0.0, 0.0)]
+    f_p = C0 / (2.0 * lres * d[0] * math.sqrt(6.35))
+    H_ac = 2.0 * math.pi * f_p / (4e-7 * math.pi * GAMMA)
+    tp = 1.0 / f_p
+    table = gaussian_pulse(nsteps, dt, 1e6, f_p, tp, 3.0 * tp)
+    srcs = [Source(1, (npml + 1, s0 - gw, kmet, 2, gw, 2), table),
+            Source(1, (npml + 1, s1, kmet, 2, gw, 2), -table)]
+    w = Workload(f"C4 {nx}x{ny}x{nz} resonator + film, eps patch", nx, ny, nz, d, dt, 0.9,
+                 bc=(PML,) * 6, npml=(npml,) * 6, ids=ids, H0=(0.0, 0.0, H_ac),
+                 m_dir=(0.0, 0.0, 1.0), sources=srcs, probes=[Probe("film_energy", film=0)], nsteps=nsteps)
+    w.materials = mats
+    w.patch_box = (px0, py0, kmet - 4, pw, ph, 4)
+    w.film_top = (fx0, s0, kmet + 4, fl, sw, 1)
+    return w
+
+
+def c4(nsteps: int = 20000) -> Workload:
+    return c4_instance(128, 64, 64, nsteps)

@@ -1,0 +1,166 @@
+"""Gradients by the discrete adjoint (mpx_adjoint) against central finite
+differences.
+
+Small cases: the loss and its finite differences come from the FP64 CPU
+oracle (independent of the HIP path); the adjoint gradients must agree within
+1e-5 relative.  The resonator workload at full size (128 x 64 x 64, a few
+hundred steps): finite differences of the GPU forward run.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import fd
+from paper_2510_22221_amd import mpx
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def small_case(pml: bool):
+    w = W.random_case(11, nx=20, ny=16, nz=14, nsteps=60,
+                      bc=(W.PML, W.PML, W.PEC, W.PEC, W.PML, W.PML) if pml else (W.PEC,) * 6,
+                      npml=(2, 2, 0, 0, 2, 2) if pml else (0,) * 6)
+    # a strong bias and a tilted magnetisation: the film's dynamics matter
+    w.H0 = (3e6, 0.0, 5e6)
+    return w
+
+
+def close(a, b, scale):
+    return abs(a - b) <= TOL * scale
+
+
+@pytest.mark.parametrize("pml", [False, True])
+def test_adjoint_matches_oracle_finite_differences(pml):
+    w = small_case(pml)
+    n, n0 = 60, 30
+    film_cells = list(zip(*[a.tolist() for a in np.nonzero(w.ids == 3)]))  # (k, j, i)
+    kf, jf, i_f = film_cells[len(film_cells) // 2]
+    kz0 = min(c[0] for c in film_cells)
+    # eps cells just below the film (random dielectric ids 0/1/4; the loss
+    # itself reads eps_r only inside the film), not PEC
+    eps_box = (i_f - 1, jf - 1, kz0 - 2, 3, 2, 2)
+    ms_box = (i_f, jf, kf, 2, 1, 1)
+    say(f"adjoint small case pml={pml}: GPU")
+    g = mpx.from_workload(w, precision=mpx.F64)
+    res = g.adjoint(n, n0, film=0, eps_box=eps_box, ms_box=ms_box, checkpoint_every=7)
+    L = fd.loss(w, n, n0)
+    say(f"  loss GPU {res['loss']:.15e} oracle {L:.15e}")
+    assert res["loss"] == pytest.approx(L, rel=1e-12)
+    # H0
+    gh = [fd.grad_H0(w, n, n0, c) for c in range(3)]
+    say(f"  dL/dH0 adjoint {res['dH0']} fd {gh}")
+    sc = max(abs(v) for v in gh)
+    for c in range(3):
+        assert close(res["dH0"][c], gh[c], sc), (c, res["dH0"][c], gh[c])
+    # eps_r of a few cells of the box
+    ge = []
+    for (di, dj, dk) in ((0, 0, 0), (1, 1, 1), (2, 0, 1)):
+        cell = (eps_box[0] + di, eps_box[1] + dj, eps_box[2] + dk)
+        if w.materials[int(w.ids[cell[2], cell[1], cell[0]])][2]:
+            continue  # a PEC cell has no eps
+        ge.append((res["deps"][dk, dj, di], fd.grad_eps(w, n, n0, cell)))
+    say(f"  dL/deps (adjoint, fd) {ge}")
+    sc = max(abs(b) for _, b in ge)
+    assert sc > 0
+    for a, b in ge:
+        assert close(a, b, sc), (a, b)
+    # Ms of film cells
+    gm = [(res["dMs"][0, 0, di], fd.grad_Ms(w, n, n0, (ms_box[0] + di, ms_box[1], ms_box[2]))) for di in range(2)]
+    say(f"  dL/dMs (adjoint, fd) {gm}")
+    sc = max(abs(b) for _, b in gm)
+    for a, b in gm:
+        assert close(a, b, sc), (a, b)
+
+
+def test_adjoint_float32_tracks_float64():
+    """The float32 path seeds its adjoint at unit scale (the loss itself is
+    ~1e-29 J s here): its gradients follow the float64 ones to float32's
+    accumulated rounding over the run."""
+    w = small_case(True)
+    n, n0 = 60, 30
+    eps_box = (8, 6, 4, 4, 3, 2)
+    ms_box = (4, 3, 6, 13, 10, 2)
+    out = {}
+    for prec in (mpx.F64, mpx.F32):
+        g = mpx.from_workload(w, precision=prec)
+        out[prec] = g.adjoint(n, n0, film=0, eps_box=eps_box, ms_box=ms_box)
+    a, b = out[mpx.F32], out[mpx.F64]
+    for key in ("dH0", "deps", "dMs"):
+        err = float(np.abs(a[key] - b[key]).max() / np.abs(b[key]).max())
+        say(f"  float32 vs float64 {key}: max error / max |grad| = {err:.2e}")
+        assert err < 1e-3, key
+    assert a["loss"] == pytest.approx(b["loss"], rel=1e-5)
+
+
+def test_adjoint_leaves_the_forward_state():
+    """After mpx_adjoint the handle is where mpx_step(nsteps) leaves it."""
+    w = small_case(False)
+    a = mpx.from_workload(w, precision=mpx.F64)
+    a.adjoint(25, 10, film=0, checkpoint_every=4)
+    b = mpx.from_workload(w, precision=mpx.F64)
+    b.step(25)
+    for f in range(9):
+        assert np.array_equal(a.get(f), b.get(f)), f
+    assert a.info()["step"] == b.info()["step"] == 25
+
+
+def test_adjoint_resonator_full_size_gpu_fd():
+    """The 128 x 64 x 64 resonator, 400 steps, against central differences of
+    the GPU forward run (float64): dL/dH0_z; the sum of dL/deps_r over the
+    eps_r patch (= dL/deps_r of the patch material, all 2048 cells moved
+    together); the sum of dL/dMs over the film (= dL/dMs of the film
+    material, which also moves the initial magnetisation Ms u)."""
+    n, n0 = 400, 200
+    w = W.c4(n)
+    w.m_dir = (0.25, 0.0, 1.0)  # precessing from the start: H0 matters within the run
+    pb = w.patch_box
+    ft = w.film_top
+    film_box = (ft[0], ft[1], ft[2] - 3, ft[3], ft[4], 4)
+    assert np.all(w.ids[film_box[2]:film_box[2] + 4, film_box[1]:film_box[1] + film_box[4],
+                        film_box[0]:film_box[0] + film_box[3]] == 3)
+    say("adjoint C4 full size: adjoint")
+    g = mpx.from_workload(w, precision=mpx.F64)
+    res = g.adjoint(n, n0, film=0, eps_box=pb, ms_box=film_box)
+
+    def gpu_loss(wx):
+        s = mpx.from_workload(wx, precision=mpx.F64)
+        s.step(n)
+        tr = s.read_probe(0, 1)
+        s.close()
+        return wx.dt * float(np.sum(tr[n0:n]))
+
+    def with_material(mid, slot, d):
+        wx = copy.copy(w)
+        mats = list(w.materials)
+        m = list(mats[mid])
+        m[slot] += d
+        mats[mid] = tuple(m)
+        wx.materials = mats
+        return wx
+
+    L = gpu_loss(w)
+    assert res["loss"] == pytest.approx(L, rel=1e-12)
+
+    def h0z(d):
+        wx = copy.copy(w)
+        wx.H0 = (0.0, 0.0, w.H0[2] + d)
+        return gpu_loss(wx)
+    gz = fd.derivative(h0z, 2e-4 * w.H0[2])
+    say(f"  dL/dH0z adjoint {res['dH0'][2]:.9e} fd {gz:.9e}")
+    assert close(res["dH0"][2], gz, abs(gz))
+    gm = fd.derivative(lambda d: gpu_loss(with_material(3, 3, d)), 2e-4 * w.materials[3][3])
+    say(f"  sum dL/dMs adjoint {res['dMs'].sum():.9e} fd {gm:.9e}")
+    assert close(res["dMs"].sum(), gm, abs(gm))
+    # The patch sits under the ground plane, far from the film: the loss moves
+    # by ~1e-11 of itself per 1e-3 of eps_r, while its own rounding noise is
+    # ~1e-15 of itself, so the difference quotient is good to ~1e-4 only.
+    ge = fd.derivative(lambda d: gpu_loss(with_material(4, 0, d)), 2e-3 * w.materials[4][0])
+    say(f"  sum dL/deps adjoint {res['deps'].sum():.9e} fd {ge:.9e}")
+    assert abs(res["deps"].sum() - ge) <= 1e-4 * abs(ge)
