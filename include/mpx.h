@@ -261,15 +261,26 @@ const char *mpx_last_error(const mpx_sim *sim);
  *              solve and, when the run starts at step 0, through the initial
  *              magnetisation M0 = Ms_s u.
  * The forward states are recomputed from checkpoints taken every
- * `checkpoint_every` steps (0: ceil(sqrt(nsteps))), so memory is about
- * (2 sqrt(nsteps) + 10) field states.  On return the handle holds the state
- * after nsteps (step counter advanced, probes recorded as by mpx_step).
+ * `checkpoint_every` steps (0: ceil(sqrt(nsteps))): memory is about
+ * nsteps / checkpoint_every + 12 field states, plus, per step of a segment,
+ * a tape of film-region and eps-box values (schedule 0).  On return the
+ * handle holds the state after nsteps (step counter advanced, probes
+ * recorded as by mpx_step).
  * Host output buffers; boxes must lie inside the grid.  Synchronous.
  * Errors: MPX_E_INVALID (arguments), MPX_E_STATE (materials / magnetisation
  * not set), MPX_E_NOMEM / MPX_E_DEVICE. */
 mpx_status mpx_adjoint(mpx_sim *sim, int64_t nsteps, int64_t loss_from, int32_t film, int32_t checkpoint_every,
                        const int32_t eps_box[6], const int32_t ms_box[6], double *loss, double *dL_dH0,
                        double *dL_deps, double *dL_dMs);
+
+/* Reverse-sweep schedule of mpx_adjoint (same gradients up to rounding):
+ *   0 (default) tape: each checkpoint segment is recomputed once while the
+ *     values the adjoint maps read are taped, then its adjoint steps run
+ *     from the tape (one captured graph replayed per segment);
+ *   1 plain: every reverse step reloads its input state and recomputes its
+ *     half steps (the reference the tape schedule is tested against).
+ * Errors: MPX_E_INVALID for another value. */
+mpx_status mpx_set_adjoint_schedule(mpx_sim *sim, int32_t schedule);
 
 /* ---- Batched stepping (many simulations per launch) --------------------
  *

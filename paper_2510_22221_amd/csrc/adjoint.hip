@@ -164,6 +164,20 @@ __global__ void __launch_bounds__(256) k_adj_film(AdjParams<T> A) {
     G.gMs[c * F.ns + l] += gms;
 }
 
+// can the face at idx be magnetic or be read by a magnetic face's solve (a
+// face within one slot of a film's face box on every non-periodic axis)?
+template <typename T>
+__device__ __forceinline__ bool near_film(const KParams<T> &p, const int *idx) {
+    for (int f = 0; f < p.nfilm; f++) {
+        const FilmDev &F = p.films[f];
+        bool in = true;
+        for (int a = 0; a < 3; a++)
+            if (!p.per[a] && (idx[a] < F.b0[a] - 1 || idx[a] > F.b0[a] + F.bn[a])) in = false;
+        if (in) return true;
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // every face: lambda of H' (and psi') -> lambda of H (and psi), the face's
 // curl-part adjoints aD, and for magnetic faces lambda of M from B^
@@ -175,12 +189,19 @@ __device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, in
     const int idx[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
     const T lHp = A.lH[C][q];
-    long long lm;
-    const int fm = p.nfilm ? mag_site(p, C, idx, lm) : -1;
-    // CPML face (never next to a film)
     const int a1 = idx[C1], a2 = idx[C2];
     const bool s1 = p.psiH[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]);
     const bool s2 = p.psiH[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
+    const bool film_reach = p.nfilm && near_film(p, idx);
+    if (!film_reach && !s1 && !s2) {
+        // bulk face out of every film's reach: H' = H - hc (d1 - d2)
+        A.aD[C][0][q] = -(p.hc * lHp);
+        A.aD[C][1][q] = p.hc * lHp;
+        return; // lambda H unchanged
+    }
+    long long lm;
+    const int fm = film_reach ? mag_site(p, C, idx, lm) : -1;
+    // CPML face (never next to a film)
     if (fm < 0 && (s1 || s2)) {
         const T g1 = -p.hc * lHp, g2 = p.hc * lHp; // d H' / d (d1 + psi1'), d (d2 + psi2')
         T ad1 = g1, ad2 = g2;
@@ -211,7 +232,7 @@ __device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, in
     }
     // transverse reads: the magnetic faces s of each other family cs with this
     // face in their four-face mean: s = t + a e_cs - b e_C, a, b in {0, 1}
-    if (p.nfilm) {
+    if (film_reach) {
 #pragma unroll
         for (int cs = 0; cs < 3; cs++) {
             if (cs == C) continue;
@@ -612,6 +633,331 @@ __global__ void k_accum(const double *part, int n, double *acc, double scale) {
 }
 
 // ---------------------------------------------------------------------------
+// tape schedule
+// ---------------------------------------------------------------------------
+
+// the E-step adjoint without recomputation: the edge's coefficients from the
+// per-slot class byte (the forward's own table) or, in a mixed slot, from its
+// four cells; no forward field is read
+template <typename T, int C>
+__device__ __forceinline__ void adj_edge_lean(const AdjParams<T> &A, int i, int j, int k) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const KParams<T> &p = A.p;
+    const long long q = p.slot(i, j, k);
+    const int idx[3] = {i, j, k};
+    bool valid = true;
+    for (int a = 0; a < 3; a++)
+        if (!p.per[a] && a != C && idx[a] == 0) valid = false;
+    T ca = T(0), cb = T(0);
+    if (valid) {
+        const uint8_t cl = p.cls[q];
+        if (cl != kMixed) {
+            const CoefDev<T> cd = p.coef[cl];
+            if (cd.pec)
+                valid = false;
+            else {
+                ca = cd.ca;
+                cb = cd.cb;
+            }
+        } else {
+            double se = 0.0, ss = 0.0;
+            for (int u = 0; u < 2 && valid; u++)
+                for (int v = 0; v < 2; v++) {
+                    int cc[3] = {i, j, k};
+                    cc[C1] -= 1 - u;
+                    cc[C2] -= 1 - v;
+                    for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                    const MatDev &M = p.mat[p.id[p.slot(cc[0], cc[1], cc[2])]];
+                    if (M.is_pec) {
+                        valid = false;
+                        break;
+                    }
+                    se += M.eps_r;
+                    ss += M.sigma;
+                }
+            if (valid) {
+                const double eps = p.eps0 * (se / 4), sig = ss / 4;
+                const double den = sig / 2.0 + eps / p.dt;
+                ca = (T)(-(sig / 2.0 - eps / p.dt) / den);
+                cb = (T)(1.0 / den);
+            }
+        }
+    }
+    if (!valid) {
+        A.lE[C][q] = T(0);
+        A.eD[C][0][q] = T(0);
+        A.eD[C][1][q] = T(0);
+        return;
+    }
+    const T lEp = A.lE[C][q];
+    const T lx = cb * lEp;
+    A.lE[C][q] = ca * lEp;
+    const int a1 = idx[C1], a2 = idx[C2];
+    T ad1 = lx, ad2 = -lx;
+    if (p.psiE[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1])) {
+        const long long q1 = p.psi_index(C1, idx);
+        const T aps = A.lpsiE[C][C1][q1] + lx;
+        A.lpsiE[C][C1][q1] = p.bE[C1][a1] * aps;
+        ad1 = lx + p.cE[C1][a1] * aps;
+    }
+    if (p.psiE[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2])) {
+        const long long q2 = p.psi_index(C2, idx);
+        const T aps = A.lpsiE[C][C2][q2] - lx;
+        A.lpsiE[C][C2][q2] = p.bE[C2][a2] * aps;
+        ad2 = -lx + p.cE[C2][a2] * aps;
+    }
+    A.eD[C][0][q] = ad1;
+    A.eD[C][1][q] = ad2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_estep_lean(AdjParams<T> A) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
+    adj_edge_lean<T, 0>(A, i, j, k);
+    adj_edge_lean<T, 1>(A, i, j, k);
+    adj_edge_lean<T, 2>(A, i, j, k);
+}
+
+// A region of slots [b0, b0 + r) (a cell box grown by one slot on the high
+// side of each axis: the edges and faces of its cells).  Thread t owns the
+// slot of region index t after folding; a slot that the fold maps onto an
+// index the region already holds (a box spanning a periodic axis) belongs to
+// that index.  Returns false for no slot or a slot owned elsewhere.
+__device__ __forceinline__ bool region_slot(const int *n, const int *per, const int *b0, const int *r, long long t,
+                                            int *q) {
+    const int loc[3] = {(int)(t % r[0]), (int)((t / r[0]) % r[1]), (int)(t / ((long long)r[0] * r[1]))};
+    for (int a = 0; a < 3; a++) {
+        int v = b0[a] + loc[a];
+        if (v >= n[a]) {
+            if (!per[a]) return false;
+            v -= n[a];
+            if (v >= b0[a]) return false;
+        }
+        q[a] = v;
+    }
+    return true;
+}
+
+// region index of the slot e (unfolded, inside [b0, b0 + r) or its wrap), -1
+// for no slot
+__device__ __forceinline__ long long region_index(const int *n, const int *per, const int *b0, const int *r,
+                                                  const int *e) {
+    int loc[3];
+    for (int a = 0; a < 3; a++) {
+        int v = e[a];
+        if (v >= n[a]) {
+            if (!per[a]) return -1;
+            if (v - n[a] >= b0[a]) v -= n[a];
+        }
+        loc[a] = v - b0[a];
+        if (loc[a] < 0 || loc[a] >= r[a]) return -1;
+    }
+    return (long long)loc[0] + (long long)r[0] * ((long long)loc[1] + (long long)r[1] * loc[2]);
+}
+
+// the film's E and H at an integer time over its cell box grown by one slot:
+// [6][region] (Ex, Ey, Ez, Hx, Hy, Hz).  merged = 1: between the two film half
+// steps of a merged pair (magnetic faces' H in the film's staging, bulk faces'
+// H one bulk half step ahead of the stored H); 0: a state at an integer time
+template <typename T>
+__global__ void __launch_bounds__(256) k_tape_loss(KParams<T> p, int film, int merged, double *dst) {
+    const FilmDev &F = p.films[film];
+    const int b0[3] = {F.cb[0], F.cb[1], F.cb[2]}, r[3] = {F.cb[3] + 1, F.cb[4] + 1, F.cb[5] + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= tb) return;
+    int q[3];
+    if (!region_slot(p.n, p.per, b0, r, t, q)) {
+        for (int w = 0; w < 6; w++) dst[w * tb + t] = 0.0;
+        return;
+    }
+    const long long sl = p.slot(q[0], q[1], q[2]);
+    for (int C = 0; C < 3; C++) {
+        dst[C * tb + t] = (double)p.E[C][sl];
+        double h;
+        long long l;
+        const int f = merged && p.nfilm ? mag_site(p, C, q, l) : -1;
+        if (!merged) {
+            h = (double)p.H[C][sl];
+        } else if (f >= 0) {
+            h = p.films[f].H1[C * p.films[f].ns + l];
+        } else {
+            const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+            int u1[3] = {q[0], q[1], q[2]}, u2[3] = {q[0], q[1], q[2]};
+            u1[C1] += 1;
+            u2[C2] += 1;
+            const T d1 = dif(ldz(p, p.E[C2], u1[0], u1[1], u1[2]), p.E[C2][sl], p.dT[C1], p.invd[C1]);
+            const T d2 = dif(ldz(p, p.E[C1], u2[0], u2[1], u2[2]), p.E[C1][sl], p.dT[C2], p.invd[C2]);
+            h = (double)(p.H[C][sl] - p.hc * (d1 - d2));
+        }
+        dst[(3 + C) * tb + t] = h;
+    }
+}
+
+// the loss term of the state a tape slot holds: scale x the gradient of the
+// film EM energy added to lambda E and lambda H; no-op unless the slot's
+// time index seg0 + m is past loss_from (seg0 null: always)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_loss_tape(AdjParams<T> A, int film, double scale, const double *tape,
+                                                       const long long *seg0, int m, long long loss_from) {
+    if (seg0 && seg0[0] + m <= loss_from) return;
+    const KParams<T> &p = A.p;
+    const FilmDev &F = p.films[film];
+    const int b0[3] = {F.cb[0], F.cb[1], F.cb[2]}, r[3] = {F.cb[3] + 1, F.cb[4] + 1, F.cb[5] + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    int q[3];
+    if (t >= tb || !region_slot(p.n, p.per, b0, r, t, q)) return;
+    const long long sl = p.slot(q[0], q[1], q[2]);
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        double se = 0.0, eps;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int cc[3] = {q[0], q[1], q[2]};
+                cc[C1] -= u;
+                cc[C2] -= v;
+                for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) se += eps;
+            }
+        if (se != 0.0) A.lE[C][sl] += (T)(scale * p.dV * p.eps0 * se * 0.25 * tape[C * tb + t]);
+        int nc = 0;
+        for (int u = 0; u < 2; u++) {
+            int cc[3] = {q[0], q[1], q[2]};
+            cc[C] -= u;
+            for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+            if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) nc++;
+        }
+        if (nc) A.lH[C][sl] += (T)(scale * p.dV * p.mu0 * 0.5 * nc * tape[(3 + C) * tb + t]);
+    }
+}
+
+// E^n and x^n = (d1 + psi1') - (d2 + psi2') - J^n (the E update's input, H at
+// n + 1/2) over the edges of a cell box: [6][region] (E0..2, x0..2); taken
+// just before the E pass
+template <typename T>
+__global__ void __launch_bounds__(256) k_tape_box(KParams<T> p, int4 bb, int4 bs, double *dst) {
+    const int b0[3] = {bb.x, bb.y, bb.z}, r[3] = {bs.x + 1, bs.y + 1, bs.z + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= tb) return;
+    int q[3];
+    if (!region_slot(p.n, p.per, b0, r, t, q)) {
+        for (int w = 0; w < 6; w++) dst[w * tb + t] = 0.0;
+        return;
+    }
+    const long long sl = p.slot(q[0], q[1], q[2]);
+    const long long step = p.step[0];
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        int d1i[3] = {q[0], q[1], q[2]}, d2i[3] = {q[0], q[1], q[2]};
+        d1i[C1] -= 1;
+        d2i[C2] -= 1;
+        T d1 = dif(p.H[C2][sl], ldz(p, p.H[C2], d1i[0], d1i[1], d1i[2]), p.dT[C1], p.invd[C1]);
+        T d2 = dif(p.H[C1][sl], ldz(p, p.H[C1], d2i[0], d2i[1], d2i[2]), p.dT[C2], p.invd[C2]);
+        const int a1 = q[C1], a2 = q[C2];
+        if (p.psiE[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1]))
+            d1 += p.bE[C1][a1] * p.psiE[C][C1][p.psi_index(C1, q)] + p.cE[C1][a1] * d1;
+        if (p.psiE[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]))
+            d2 += p.bE[C2][a2] * p.psiE[C][C2][p.psi_index(C2, q)] + p.cE[C2][a2] * d2;
+        double J = 0.0;
+        for (int s = 0; s < p.nsrc; s++) {
+            const SrcDev &S = p.srcs[s];
+            if (S.comp != C) continue;
+            if (q[0] < S.box[0] || q[0] >= S.box[0] + S.box[3] || q[1] < S.box[1] || q[1] >= S.box[1] + S.box[4] ||
+                q[2] < S.box[2] || q[2] >= S.box[2] + S.box[5])
+                continue;
+            if (step < S.n) J += S.table[step];
+        }
+        dst[C * tb + t] = (double)p.E[C][sl];
+        dst[(3 + C) * tb + t] = (double)(d1 - d2) - J;
+    }
+}
+
+// dL/dca += lambda E' E^n, dL/dcb += lambda E' x^n over the box's edges (run
+// before the E-step adjoint replaces lambda E' by lambda E)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_box(AdjParams<T> A, int4 bb, int4 bs, const double *tape, double *gca,
+                                                 double *gcb) {
+    const KParams<T> &p = A.p;
+    const int b0[3] = {bb.x, bb.y, bb.z}, r[3] = {bs.x + 1, bs.y + 1, bs.z + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    int q[3];
+    if (t >= tb || !region_slot(p.n, p.per, b0, r, t, q)) return;
+    const long long sl = p.slot(q[0], q[1], q[2]);
+    for (int C = 0; C < 3; C++) {
+        const double l = (double)A.lE[C][sl];
+        gca[C * tb + t] += l * tape[C * tb + t];
+        gcb[C * tb + t] += l * tape[(3 + C) * tb + t];
+    }
+}
+
+// dL/d eps_r of the box's cells from the box accumulators (eps of an edge:
+// eps0 x the mean over its four cells)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_eps_box(KParams<T> p, int4 bb, int4 bs, const double *gca,
+                                                     const double *gcb, double *out) {
+    const int b0[3] = {bb.x, bb.y, bb.z}, r[3] = {bs.x + 1, bs.y + 1, bs.z + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long ncell = (long long)bs.x * bs.y * bs.z;
+    if (t >= ncell) return;
+    const int cell[3] = {bb.x + (int)(t % bs.x), bb.y + (int)((t / bs.x) % bs.y),
+                         bb.z + (int)(t / ((long long)bs.x * bs.y))};
+    double g = 0.0;
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int e[3] = {cell[0], cell[1], cell[2]};
+                e[C1] += u;
+                e[C2] += v;
+                const long long ri = region_index(p.n, p.per, b0, r, e);
+                if (ri < 0) continue;
+                int f[3];
+                for (int a = 0; a < 3; a++) f[a] = fold(e[a], p.n[a], p.per[a]);
+                bool valid = true;
+                for (int a = 0; a < 3; a++)
+                    if (!p.per[a] && a != C && f[a] == 0) valid = false;
+                if (!valid) continue;
+                double se = 0.0, ss = 0.0;
+                bool pec = false;
+                for (int uu = 0; uu < 2; uu++)
+                    for (int vv = 0; vv < 2; vv++) {
+                        int cc[3] = {f[0], f[1], f[2]};
+                        cc[C1] -= 1 - uu;
+                        cc[C2] -= 1 - vv;
+                        for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                        const MatDev &M = p.mat[p.id[p.slot(cc[0], cc[1], cc[2])]];
+                        pec = pec || M.is_pec;
+                        se += M.eps_r;
+                        ss += M.sigma;
+                    }
+                if (pec) continue;
+                const double eps = p.eps0 * (se / 4), sig = ss / 4;
+                const double den = sig / 2.0 + eps / p.dt;
+                const double dca = (sig / p.dt) / (den * den), dcb = -(1.0 / p.dt) / (den * den);
+                g += (gca[C * tb + ri] * dca + gcb[C * tb + ri] * dcb) * (p.eps0 / 4.0);
+            }
+    }
+    out[t] = g;
+}
+
+__global__ void __launch_bounds__(256) k_copy_segs(const CopySeg *segs) {
+    const CopySeg S = segs[blockIdx.y];
+    const long long n16 = S.bytes >> 4;
+    const uint4 *src = (const uint4 *)S.src;
+    uint4 *dst = (uint4 *)S.dst;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n16; t += stride) dst[t] = src[t];
+    const long long rem = (S.bytes - (n16 << 4)) >> 2;
+    if (blockIdx.x == 0 && threadIdx.x < rem)
+        ((uint32_t *)S.dst)[n16 * 4 + threadIdx.x] = ((const uint32_t *)S.src)[n16 * 4 + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static dim3 slot_grid(const int *n) { return dim3((n[0] + 63) / 64, (n[1] + 3) / 4, n[2]); }
@@ -668,12 +1014,90 @@ hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hi
     return hipGetLastError();
 }
 
+long long film_tape_size(const int *cb) { return 6LL * (cb[3] + 1) * (cb[4] + 1) * (cb[5] + 1); }
+long long box_tape_size(const int *box) { return 6LL * (box[3] + 1) * (box[4] + 1) * (box[5] + 1); }
+
+template <typename T>
+hipError_t launch_adj_half_tape(const AdjParams<T> &A, int nblk, hipStream_t s) {
+    if (nblk) k_adj_film<T><<<dim3(nblk), dim3(256), 0, s>>>(A);
+    k_adj_face<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    k_adj_curlE<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_estep_lean(const AdjParams<T> &A, hipStream_t s) {
+    k_adj_estep_lean<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    k_adj_curlH<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+// cb: the film's cell box (it sizes the grid)
+template <typename T>
+hipError_t launch_tape_loss(const KParams<T> &p, int film, int merged, double *dst, hipStream_t s, const int *cb) {
+    const long long tb = film_tape_size(cb) / 6;
+    k_tape_loss<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(p, film, merged, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_loss_tape(const AdjParams<T> &A, int film, double scale, const double *tape,
+                                const long long *seg0, int m, long long loss_from, hipStream_t s, const int *cb) {
+    const long long tb = film_tape_size(cb) / 6;
+    k_adj_loss_tape<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(A, film, scale, tape, seg0, m,
+                                                                               loss_from);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tape_box(const KParams<T> &p, const int *box, double *dst, hipStream_t s) {
+    const long long tb = box_tape_size(box) / 6;
+    k_tape_box<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(
+        p, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_box(const AdjParams<T> &A, const int *box, const double *tape, double *gca, double *gcb,
+                          hipStream_t s) {
+    const long long tb = box_tape_size(box) / 6;
+    k_adj_box<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(
+        A, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), tape, gca, gcb);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double *gca, const double *gcb, double *out,
+                              hipStream_t s) {
+    const long long nc = (long long)box[3] * box[4] * box[5];
+    if (nc == 0) return hipSuccess;
+    k_adj_eps_box<T><<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s>>>(
+        p, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), gca, gcb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s) {
+    if (nseg == 0) return hipSuccess;
+    k_copy_segs<<<dim3(nblk, nseg), dim3(256), 0, s>>>(segs);
+    return hipGetLastError();
+}
+
 #define MPX_ADJ(T)                                                                              \
     template hipError_t launch_adj_half<T>(const AdjParams<T> &, int, hipStream_t);            \
     template hipError_t launch_adj_estep<T>(const AdjParams<T> &, hipStream_t);                \
     template hipError_t launch_adj_loss<T>(const AdjParams<T> &, int, double, hipStream_t);    \
     template hipError_t launch_adj_eps<T>(const AdjParams<T> &, const int *, double *, hipStream_t);      \
-    template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t);
+    template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t); \
+    template hipError_t launch_adj_half_tape<T>(const AdjParams<T> &, int, hipStream_t);                        \
+    template hipError_t launch_adj_estep_lean<T>(const AdjParams<T> &, hipStream_t);                            \
+    template hipError_t launch_tape_loss<T>(const KParams<T> &, int, int, double *, hipStream_t, const int *);   \
+    template hipError_t launch_adj_loss_tape<T>(const AdjParams<T> &, int, double, const double *,              \
+                                                const long long *, int, long long, hipStream_t, const int *);   \
+    template hipError_t launch_tape_box<T>(const KParams<T> &, const int *, double *, hipStream_t);             \
+    template hipError_t launch_adj_box<T>(const AdjParams<T> &, const int *, const double *, double *, double *, \
+                                          hipStream_t);                                                         \
+    template hipError_t launch_adj_eps_box<T>(const KParams<T> &, const int *, const double *, const double *,   \
+                                              double *, hipStream_t);
 MPX_ADJ(float)
 MPX_ADJ(double)
 

@@ -64,6 +64,7 @@ struct mpx_sim {
     void *H2[3] = {nullptr, nullptr, nullptr};
     int parity = 0;
     int fused = 0; // separate passes (the fastest schedule measured on gfx950)
+    int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
     int kchunk = 16;
     void *d_coef = nullptr;
     // materials
@@ -93,6 +94,7 @@ struct mpx_sim {
     std::vector<SrcHost> srcs;
     std::vector<ProbeHost> probes;
     ProbeDev *d_probes = nullptr;
+    int probe_maxpart = 0; // most partial-sum blocks of a film-energy probe
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
     int4 *d_mixed = nullptr;     // slots whose eight cells do not share one id
@@ -469,7 +471,7 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
         if ((r = rec(1, 1)) != MPX_OK) return r;
         if ((r = rec(2, 0)) != MPX_OK) return r;
         CK(launch_film<T>(pb, nblk, 1, 0, st));
-        CK(launch_probes<T>(pb, np, st));
+        CK(launch_probes<T>(pb, np, s->probe_maxpart, st));
         if (nblk)
             CK(launch_film<T>(pb, nblk, 2, 1, st));
         else
@@ -487,7 +489,7 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
     if ((r = rec(0, 1)) != MPX_OK) return r;
     if ((r = rec(2, 0)) != MPX_OK) return r;
     CK(launch_film<T>(p, nblk, 1, 0, st));
-    CK(launch_probes<T>(p, np, st));
+    CK(launch_probes<T>(p, np, s->probe_maxpart, st));
     CK(launch_film<T>(p, nblk, 2, 0, st));
     if ((r = rec(2, 1)) != MPX_OK) return r;
     if ((r = rec(1, 0)) != MPX_OK) return r;
@@ -504,7 +506,7 @@ mpx_status run_last(mpx_sim *s, int par, hipStream_t st = nullptr) {
     if (!st) st = s->stream;
     CK(launch_epass<T>(p, st));
     CK(launch_film<T>(p, s->nblk, 1, 0, st));
-    CK(launch_probes<T>(p, (int)s->probes.size(), st));
+    CK(launch_probes<T>(p, (int)s->probes.size(), s->probe_maxpart, st));
     CK(launch_commit<T>(p, s->nblk, st));
     CK(launch_hbulk<T>(p, 1, 1, st));
     return MPX_OK;
@@ -625,6 +627,8 @@ mpx_status update_pass_flags(mpx_sim *s) {
 mpx_status upload_probes(mpx_sim *s) {
     (void)hipFree(s->d_probes);
     s->d_probes = nullptr;
+    s->probe_maxpart = 0;
+    for (auto &pr : s->probes) s->probe_maxpart = std::max<int>(s->probe_maxpart, (int)pr.dev.npart);
     if (s->probes.empty()) return MPX_OK;
     std::vector<ProbeDev> v;
     for (auto &pr : s->probes) v.push_back(pr.dev);
@@ -655,6 +659,7 @@ struct mpx_batch {
     int nwmixed = 0;
     int2 *d_wfilm = nullptr, *d_wext = nullptr, *d_wprobe = nullptr;
     int nwfilm = 0, nwext = 0, nwprobe = 0;
+    int probe_maxpart = 0;
     int *d_tick = nullptr;
     int ntick = 0;
     int graph_steps = 64;
@@ -713,6 +718,8 @@ mpx_status batch_tables(mpx_batch *b) {
         for (int k = 0; k < (int)s->probes.size(); k++) wprobe.push_back(make_int2(q, k));
         if (s->nblk == 0) tick.push_back(q);
     }
+    b->probe_maxpart = 0;
+    for (const mpx_sim *s : b->sims) b->probe_maxpart = std::max(b->probe_maxpart, s->probe_maxpart);
     (void)hipFree(b->d_work);
     (void)hipFree(b->d_work2);
     (void)hipFree(b->d_wmixed);
@@ -787,7 +794,7 @@ mpx_status batch_body(mpx_batch *b, int f) {
         // moves every instance's step counter)
         BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, b->d_wmixed, b->nwmixed, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
-        BCK(launch_probes_batch<T>(pa, b->d_wprobe, b->nwprobe, st));
+        BCK(launch_probes_batch<T>(pa, b->d_wprobe, b->nwprobe, b->probe_maxpart, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 0, st));
         BCK(launch_hbulk_batch<T>(pa, b->d_work2, b->nwork2, 2, 1, st));
         return MPX_OK;
@@ -797,7 +804,7 @@ mpx_status batch_body(mpx_batch *b, int f) {
     else
         BCK(launch_fused_batch<T>(pa, b->d_work, b->nwork, b->variant - 1, st));
     BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
-    BCK(launch_probes_batch<T>(pb, b->d_wprobe, b->nwprobe, st));
+    BCK(launch_probes_batch<T>(pb, b->d_wprobe, b->nwprobe, b->probe_maxpart, st));
     BCK(launch_film_batch<T>(pb, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 1, st));
     BCK(launch_tick_batch<T>(pb, b->d_tick, b->ntick, st));
     return MPX_OK;
@@ -949,7 +956,10 @@ struct AdjHost {
     double *gca[3] = {}, *gcb[3] = {};
     std::vector<AdjFilmDev> af;
     AdjFilmDev *d_af = nullptr;
+    AdjFilmDev *d_af2 = nullptr; // tape schedule: lM and lMout swapped
     double *d_part = nullptr, *d_loss = nullptr, *d_out = nullptr;
+    double *gbox_a = nullptr, *gbox_b = nullptr; // tape schedule: dL/dca, dL/dcb over the eps box's edges
+    long long *d_seg0 = nullptr;                 // tape schedule: first step of the segment in hand
 };
 
 void adj_free(AdjHost &h) {
@@ -976,13 +986,17 @@ void adj_free(AdjHost &h) {
         (void)hipFree(g.gH0);
     }
     (void)hipFree(h.d_af);
+    (void)hipFree(h.d_af2);
+    (void)hipFree(h.gbox_a);
+    (void)hipFree(h.gbox_b);
+    (void)hipFree(h.d_seg0);
     (void)hipFree(h.d_part);
     (void)hipFree(h.d_loss);
     (void)hipFree(h.d_out);
     h = AdjHost();
 }
 
-mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout) {
+mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout, bool full_eps = true) {
     const size_t fb = s->nslot * s->esz;
     auto z = [&](void **p, size_t bytes) -> mpx_status {
         CK(hipMalloc(p, std::max<size_t>(bytes, 8)));
@@ -992,8 +1006,10 @@ mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout) {
     mpx_status r;
     for (int c = 0; c < 3; c++) {
         if ((r = z(&h.lE[c], fb)) != MPX_OK || (r = z(&h.lH[c], fb)) != MPX_OK) return r;
-        if ((r = z((void **)&h.gca[c], s->nslot * sizeof(double))) != MPX_OK) return r;
-        if ((r = z((void **)&h.gcb[c], s->nslot * sizeof(double))) != MPX_OK) return r;
+        if (full_eps) {
+            if ((r = z((void **)&h.gca[c], s->nslot * sizeof(double))) != MPX_OK) return r;
+            if ((r = z((void **)&h.gcb[c], s->nslot * sizeof(double))) != MPX_OK) return r;
+        }
         for (int w = 0; w < 2; w++)
             if ((r = z(&h.aD[c][w], fb)) != MPX_OK || (r = z(&h.eD[c][w], fb)) != MPX_OK) return r;
         for (int a = 0; a < 3; a++)
@@ -1051,6 +1067,56 @@ mpx_status half_step_inplace(mpx_sim *s) {
     CK(launch_film<T>(p, s->nblk, 1, 0, s->stream));
     CK(launch_commit<T>(p, s->nblk, s->stream));
     CK(launch_hbulk<T>(p, 1, 0, s->stream));
+    return MPX_OK;
+}
+
+// dL/dH0 and dL/dMs per cell of ms_box from the films' per-face sums (seed
+// scale S divided out)
+mpx_status film_grads(mpx_sim *s, const AdjHost &h, double S, const int *ms_box, double *gH0, double *gms) {
+    gH0[0] = gH0[1] = gH0[2] = 0.0;
+    std::vector<std::vector<double>> gf(s->films.size());
+    for (size_t f = 0; f < s->films.size(); f++) {
+        const FilmHost &F = s->films[f];
+        std::vector<double> v(9 * F.ns);
+        CK(hipMemcpy(v.data(), h.af[f].gH0, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int c = 0; c < 3; c++)
+            for (int w = 0; w < 3; w++)
+                for (long long l = 0; l < F.ns; l++) gH0[w] += v[(c * 3 + w) * F.ns + l] / S;
+        gf[f].resize(3 * F.ns);
+        CK(hipMemcpy(gf[f].data(), h.af[f].gMs, gf[f].size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    const long long nms = (long long)ms_box[3] * ms_box[4] * ms_box[5];
+    for (long long t = 0; t < nms; t++) {
+        const int cc[3] = {ms_box[0] + (int)(t % ms_box[3]), ms_box[1] + (int)((t / ms_box[3]) % ms_box[4]),
+                           ms_box[2] + (int)(t / ((long long)ms_box[3] * ms_box[4]))};
+        double g = 0.0;
+        // the cell's two faces of each family: Ms of a face is the mean over
+        // its in-domain cells
+        for (int c = 0; c < 3; c++)
+            for (int u = 0; u < 2; u++) {
+                int fi[3] = {cc[0], cc[1], cc[2]};
+                fi[c] += u;
+                if (fi[c] >= s->n[c]) {
+                    if (!s->per[c]) continue;
+                    fi[c] -= s->n[c];
+                }
+                for (size_t f = 0; f < s->films.size(); f++) {
+                    const FilmHost &F = s->films[f];
+                    const int r0 = fi[0] - F.b0[0], r1 = fi[1] - F.b0[1], r2 = fi[2] - F.b0[2];
+                    if (r0 < 0 || r0 >= F.bn[0] || r1 < 0 || r1 >= F.bn[1] || r2 < 0 || r2 >= F.bn[2]) continue;
+                    const long long l = r0 + (long long)F.bn[0] * (r1 + (long long)F.bn[1] * r2);
+                    int cnt = 0;
+                    for (int uu = -1; uu <= 0; uu++) {
+                        int q3[3] = {fi[0], fi[1], fi[2]};
+                        q3[c] += uu;
+                        if (cell_id_h(s, q3[0], q3[1], q3[2]) >= 0) cnt++;
+                    }
+                    if (cnt) g += gf[f][c * F.ns + l] / cnt;
+                    break;
+                }
+            }
+        gms[t] = g / S;
+    }
     return MPX_OK;
 }
 
@@ -1150,51 +1216,7 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
         }
         CK(hipStreamSynchronize(st));
         for (long long t = 0; t < neps; t++) geps[t] /= S;
-        // dL/dH0 and dL/dMs per cell from the films' per-face sums
-        gH0[0] = gH0[1] = gH0[2] = 0.0;
-        std::vector<std::vector<double>> gf(s->films.size());
-        for (size_t f = 0; f < s->films.size(); f++) {
-            const FilmHost &F = s->films[f];
-            std::vector<double> v(9 * F.ns);
-            CK(hipMemcpy(v.data(), h.af[f].gH0, v.size() * sizeof(double), hipMemcpyDeviceToHost));
-            for (int c = 0; c < 3; c++)
-                for (int w = 0; w < 3; w++)
-                    for (long long l = 0; l < F.ns; l++) gH0[w] += v[(c * 3 + w) * F.ns + l] / S;
-            gf[f].resize(3 * F.ns);
-            CK(hipMemcpy(gf[f].data(), h.af[f].gMs, gf[f].size() * sizeof(double), hipMemcpyDeviceToHost));
-        }
-        const long long nms = (long long)ms_box[3] * ms_box[4] * ms_box[5];
-        for (long long t = 0; t < nms; t++) {
-            const int cc[3] = {ms_box[0] + (int)(t % ms_box[3]), ms_box[1] + (int)((t / ms_box[3]) % ms_box[4]),
-                               ms_box[2] + (int)(t / ((long long)ms_box[3] * ms_box[4]))};
-            double g = 0.0;
-            // the cell's two faces of each family: Ms of a face is the mean over
-            // its in-domain cells
-            for (int c = 0; c < 3; c++)
-                for (int u = 0; u < 2; u++) {
-                    int fi[3] = {cc[0], cc[1], cc[2]};
-                    fi[c] += u;
-                    if (fi[c] >= s->n[c]) {
-                        if (!s->per[c]) continue;
-                        fi[c] -= s->n[c];
-                    }
-                    for (size_t f = 0; f < s->films.size(); f++) {
-                        const FilmHost &F = s->films[f];
-                        const int r0 = fi[0] - F.b0[0], r1 = fi[1] - F.b0[1], r2 = fi[2] - F.b0[2];
-                        if (r0 < 0 || r0 >= F.bn[0] || r1 < 0 || r1 >= F.bn[1] || r2 < 0 || r2 >= F.bn[2]) continue;
-                        const long long l = r0 + (long long)F.bn[0] * (r1 + (long long)F.bn[1] * r2);
-                        int cnt = 0;
-                        for (int uu = -1; uu <= 0; uu++) {
-                            int q3[3] = {fi[0], fi[1], fi[2]};
-                            q3[c] += uu;
-                            if (cell_id_h(s, q3[0], q3[1], q3[2]) >= 0) cnt++;
-                        }
-                        if (cnt) g += gf[f][c * F.ns + l] / cnt;
-                        break;
-                    }
-                }
-            gms[t] = g / S;
-        }
+        if ((q = film_grads(s, h, S, ms_box, gH0, gms)) != MPX_OK) return q;
         // leave the handle at the end of the forward run
         if ((q = snap_copy(s, fin, false)) != MPX_OK) return q;
         CK(hipStreamSynchronize(st));
@@ -1206,6 +1228,406 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
     for (auto &z : cp) snap_free(z);
     for (auto &z : seg) snap_free(z);
     snap_free(fin);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// tape schedule
+//
+// Forward: the plain stepping path (merged pairs, graphs) with a temporary
+// film-energy probe for the loss and a full snapshot every K steps.
+// Reverse, segment by segment: reload the segment's snapshot, recompute its
+// steps once with the merged-pair kernels while writing a tape of what the
+// adjoint maps read (the film's M and prepass values of both half steps, the
+// film region's E and H at each integer time, E^n and the curl input x^n over
+// the eps box), then run the adjoint maps of the segment's steps backwards
+// from the tape: no forward work and no full-state copy inside the reverse
+// sweep.  Every full segment launches the same kernels with the same
+// arguments (the tape is reused; the step index lives on the device), so one
+// captured graph serves them all.
+// ---------------------------------------------------------------------------
+
+// a full state at an integer time in one allocation, and its copy tables
+struct Snap2 {
+    char *buf = nullptr;
+    long long step = 0;
+};
+
+struct SnapLayout {
+    std::vector<void *> handle; // handle-side arrays, in layout order
+    std::vector<size_t> off, bytes;
+    std::vector<int> film_of;   // film index of an M segment, -1 otherwise
+    size_t total = 0;
+    int nblk = 1;
+};
+
+SnapLayout snap_layout(const mpx_sim *s) {
+    SnapLayout L;
+    auto add = [&](void *h, size_t b, int f) {
+        L.handle.push_back(h);
+        L.off.push_back(L.total);
+        L.bytes.push_back(b);
+        L.film_of.push_back(f);
+        L.total += (b + 255) / 256 * 256;
+        L.nblk = std::max<int>(L.nblk, (int)std::min<size_t>(2048, (b / 16 + 255) / 256));
+    };
+    const size_t fb = s->nslot * s->esz;
+    for (int c = 0; c < 3; c++) add(Eset(s, s->parity)[c], fb, -1);
+    for (int c = 0; c < 3; c++) add(Hset(s, s->parity)[c], fb, -1);
+    for (int c = 0; c < 3; c++)
+        for (int a = 0; a < 3; a++)
+            if (s->psiE[c][a]) {
+                add(psiEset(s, s->parity, c, a), psi_count(s, a) * s->esz, -1);
+                add(s->psiH[c][a], psi_count(s, a) * s->esz, -1);
+            }
+    for (size_t f = 0; f < s->films.size(); f++) add(s->films[f].M, 9 * s->films[f].ns * sizeof(double), (int)f);
+    return L;
+}
+
+struct Tape {
+    int K = 0, nf = 0;
+    char *buf = nullptr;
+    std::vector<double *> Mf, Mh, B1s, B1n, B2s, B2n; // [f][slot]
+    double *loss = nullptr, *box = nullptr;
+    long long loss_sz = 0, box_sz = 0;
+    FilmDev *d_var = nullptr;
+    CopySeg *d_tab = nullptr; // copy tables: per snapshot save, load, load-to-tape
+    int nseg = 0;
+    double *lossp(int m) const { return loss + (size_t)m * loss_sz; }
+    double *boxp(int m) const { return box + (size_t)m * box_sz; }
+};
+enum { V_P1 = 0, V_P2, V_C, V_R1, V_BR, V_BRC, NV };
+
+void tape_free(Tape &t) {
+    (void)hipFree(t.buf);
+    (void)hipFree(t.d_var);
+    (void)hipFree(t.d_tab);
+    t = Tape();
+}
+
+mpx_status tape_alloc(mpx_sim *s, Tape &t, int K, const int *film_cb, const int *eps_box) {
+    t.K = K;
+    t.nf = (int)s->films.size();
+    const int nf = t.nf;
+    t.loss_sz = film_tape_size(film_cb);
+    t.box_sz = (long long)eps_box[3] * eps_box[4] * eps_box[5] > 0 ? box_tape_size(eps_box) : 0;
+    // layout: per film the M slots (K + 1 integer-time, K half-time) and the
+    // prepass slots, then the loss and box tapes
+    size_t off = 0;
+    std::vector<size_t> o;
+    auto put = [&](size_t bytes) {
+        o.push_back(off);
+        off += (bytes + 255) / 256 * 256;
+    };
+    for (int f = 0; f < nf; f++) {
+        const FilmHost &F = s->films[f];
+        for (int m = 0; m <= K; m++) put(9 * F.ns * sizeof(double));
+        for (int m = 0; m < K; m++) put(9 * F.ns * sizeof(double));
+        for (int m = 0; m < K; m++)
+            for (int w = 0; w < 4; w++) put(3 * F.nse * sizeof(double));
+    }
+    put((size_t)K * t.loss_sz * sizeof(double));
+    put((size_t)std::max<long long>(1, K * t.box_sz) * sizeof(double));
+    CK(hipMalloc(&t.buf, off));
+    CK(hipMemsetAsync(t.buf, 0, off, s->stream));
+    size_t q = 0;
+    t.Mf.assign((size_t)nf * (K + 1), nullptr);
+    t.Mh.assign((size_t)nf * K, nullptr);
+    t.B1s = t.B1n = t.B2s = t.B2n = std::vector<double *>((size_t)nf * K, nullptr);
+    for (int f = 0; f < nf; f++) {
+        for (int m = 0; m <= K; m++) t.Mf[(size_t)f * (K + 1) + m] = (double *)(t.buf + o[q++]);
+        for (int m = 0; m < K; m++) t.Mh[(size_t)f * K + m] = (double *)(t.buf + o[q++]);
+        for (int m = 0; m < K; m++) {
+            t.B1s[(size_t)f * K + m] = (double *)(t.buf + o[q++]);
+            t.B1n[(size_t)f * K + m] = (double *)(t.buf + o[q++]);
+            t.B2s[(size_t)f * K + m] = (double *)(t.buf + o[q++]);
+            t.B2n[(size_t)f * K + m] = (double *)(t.buf + o[q++]);
+        }
+    }
+    t.loss = (double *)(t.buf + o[q++]);
+    t.box = (double *)(t.buf + o[q++]);
+    // film descriptors per slot and use
+    std::vector<FilmDev> base(nf), var((size_t)K * NV * nf);
+    if (nf) CK(hipMemcpy(base.data(), s->d_films, nf * sizeof(FilmDev), hipMemcpyDeviceToHost));
+    for (int m = 0; m < K; m++)
+        for (int f = 0; f < nf; f++) {
+            auto Mf = [&](int mm) { return t.Mf[(size_t)f * (K + 1) + mm]; };
+            auto Mh = [&](int mm) { return t.Mh[(size_t)f * K + std::min(mm, K - 1)]; };
+            auto B1s = [&](int mm) { return t.B1s[(size_t)f * K + std::min(mm, K - 1)]; };
+            auto B1n = [&](int mm) { return t.B1n[(size_t)f * K + std::min(mm, K - 1)]; };
+            const size_t i0 = (size_t)m * NV * nf + f;
+            FilmDev d;
+            // HALF2 of step m: reads M^{n+1/2}, writes M^{n+1} and its prepass
+            d = base[f];
+            d.M = Mh(m);
+            d.M1 = Mf(m + 1);
+            d.Bs = t.B2s[(size_t)f * K + m];
+            d.Bn = t.B2n[(size_t)f * K + m];
+            var[i0 + V_P1 * nf] = d;
+            // HALF1 of step m + 1 (merged pair): reads M^{n+1}, writes M^{n+3/2}
+            d = base[f];
+            d.M = Mh(m + 1);
+            d.M1 = Mf(m + 1);
+            d.Bs = B1s(m + 1);
+            d.Bn = B1n(m + 1);
+            var[i0 + V_P2 * nf] = d;
+            // commit after the segment's last HALF2 (copies M^{n+1} onto itself)
+            d = base[f];
+            d.M = d.M1 = Mf(m + 1);
+            var[i0 + V_C * nf] = d;
+            // the adjoint of HALF1 of step m: M^n and its prepass
+            d = base[f];
+            d.M = Mf(m);
+            d.Bs = B1s(m);
+            d.Bn = B1n(m);
+            var[i0 + V_R1 * nf] = d;
+            // the bracket (HALF1 of the segment's first step) and its commit
+            d = base[f];
+            d.M = Mf(0);
+            d.M1 = Mh(0);
+            d.Bs = B1s(0);
+            d.Bn = B1n(0);
+            var[i0 + V_BR * nf] = d;
+            d = base[f];
+            d.M = d.M1 = Mh(0);
+            var[i0 + V_BRC * nf] = d;
+        }
+    if (nf) {
+        CK(hipMalloc(&t.d_var, var.size() * sizeof(FilmDev)));
+        CK(hipMemcpy(t.d_var, var.data(), var.size() * sizeof(FilmDev), hipMemcpyHostToDevice));
+    }
+    return MPX_OK;
+}
+
+const FilmDev *tvar(const Tape &t, int m, int v) { return t.d_var ? t.d_var + ((size_t)m * NV + v) * t.nf : nullptr; }
+
+// copy tables of every snapshot: [snapshot][save | load | load-to-tape][segment]
+mpx_status snap_tables(mpx_sim *s, Tape &t, const SnapLayout &L, const std::vector<Snap2 *> &snaps) {
+    const int ns = (int)L.handle.size();
+    t.nseg = ns;
+    std::vector<CopySeg> tab((size_t)snaps.size() * 3 * ns);
+    for (size_t z = 0; z < snaps.size(); z++)
+        for (int q = 0; q < ns; q++) {
+            char *sp = snaps[z]->buf + L.off[q];
+            void *h = L.handle[q];
+            const long long b = (long long)L.bytes[q];
+            tab[(z * 3 + 0) * ns + q] = CopySeg{h, sp, b};
+            tab[(z * 3 + 1) * ns + q] = CopySeg{sp, h, b};
+            void *ht = L.film_of[q] >= 0 ? (void *)t.Mf[(size_t)L.film_of[q] * (t.K + 1)] : h;
+            tab[(z * 3 + 2) * ns + q] = CopySeg{sp, ht, b};
+        }
+    CK(hipMalloc(&t.d_tab, std::max<size_t>(1, tab.size()) * sizeof(CopySeg)));
+    CK(hipMemcpy(t.d_tab, tab.data(), tab.size() * sizeof(CopySeg), hipMemcpyHostToDevice));
+    return MPX_OK;
+}
+
+template <typename T>
+mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int film, int K, const int *eps_box,
+                            const int *ms_box, double *loss, double *gH0, double *geps, double *gms) {
+    hipStream_t st = s->stream;
+    const int saved_fused = s->fused;
+    s->fused = 0;
+    const long long step0 = s->step;
+    const int ncp = (int)((N + K - 1) / K);
+    const long long neps = (long long)eps_box[3] * eps_box[4] * eps_box[5];
+    const int nblk = s->nblk;
+    const FilmHost &LF = s->films[film];
+    std::vector<Snap2> cp(ncp);
+    Snap2 fin;
+    AdjHost h;
+    Tape tp;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool probe_added = false;
+    auto body = [&]() -> mpx_status {
+        mpx_status q;
+        if ((q = adj_alloc(s, h, neps, false)) != MPX_OK) return q;
+        if (!h.af.empty()) {
+            // lambda M ping-pong: the first map of a step reads lM and writes
+            // lMout, the second reads lMout and writes lM
+            std::vector<AdjFilmDev> af2 = h.af;
+            for (auto &g : af2) std::swap(g.lM, g.lMout);
+            CK(hipMalloc(&h.d_af2, af2.size() * sizeof(AdjFilmDev)));
+            CK(hipMemcpy(h.d_af2, af2.data(), af2.size() * sizeof(AdjFilmDev), hipMemcpyHostToDevice));
+        }
+        if (neps > 0) {
+            const size_t gb = (size_t)box_tape_size(eps_box) / 2 * sizeof(double); // 3 components
+            CK(hipMalloc(&h.gbox_a, gb));
+            CK(hipMalloc(&h.gbox_b, gb));
+            CK(hipMemsetAsync(h.gbox_a, 0, gb, st));
+            CK(hipMemsetAsync(h.gbox_b, 0, gb, st));
+        }
+        CK(hipMalloc(&h.d_seg0, sizeof(long long)));
+        if ((q = tape_alloc(s, tp, K, LF.cb, eps_box)) != MPX_OK) return q;
+        const SnapLayout L = snap_layout(s);
+        std::vector<Snap2 *> all;
+        for (auto &z : cp) {
+            CK(hipMalloc(&z.buf, L.total));
+            all.push_back(&z);
+        }
+        CK(hipMalloc(&fin.buf, L.total));
+        all.push_back(&fin);
+        if ((q = snap_tables(s, tp, L, all)) != MPX_OK) return q;
+        const int ns = tp.nseg;
+        auto tab = [&](int z, int kind) { return tp.d_tab + ((size_t)z * 3 + kind) * ns; };
+        const double dt = s->dt;
+
+        // forward: the loss through a temporary film-energy probe
+        {
+            ProbeHost ph{};
+            ph.dev.kind = MPX_PROBE_FILM_ENERGY;
+            ph.dev.film = film;
+            ph.dev.nval = 1;
+            ph.dev.cap = N;
+            ph.dev.start = s->step;
+            ph.dev.npart = ((long long)LF.cb[3] * LF.cb[4] * LF.cb[5] + 255) / 256;
+            CK(hipMalloc(&ph.dev.data, N * sizeof(double)));
+            CK(hipMalloc(&ph.dev.part, ph.dev.npart * sizeof(double)));
+            s->probes.push_back(ph);
+            probe_added = true;
+            drop_graph(s);
+            if ((q = upload_probes(s)) != MPX_OK) return q;
+        }
+        for (int g = 0; g < ncp; g++) {
+            const long long c0 = (long long)g * K, len = std::min<long long>(K, N - c0);
+            CK(launch_copy_segs(tab(g, 0), ns, L.nblk, st));
+            cp[g].step = s->step;
+            if ((q = enqueue_steps<T>(s, len)) != MPX_OK) return q;
+            s->step += len;
+        }
+        CK(launch_copy_segs(tab(ncp, 0), ns, L.nblk, st));
+        fin.step = s->step;
+        std::vector<double> tr(N);
+        CK(hipMemcpyAsync(tr.data(), s->probes.back().dev.data, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        {
+            ProbeHost ph = s->probes.back();
+            s->probes.pop_back();
+            probe_added = false;
+            (void)hipFree(ph.dev.data);
+            (void)hipFree(ph.dev.part);
+            drop_graph(s);
+            if ((q = upload_probes(s)) != MPX_OK) return q;
+        }
+        double Lsum = 0.0;
+        for (long long i = loss_from; i < N; i++) Lsum += tr[i];
+        *loss = dt * Lsum;
+        // the seed is scaled by a power of two near 1/L (see the plain
+        // schedule); exact in float64
+        double S = 1.0;
+        if (std::isfinite(*loss) && *loss > 0.0) S = std::ldexp(1.0, -std::ilogb(*loss));
+
+        // the loss term of the final state
+        {
+            AdjParams<T> A;
+            adj_params<T>(s, h, A);
+            CK(launch_tape_loss<T>(A.p, film, 0, tp.lossp(0), st, LF.cb));
+            CK(launch_adj_loss_tape<T>(A, film, dt * S, tp.lossp(0), nullptr, 0, loss_from, st, LF.cb));
+        }
+
+        // recompute a segment of len steps with the tape, then its adjoint
+        auto segment = [&](int len) -> mpx_status {
+            KParams<T> p;
+            fill_params<T>(s, p, MODE_INPLACE, s->parity);
+            p.films = tvar(tp, 0, V_R1);
+            CK(launch_tape_loss<T>(p, film, 0, tp.lossp(0), st, LF.cb));
+            p.films = tvar(tp, 0, V_BR);
+            CK(launch_film<T>(p, nblk, 1, 0, st));
+            p.films = tvar(tp, 0, V_BRC);
+            CK(launch_commit<T>(p, nblk, st));
+            CK(launch_hbulk<T>(p, 1, 0, st));
+            for (int m = 0; m < len; m++) {
+                if (neps > 0) CK(launch_tape_box<T>(p, eps_box, tp.boxp(m), st));
+                CK(launch_epass<T>(p, st));
+                p.films = tvar(tp, m, V_P1);
+                CK(launch_film<T>(p, nblk, 1, 0, st));
+                if (m + 1 < len) {
+                    CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
+                    p.films = tvar(tp, m, V_P2);
+                    CK(launch_film<T>(p, nblk, 2, 0, st));
+                    CK(launch_hbulk<T>(p, 2, 1, st));
+                } else {
+                    p.films = tvar(tp, m, V_C);
+                    CK(launch_commit<T>(p, nblk, st));
+                    CK(launch_hbulk<T>(p, 1, 1, st));
+                }
+            }
+            for (int m = len - 1; m >= 0; m--) {
+                AdjParams<T> A;
+                adj_params<T>(s, h, A);
+                A.p.films = tvar(tp, m, V_P1);
+                A.af = h.d_af;
+                CK(launch_adj_half_tape<T>(A, nblk, st));
+                if (neps > 0) CK(launch_adj_box<T>(A, eps_box, tp.boxp(m), h.gbox_a, h.gbox_b, st));
+                CK(launch_adj_estep_lean<T>(A, st));
+                A.p.films = tvar(tp, m, V_R1);
+                A.af = h.d_af2;
+                CK(launch_adj_half_tape<T>(A, nblk, st));
+                CK(launch_adj_loss_tape<T>(A, film, dt * S, tp.lossp(m), h.d_seg0, m, loss_from, st, LF.cb));
+            }
+            return MPX_OK;
+        };
+        for (int g = ncp - 1; g >= 0; g--) {
+            const long long c0 = (long long)g * K;
+            const int len = (int)std::min<long long>(K, N - c0);
+            CK(launch_copy_segs(tab(g, 2), ns, L.nblk, st));
+            s->step = cp[g].step;
+            CK(launch_set_step(s->d_step, cp[g].step, st));
+            CK(launch_set_step(h.d_seg0, c0, st));
+            if (len == K && ncp > 1) {
+                if (!gexec) {
+                    CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    q = segment(len);
+                    hipGraph_t gg = nullptr;
+                    const hipError_t e = hipStreamEndCapture(st, &gg);
+                    if (q != MPX_OK) {
+                        if (gg) (void)hipGraphDestroy(gg);
+                        return q;
+                    }
+                    CK(e);
+                    graph = gg;
+                    CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+                }
+                CK(hipGraphLaunch(gexec, st));
+            } else if ((q = segment(len)) != MPX_OK) {
+                return q;
+            }
+        }
+        // the initial magnetisation M0 = Ms u
+        if (step0 == 0 && s->have_u) CK(launch_adj_init_ms(s->d_blocktab, nblk, s->d_films, h.d_af, s->u, st));
+        if (neps > 0) {
+            KParams<T> p;
+            fill_params<T>(s, p, MODE_INPLACE, s->parity);
+            CK(launch_adj_eps_box<T>(p, eps_box, h.gbox_a, h.gbox_b, h.d_out, st));
+            CK(hipMemcpyAsync(geps, h.d_out, neps * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        CK(hipStreamSynchronize(st));
+        for (long long t = 0; t < neps; t++) geps[t] /= S;
+        if ((q = film_grads(s, h, S, ms_box, gH0, gms)) != MPX_OK) return q;
+        // leave the handle at the end of the forward run
+        CK(launch_copy_segs(tab(ncp, 1), ns, L.nblk, st));
+        s->step = fin.step;
+        CK(launch_set_step(s->d_step, fin.step, st));
+        CK(hipStreamSynchronize(st));
+        return MPX_OK;
+    };
+    mpx_status r = body();
+    if (probe_added) {
+        ProbeHost ph = s->probes.back();
+        s->probes.pop_back();
+        (void)hipFree(ph.dev.data);
+        (void)hipFree(ph.dev.part);
+        drop_graph(s);
+        (void)upload_probes(s);
+    }
+    if (r != MPX_OK) (void)hipStreamSynchronize(st);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    s->fused = saved_fused;
+    adj_free(h);
+    tape_free(tp);
+    for (auto &z : cp) (void)hipFree(z.buf);
+    (void)hipFree(fin.buf);
     return r;
 }
 
@@ -1327,7 +1749,10 @@ mpx_status mpx_destroy(mpx_sim *s) {
     }
     free_films(s);
     for (auto &src : s->srcs) (void)hipFree(src.table);
-    for (auto &pr : s->probes) (void)hipFree(pr.dev.data);
+    for (auto &pr : s->probes) {
+        (void)hipFree(pr.dev.data);
+        (void)hipFree(pr.dev.part);
+    }
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_srcs);
     (void)hipFree(s->d_pflags);
@@ -1649,6 +2074,11 @@ mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
     }
     CK(hipMalloc(&h.dev.data, pd->capacity * h.dev.nval * sizeof(double)));
     CK(hipMemset(h.dev.data, 0, pd->capacity * h.dev.nval * sizeof(double)));
+    if (pd->kind == MPX_PROBE_FILM_ENERGY) {
+        const int *cb = s->films[pd->film].cb;
+        h.dev.npart = ((long long)cb[3] * cb[4] * cb[5] + 255) / 256;
+        CK(hipMalloc(&h.dev.part, h.dev.npart * sizeof(double)));
+    }
     s->probes.push_back(h);
     drop_graph(s);
     if ((r = upload_probes(s)) != MPX_OK) return r;
@@ -1970,9 +2400,23 @@ mpx_status mpx_adjoint(mpx_sim *s, int64_t nsteps, int64_t loss_from, int32_t fi
     if (K == 0) K = std::max(1, (int)std::ceil(std::sqrt((double)nsteps)));
     K = (int)std::min<int64_t>(K, nsteps);
     drop_graph(s);
-    r = s->prec == MPX_F64 ? run_adjoint<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
-                           : run_adjoint<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
+    if (s->adj_schedule == 0)
+        r = s->prec == MPX_F64
+                ? run_adjoint_tape<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
+                : run_adjoint_tape<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
+    else
+        r = s->prec == MPX_F64
+                ? run_adjoint<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
+                : run_adjoint<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
     return r;
+}
+
+mpx_status mpx_set_adjoint_schedule(mpx_sim *s, int32_t schedule) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (schedule < 0 || schedule > 1) return fail(s, MPX_E_INVALID, "adjoint schedule");
+    s->adj_schedule = schedule;
+    return MPX_OK;
 }
 
 

@@ -356,39 +356,9 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
             __syncthreads();
         }
     } else {
-        const FilmDev &F = p.films[P.film];
-        const long long ncell = (long long)F.cb[3] * F.cb[4] * F.cb[5];
+        // film EM energy: the partial sums of k_probe_parts, in block order
         double s = 0.0;
-        for (long long t = threadIdx.x; t < ncell; t += blockDim.x) {
-            const int cc[3] = {F.cb[0] + (int)(t % F.cb[3]), F.cb[1] + (int)((t / F.cb[3]) % F.cb[4]),
-                               F.cb[2] + (int)(t / ((long long)F.cb[3] * F.cb[4]))};
-            const int m = cell_id(p.n, p.per, p.px, p.id, cc[0], cc[1], cc[2]);
-            if (m < 0 || !(p.mat[m].Ms > 0.0)) continue;
-            double we = 0.0, wh = 0.0;
-            for (int c = 0; c < 3; c++) {
-                const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-                double e2 = 0.0;
-                for (int u = 0; u < 2; u++)
-                    for (int vv = 0; vv < 2; vv++) {
-                        int q[3] = {cc[0], cc[1], cc[2]};
-                        q[c1] += u;
-                        q[c2] += vv;
-                        const double e = (double)ldz(p, p.E[c], q[0], q[1], q[2]);
-                        e2 += e * e;
-                    }
-                we += e2 / 4.0;
-                double h2 = 0.0;
-                for (int u = 0; u < 2; u++) {
-                    int q[3] = {cc[0], cc[1], cc[2]};
-                    q[c] += u;
-                    for (int a = 0; a < 3; a++) q[a] = fold(q[a], p.n[a], p.per[a]);
-                    const double h = (q[0] < 0 || q[1] < 0 || q[2] < 0) ? 0.0 : h_integer_time(p, c, q);
-                    h2 += h * h;
-                }
-                wh += h2 / 2.0;
-            }
-            s += 0.5 * p.eps0 * p.mat[m].eps_r * we + 0.5 * p.mu0 * wh;
-        }
+        for (long long b = threadIdx.x; b < P.npart; b += blockDim.x) s += P.part[b];
         red[threadIdx.x] = s;
         __syncthreads();
         for (int st = 128; st > 0; st >>= 1) {
@@ -406,6 +376,71 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
         }
         if (bad) atomicOr(p.flag, 1);
     }
+}
+
+// EM energy density sum of one film cell (eps0 eps_r <E^2>/2 + mu0 <H^2>/2 over
+// its twelve edges and six faces, H at the integer time), zero elsewhere
+template <typename T>
+__device__ double film_cell_energy(const KParams<T> &p, const FilmDev &F, long long t) {
+    const int cc[3] = {F.cb[0] + (int)(t % F.cb[3]), F.cb[1] + (int)((t / F.cb[3]) % F.cb[4]),
+                       F.cb[2] + (int)(t / ((long long)F.cb[3] * F.cb[4]))};
+    const int m = cell_id(p.n, p.per, p.px, p.id, cc[0], cc[1], cc[2]);
+    if (m < 0 || !(p.mat[m].Ms > 0.0)) return 0.0;
+    double we = 0.0, wh = 0.0;
+    for (int c = 0; c < 3; c++) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        double e2 = 0.0;
+        for (int u = 0; u < 2; u++)
+            for (int vv = 0; vv < 2; vv++) {
+                int q[3] = {cc[0], cc[1], cc[2]};
+                q[c1] += u;
+                q[c2] += vv;
+                const double e = (double)ldz(p, p.E[c], q[0], q[1], q[2]);
+                e2 += e * e;
+            }
+        we += e2 / 4.0;
+        double h2 = 0.0;
+        for (int u = 0; u < 2; u++) {
+            int q[3] = {cc[0], cc[1], cc[2]};
+            q[c] += u;
+            for (int a = 0; a < 3; a++) q[a] = fold(q[a], p.n[a], p.per[a]);
+            const double h = (q[0] < 0 || q[1] < 0 || q[2] < 0) ? 0.0 : h_integer_time(p, c, q);
+            h2 += h * h;
+        }
+        wh += h2 / 2.0;
+    }
+    return 0.5 * p.eps0 * p.mat[m].eps_r * we + 0.5 * p.mu0 * wh;
+}
+
+// film-energy probes: block b of probe pb sums cells [256 b, 256 b + 256) of
+// the film's cell box into P.part[b]
+template <typename T>
+__device__ __forceinline__ void probe_parts_body(const KParams<T> &p, int pb) {
+    __shared__ double red[256];
+    const ProbeDev &P = p.probes[pb];
+    if (P.kind != 2 || (long long)blockIdx.x >= P.npart) return;
+    const FilmDev &F = p.films[P.film];
+    const long long ncell = (long long)F.cb[3] * F.cb[4] * F.cb[5];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    red[threadIdx.x] = t < ncell ? film_cell_energy(p, F, t) : 0.0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.part[blockIdx.x] = red[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_probe_parts(KParams<T> p) {
+    probe_parts_body(p, blockIdx.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_probe_parts_batch(const KParams<T> *__restrict__ plist,
+                                                           const int2 *__restrict__ work) {
+    const int2 wk = work[blockIdx.y];
+    probe_parts_body(plist[wk.x], wk.y);
 }
 
 template <typename T>
@@ -585,8 +620,9 @@ hipError_t launch_commit(const KParams<T> &p, int nblk, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_probes(const KParams<T> &p, int nprobe, hipStream_t s) {
+hipError_t launch_probes(const KParams<T> &p, int nprobe, int maxpart, hipStream_t s) {
     if (nprobe == 0) return hipSuccess;
+    if (maxpart > 0) hipLaunchKernelGGL(k_probe_parts<T>, dim3(maxpart, nprobe), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_probes<T>, dim3(nprobe), dim3(256), 0, s, p);
     return hipGetLastError();
 }
@@ -614,8 +650,9 @@ hipError_t launch_film_batch(const KParams<T> *plist, const int2 *work_ext, int 
 }
 
 template <typename T>
-hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, hipStream_t s) {
+hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, int maxpart, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    if (maxpart > 0) hipLaunchKernelGGL(k_probe_parts_batch<T>, dim3(maxpart, n), dim3(256), 0, s, plist, work);
     hipLaunchKernelGGL(k_probes_batch<T>, dim3(n), dim3(256), 0, s, plist, work);
     return hipGetLastError();
 }
@@ -633,9 +670,9 @@ hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hi
     template hipError_t launch_commit<T>(const KParams<T> &, int, hipStream_t);             \
     template hipError_t launch_film_batch<T>(const KParams<T> *, const int2 *, int, const int2 *, int, int, int, \
                                              hipStream_t);                                  \
-    template hipError_t launch_probes_batch<T>(const KParams<T> *, const int2 *, int, hipStream_t); \
+    template hipError_t launch_probes_batch<T>(const KParams<T> *, const int2 *, int, int, hipStream_t); \
     template hipError_t launch_tick_batch<T>(const KParams<T> *, const int *, int, hipStream_t);   \
-    template hipError_t launch_probes<T>(const KParams<T> &, int, hipStream_t);             \
+    template hipError_t launch_probes<T>(const KParams<T> &, int, int, hipStream_t);        \
     template hipError_t launch_energy<T>(const KParams<T> &, int, double *, double *, hipStream_t);
 
 MPX_INSTANTIATE(float)

@@ -49,6 +49,8 @@ struct ProbeDev {
     int kind, field, i, j, k, film, nval, pad;
     long long cap, start;
     double *data;
+    double *part;    // film-energy probes: one partial sum per 256 cells of the film's cell box
+    long long npart;
 };
 
 // Coefficients of an edge whose four cells share one material id, computed
@@ -119,6 +121,14 @@ struct KParams {
     }
 };
 
+// one contiguous device-to-device copy of a snapshot table (bytes: a multiple
+// of 4; both ends 16-byte aligned)
+struct CopySeg {
+    const void *src;
+    void *dst;
+    long long bytes;
+};
+
 // adjoint arrays of one film (layouts of FilmDev::M)
 struct AdjFilmDev {
     double *lM;    // [family][component][site] lambda of M (in: after the map)
@@ -141,6 +151,26 @@ struct AdjParams {
 };
 
 template <typename T> hipError_t launch_adj_half(const AdjParams<T> &A, int nblk, hipStream_t s);
+// tape schedule: the half-step adjoint without the lambda-M commit (the caller
+// alternates the two lambda-M buffers), the lean E-step adjoint, and the
+// film-region and box-region tapes and their adjoint kernels
+template <typename T> hipError_t launch_adj_half_tape(const AdjParams<T> &A, int nblk, hipStream_t s);
+template <typename T> hipError_t launch_adj_estep_lean(const AdjParams<T> &A, hipStream_t s);
+template <typename T>
+hipError_t launch_tape_loss(const KParams<T> &p, int film, int merged, double *dst, hipStream_t s, const int *cb);
+template <typename T>
+hipError_t launch_adj_loss_tape(const AdjParams<T> &A, int film, double scale, const double *tape,
+                                const long long *seg0, int m, long long loss_from, hipStream_t s, const int *cb);
+template <typename T> hipError_t launch_tape_box(const KParams<T> &p, const int *box, double *dst, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_box(const AdjParams<T> &A, const int *box, const double *tape, double *gca, double *gcb,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double *gca, const double *gcb, double *out,
+                              hipStream_t s);
+hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s);
+long long film_tape_size(const int *cb);
+long long box_tape_size(const int *box);
 template <typename T> hipError_t launch_adj_estep(const AdjParams<T> &A, hipStream_t s);
 template <typename T> hipError_t launch_adj_loss(const AdjParams<T> &A, int film, double scale, hipStream_t s);
 template <typename T> hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hipStream_t s);
@@ -175,10 +205,11 @@ hipError_t launch_fused_batch(const KParams<T> *plist, const int4 *work, int nwo
 template <typename T>
 hipError_t launch_film_batch(const KParams<T> *plist, const int2 *work_ext, int n_ext, const int2 *work, int n,
                              int phase, int inc, hipStream_t s);
-template <typename T> hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_probes_batch(const KParams<T> *plist, const int2 *work, int n, int maxpart, hipStream_t s);
 template <typename T> hipError_t launch_tick_batch(const KParams<T> *plist, const int *inst, int n, hipStream_t s);
 template <typename T> hipError_t launch_commit(const KParams<T> &p, int nblk, hipStream_t s);
-template <typename T> hipError_t launch_probes(const KParams<T> &p, int nprobe, hipStream_t s);
+template <typename T> hipError_t launch_probes(const KParams<T> &p, int nprobe, int maxpart, hipStream_t s);
 template <typename T>
 hipError_t launch_energy(const KParams<T> &p, int nblk, double *part, double *out, hipStream_t s);
 

@@ -13,8 +13,6 @@
 
 namespace mpx {
 
-constexpr int kMixed = 255;
-
 // coefficient table of edges whose four cells share one id, staged in LDS;
 // PEC ids hold ca = cb = 0 (the edge stays zero)
 template <typename T>

@@ -35,7 +35,7 @@ EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "m
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
            "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
-           "mpx_last_error", "mpx_adjoint", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
+           "mpx_last_error", "mpx_adjoint", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
            "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
 
 
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
         "mpx_last_error": (C.c_char_p, [P]),
         "mpx_adjoint": (I32, [P, I64, I64, I32, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D),
                               P, P]),
+        "mpx_set_adjoint_schedule": (I32, [P, I32]),
         "mpx_batch_create": (I32, [C.POINTER(P), I32, C.POINTER(P)]),
         "mpx_batch_destroy": (I32, [P]),
         "mpx_batch_set_schedule": (I32, [P, I32, I32]),
@@ -310,6 +311,10 @@ class Sim:
                                      C.byref(loss), dh0, deps.ctypes.data if deps.size else None,
                                      dms.ctypes.data if dms.size else None), "adjoint")
         return {"loss": loss.value, "dH0": np.array(dh0[:]), "deps": deps, "dMs": dms}
+
+    def set_adjoint_schedule(self, schedule: int):
+        """0: tape schedule (default); 1: plain recompute-per-step schedule."""
+        self._ck(self._L.mpx_set_adjoint_schedule(self._h, int(schedule)), "set_adjoint_schedule")
 
     def films(self):
         out = []

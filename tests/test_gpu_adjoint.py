@@ -79,6 +79,41 @@ def test_adjoint_matches_oracle_finite_differences(pml):
         assert close(a, b, sc), (a, b)
 
 
+def periodic_case():
+    w = W.random_case(6, nx=29, ny=17, nz=23, bc=(W.PERIODIC, W.PERIODIC, W.PEC, W.PEC, W.PML, W.PML),
+                      npml=(0, 0, 0, 0, 4, 4), nsteps=40)
+    w.H0 = (2e6, 1e6, 4e6)
+    return w
+
+
+@pytest.mark.parametrize("case,n,n0,K", [("pec", 60, 30, 7), ("pml", 60, 0, 60), ("pml", 33, 20, 1),
+                                         ("periodic", 40, 10, 6)])
+def test_tape_schedule_matches_plain(case, n, n0, K):
+    """The tape schedule (one recompute per segment, adjoint from the tape,
+    graph replays) against the plain schedule (reload and recompute per
+    reverse step): the same gradients to float64 rounding."""
+    w = {"pec": lambda: small_case(False), "pml": lambda: small_case(True), "periodic": periodic_case}[case]()
+    fc = np.argwhere(w.ids == 3)
+    lo, hi = fc.min(axis=0), fc.max(axis=0)  # (k, j, i)
+    eps_box = (max(0, lo[2] - 2), max(0, lo[1] - 1), max(0, lo[0] - 3), min(6, w.nx - max(0, lo[2] - 2)), 4, 3)
+    ms_box = (lo[2], lo[1], lo[0], hi[2] - lo[2] + 1, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1)
+    say(f"tape vs plain: {case} n={n} n0={n0} K={K}")
+    out = []
+    for sched in (0, 1):
+        g = mpx.from_workload(w, precision=mpx.F64)
+        g.set_adjoint_schedule(sched)
+        out.append(g.adjoint(n, n0, film=0, checkpoint_every=K, eps_box=eps_box, ms_box=ms_box))
+        g.close()
+    a, b = out
+    assert a["loss"] == pytest.approx(b["loss"], rel=1e-13)
+    for key in ("dH0", "deps", "dMs"):
+        sc = float(np.abs(b[key]).max())
+        err = float(np.abs(a[key] - b[key]).max())
+        say(f"  {key}: max |tape - plain| / max |plain| = {err / sc if sc else err:.2e}")
+        assert sc > 0, key
+        assert err <= 1e-10 * sc, key
+
+
 def test_adjoint_float32_tracks_float64():
     """The float32 path seeds its adjoint at unit scale (the loss itself is
     ~1e-29 J s here): its gradients follow the float64 ones to float32's
