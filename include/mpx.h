@@ -276,7 +276,8 @@ mpx_status mpx_adjoint(mpx_sim *sim, int64_t nsteps, int64_t loss_from, int32_t 
 /* Reverse-sweep schedule of mpx_adjoint (same gradients up to rounding):
  *   0 (default) tape: each checkpoint segment is recomputed once while the
  *     values the adjoint maps read are taped, then its adjoint steps run
- *     from the tape (one captured graph replayed per segment);
+ *     from the tape (one captured graph replayed per segment, unless graphs
+ *     are off: mpx_set_graph_steps(sim, 0));
  *   1 plain: every reverse step reloads its input state and recomputes its
  *     half steps (the reference the tape schedule is tested against).
  * Errors: MPX_E_INVALID for another value. */

@@ -182,11 +182,14 @@ __device__ __forceinline__ bool near_film(const KParams<T> &p, const int *idx) {
 // every face: lambda of H' (and psi') -> lambda of H (and psi), the face's
 // curl-part adjoints aD, and for magnetic faces lambda of M from B^
 // ---------------------------------------------------------------------------
+// lin1/lin2: lambda psiH of the derivative axes C+1, C+2 before the map;
+// lout1/lout2: where the values after it go (the same arrays in place)
 template <typename T, int C>
-__device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, int k) {
+__device__ __forceinline__ void adj_face_core(const AdjParams<T> &A, const int *idx, const T *lin1, const T *lin2,
+                                              T *lout1, T *lout2, T &ad0, T &ad1) {
     constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
     const KParams<T> &p = A.p;
-    const int idx[3] = {i, j, k};
+    const int i = idx[0], j = idx[1], k = idx[2];
     const long long q = p.slot(i, j, k);
     const T lHp = A.lH[C][q];
     const int a1 = idx[C1], a2 = idx[C2];
@@ -195,8 +198,8 @@ __device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, in
     const bool film_reach = p.nfilm && near_film(p, idx);
     if (!film_reach && !s1 && !s2) {
         // bulk face out of every film's reach: H' = H - hc (d1 - d2)
-        A.aD[C][0][q] = -(p.hc * lHp);
-        A.aD[C][1][q] = p.hc * lHp;
+        ad0 = -(p.hc * lHp);
+        ad1 = p.hc * lHp;
         return; // lambda H unchanged
     }
     long long lm;
@@ -204,21 +207,20 @@ __device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, in
     // CPML face (never next to a film)
     if (fm < 0 && (s1 || s2)) {
         const T g1 = -p.hc * lHp, g2 = p.hc * lHp; // d H' / d (d1 + psi1'), d (d2 + psi2')
-        T ad1 = g1, ad2 = g2;
+        ad0 = g1;
+        ad1 = g2;
         if (s1) {
             const long long qq = p.psi_index(C1, idx);
-            const T aps = A.lpsiH[C][C1][qq] + g1;
-            A.lpsiH[C][C1][qq] = p.bH[C1][a1] * aps;
-            ad1 = g1 + p.cH[C1][a1] * aps;
+            const T aps = lin1[qq] + g1;
+            lout1[qq] = p.bH[C1][a1] * aps;
+            ad0 = g1 + p.cH[C1][a1] * aps;
         }
         if (s2) {
             const long long qq = p.psi_index(C2, idx);
-            const T aps = A.lpsiH[C][C2][qq] + g2;
-            A.lpsiH[C][C2][qq] = p.bH[C2][a2] * aps;
-            ad2 = g2 + p.cH[C2][a2] * aps;
+            const T aps = lin2[qq] + g2;
+            lout2[qq] = p.bH[C2][a2] * aps;
+            ad1 = g2 + p.cH[C2][a2] * aps;
         }
-        A.aD[C][0][q] = ad1;
-        A.aD[C][1][q] = ad2;
         return; // lambda H unchanged (dH'/dH = 1)
     }
     // lambda of B^* and B^ of this face: from the face's own update and from
@@ -266,16 +268,28 @@ __device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, in
         const FilmDev &F = p.films[fm];
         const AdjFilmDev &G = A.af[fm];
         G.lMout[(C * 3 + C) * F.ns + lm] += lbt;
-        A.aD[C][0][q] = (T)(-p.hcd * lbs);
-        A.aD[C][1][q] = (T)(p.hcd * lbs);
+        ad0 = (T)(-p.hcd * lbs);
+        ad1 = (T)(p.hcd * lbs);
     } else {
         // bulk face: H' = H - hc (d1 - d2) in the field precision; its B^ and
         // B^* as read by the solves are H and H - hc (d1 - d2) in float64
         A.lH[C][q] = (T)((double)lHp + lbn + lbs_f);
-        A.aD[C][0][q] = (T)(-(double)p.hc * (double)lHp - p.hcd * lbs_f);
-        A.aD[C][1][q] = (T)((double)p.hc * (double)lHp + p.hcd * lbs_f);
+        ad0 = (T)(-(double)p.hc * (double)lHp - p.hcd * lbs_f);
+        ad1 = (T)((double)p.hc * (double)lHp + p.hcd * lbs_f);
     }
 }
+
+template <typename T, int C>
+__device__ __forceinline__ void adj_face(const AdjParams<T> &A, int i, int j, int k) {
+    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    const int idx[3] = {i, j, k};
+    T a0, a1;
+    adj_face_core<T, C>(A, idx, A.lpsiH[C][C1], A.lpsiH[C][C2], A.lpsiH[C][C1], A.lpsiH[C][C2], a0, a1);
+    const long long q = A.p.slot(i, j, k);
+    A.aD[C][0][q] = a0;
+    A.aD[C][1][q] = a1;
+}
+
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_face(AdjParams<T> A) {
@@ -636,89 +650,6 @@ __global__ void k_accum(const double *part, int n, double *acc, double scale) {
 // tape schedule
 // ---------------------------------------------------------------------------
 
-// the E-step adjoint without recomputation: the edge's coefficients from the
-// per-slot class byte (the forward's own table) or, in a mixed slot, from its
-// four cells; no forward field is read
-template <typename T, int C>
-__device__ __forceinline__ void adj_edge_lean(const AdjParams<T> &A, int i, int j, int k) {
-    constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-    const KParams<T> &p = A.p;
-    const long long q = p.slot(i, j, k);
-    const int idx[3] = {i, j, k};
-    bool valid = true;
-    for (int a = 0; a < 3; a++)
-        if (!p.per[a] && a != C && idx[a] == 0) valid = false;
-    T ca = T(0), cb = T(0);
-    if (valid) {
-        const uint8_t cl = p.cls[q];
-        if (cl != kMixed) {
-            const CoefDev<T> cd = p.coef[cl];
-            if (cd.pec)
-                valid = false;
-            else {
-                ca = cd.ca;
-                cb = cd.cb;
-            }
-        } else {
-            double se = 0.0, ss = 0.0;
-            for (int u = 0; u < 2 && valid; u++)
-                for (int v = 0; v < 2; v++) {
-                    int cc[3] = {i, j, k};
-                    cc[C1] -= 1 - u;
-                    cc[C2] -= 1 - v;
-                    for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
-                    const MatDev &M = p.mat[p.id[p.slot(cc[0], cc[1], cc[2])]];
-                    if (M.is_pec) {
-                        valid = false;
-                        break;
-                    }
-                    se += M.eps_r;
-                    ss += M.sigma;
-                }
-            if (valid) {
-                const double eps = p.eps0 * (se / 4), sig = ss / 4;
-                const double den = sig / 2.0 + eps / p.dt;
-                ca = (T)(-(sig / 2.0 - eps / p.dt) / den);
-                cb = (T)(1.0 / den);
-            }
-        }
-    }
-    if (!valid) {
-        A.lE[C][q] = T(0);
-        A.eD[C][0][q] = T(0);
-        A.eD[C][1][q] = T(0);
-        return;
-    }
-    const T lEp = A.lE[C][q];
-    const T lx = cb * lEp;
-    A.lE[C][q] = ca * lEp;
-    const int a1 = idx[C1], a2 = idx[C2];
-    T ad1 = lx, ad2 = -lx;
-    if (p.psiE[C][C1] && (a1 < p.nlo[C1] || a1 >= p.n[C1] - p.nhi[C1])) {
-        const long long q1 = p.psi_index(C1, idx);
-        const T aps = A.lpsiE[C][C1][q1] + lx;
-        A.lpsiE[C][C1][q1] = p.bE[C1][a1] * aps;
-        ad1 = lx + p.cE[C1][a1] * aps;
-    }
-    if (p.psiE[C][C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2])) {
-        const long long q2 = p.psi_index(C2, idx);
-        const T aps = A.lpsiE[C][C2][q2] - lx;
-        A.lpsiE[C][C2][q2] = p.bE[C2][a2] * aps;
-        ad2 = -lx + p.cE[C2][a2] * aps;
-    }
-    A.eD[C][0][q] = ad1;
-    A.eD[C][1][q] = ad2;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_adj_estep_lean(AdjParams<T> A) {
-    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-    if (i >= A.p.n[0] || j >= A.p.n[1]) return;
-    adj_edge_lean<T, 0>(A, i, j, k);
-    adj_edge_lean<T, 1>(A, i, j, k);
-    adj_edge_lean<T, 2>(A, i, j, k);
-}
-
 // A region of slots [b0, b0 + r) (a cell box grown by one slot on the high
 // side of each axis: the edges and faces of its cells).  Thread t owns the
 // slot of region index t after folding; a slot that the fold maps onto an
@@ -875,25 +806,6 @@ __global__ void __launch_bounds__(256) k_tape_box(KParams<T> p, int4 bb, int4 bs
     }
 }
 
-// dL/dca += lambda E' E^n, dL/dcb += lambda E' x^n over the box's edges (run
-// before the E-step adjoint replaces lambda E' by lambda E)
-template <typename T>
-__global__ void __launch_bounds__(256) k_adj_box(AdjParams<T> A, int4 bb, int4 bs, const double *tape, double *gca,
-                                                 double *gcb) {
-    const KParams<T> &p = A.p;
-    const int b0[3] = {bb.x, bb.y, bb.z}, r[3] = {bs.x + 1, bs.y + 1, bs.z + 1};
-    const long long tb = (long long)r[0] * r[1] * r[2];
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    int q[3];
-    if (t >= tb || !region_slot(p.n, p.per, b0, r, t, q)) return;
-    const long long sl = p.slot(q[0], q[1], q[2]);
-    for (int C = 0; C < 3; C++) {
-        const double l = (double)A.lE[C][sl];
-        gca[C * tb + t] += l * tape[C * tb + t];
-        gcb[C * tb + t] += l * tape[(3 + C) * tb + t];
-    }
-}
-
 // dL/d eps_r of the box's cells from the box accumulators (eps of an edge:
 // eps0 x the mean over its four cells)
 template <typename T>
@@ -943,6 +855,396 @@ __global__ void __launch_bounds__(256) k_adj_eps_box(KParams<T> p, int4 bb, int4
             }
     }
     out[t] = g;
+}
+
+// ---------------------------------------------------------------------------
+// fused schedule: one stencil pass per transposed map
+// ---------------------------------------------------------------------------
+
+// E-step coefficients of the edge of family C at slot idx (in the domain):
+// ok = false for an edge on a lower wall or with a PEC cell (E' = 0).  The
+// mixed-slot case is out of line with scalar arguments (a reference to the
+// kernel's parameter block would make the compiler copy it to scratch).
+template <typename T>
+struct EdgeCoef {
+    T ca, cb;
+    bool ok;
+};
+
+template <typename T>
+__device__ __noinline__ EdgeCoef<T> edge_coef_mixed(const uint8_t *id, const MatDev *mat, int n0, int n1, int n2,
+                                                     int per0, int per1, int per2, int px, double eps0, double dt,
+                                                     int C, int i, int j, int k) {
+    const int n[3] = {n0, n1, n2}, per[3] = {per0, per1, per2};
+    const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+    double se = 0.0, ss = 0.0;
+    EdgeCoef<T> r{T(0), T(0), false};
+    for (int u = 0; u < 2; u++)
+        for (int v = 0; v < 2; v++) {
+            int cc[3] = {i, j, k};
+            cc[C1] -= 1 - u;
+            cc[C2] -= 1 - v;
+            for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], n[a], per[a]);
+            const MatDev &M = mat[id[(long long)cc[0] + (long long)px * ((long long)cc[1] + (long long)n1 * cc[2])]];
+            if (M.is_pec) return r;
+            se += M.eps_r;
+            ss += M.sigma;
+        }
+    const double eps = eps0 * (se / 4), sig = ss / 4;
+    const double den = sig / 2.0 + eps / dt;
+    r.ca = (T)(-(sig / 2.0 - eps / dt) / den);
+    r.cb = (T)(1.0 / den);
+    r.ok = true;
+    return r;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ bool edge_coef(const KParams<T> &p, const int *idx, long long q, T &ca, T &cb) {
+    for (int a = 0; a < 3; a++)
+        if (a != C && !p.per[a] && idx[a] == 0) return false;
+    const uint8_t cl = p.cls[q];
+    if (cl != kMixed) {
+        const CoefDev<T> cd = p.coef[cl];
+        ca = cd.ca;
+        cb = cd.cb;
+        return !cd.pec;
+    }
+    const EdgeCoef<T> r = edge_coef_mixed<T>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.per[0], p.per[1], p.per[2], p.px,
+                                             p.eps0, p.dt, C, idx[0], idx[1], idx[2]);
+    ca = r.ca;
+    cb = r.cb;
+    return r.ok;
+}
+
+// the first film whose reach holds the face slot idx, its region index lr
+template <typename T>
+__device__ __forceinline__ int first_region(const AdjParams<T> &A, const int *idx, long long &lr) {
+    for (int f = 0; f < A.p.nfilm; f++) {
+        const AdjFilmDev &G = A.af[f];
+        const int r0 = idx[0] - G.r0[0], r1 = idx[1] - G.r0[1], r2 = idx[2] - G.r0[2];
+        if (r0 >= 0 && r0 < G.rn[0] && r1 >= 0 && r1 < G.rn[1] && r2 >= 0 && r2 < G.rn[2]) {
+            lr = (long long)r0 + (long long)G.rn[0] * ((long long)r1 + (long long)G.rn[1] * r2);
+            return f;
+        }
+    }
+    return -1;
+}
+
+// a neighbour slot t - e_a (D = -1) or t + e_a (D = +1): folded, false when
+// outside the domain
+template <int D>
+__device__ __forceinline__ bool nb(const int *n, const int *per, const int *t, int a, int *q) {
+    q[0] = t[0];
+    q[1] = t[1];
+    q[2] = t[2];
+    q[a] = fold(t[a] + D, n[a], per[a]);
+    return q[a] >= 0;
+}
+
+// the film region's faces: the general face adjoint (magnetic faces, faces
+// the solves read), lambda H and lambda M updated in place, the curl-part
+// adjoints stored for the field pass
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_film_faces(AdjParams<T> A, int f) {
+    const AdjFilmDev &G = A.af[f];
+    const long long lr = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (lr >= G.nr) return;
+    const int idx[3] = {G.r0[0] + (int)(lr % G.rn[0]), G.r0[1] + (int)((lr / G.rn[0]) % G.rn[1]),
+                        G.r0[2] + (int)(lr / ((long long)G.rn[0] * G.rn[1]))};
+    long long l2;
+    if (first_region(A, idx, l2) != f) return;
+    // one face family per grid row
+    T a0, a1;
+    const int F = blockIdx.y;
+    if (F == 0)
+        adj_face_core<T, 0>(A, idx, A.lpsiH[0][1], A.lpsiH[0][2], A.lpsiHo[0][1], A.lpsiHo[0][2], a0, a1);
+    else if (F == 1)
+        adj_face_core<T, 1>(A, idx, A.lpsiH[1][2], A.lpsiH[1][0], A.lpsiHo[1][2], A.lpsiHo[1][0], a0, a1);
+    else
+        adj_face_core<T, 2>(A, idx, A.lpsiH[2][0], A.lpsiH[2][1], A.lpsiHo[2][0], A.lpsiHo[2][1], a0, a1);
+    G.aDr[(2 * F) * G.nr + lr] = (double)a0;
+    G.aDr[(2 * F + 1) * G.nr + lr] = (double)a1;
+}
+
+// region index of the folded slot t in the region [b0, b0 + r) (which may
+// wrap on a periodic axis), -1 outside
+__device__ __forceinline__ long long region_index_folded(const int *n, const int *per, const int *b0, const int *r,
+                                                         const int *t) {
+    long long li = 0, mul = 1;
+    for (int a = 0; a < 3; a++) {
+        int loc = t[a] - b0[a];
+        if (loc < 0 && per[a]) loc += n[a];
+        if (loc < 0 || loc >= r[a]) return -1;
+        li += mul * loc;
+        mul *= r[a];
+    }
+    return li;
+}
+
+// curl-part adjoints (aD0, aD1) of the face of family F at slot f (in the
+// domain), general case: from the film region's table, or from lambda H with
+// the CPML recursions (own: also store lambda psiH after the map)
+template <typename T, int F, int FILM>
+__device__ __forceinline__ void hface(const AdjParams<T> &A, const int *f, bool own, T &aD0, T &aD1) {
+    constexpr int F1 = (F + 1) % 3, F2 = (F + 2) % 3;
+    const KParams<T> &p = A.p;
+    if (FILM) {
+        long long lr;
+        const int fr = first_region(A, f, lr);
+        if (fr >= 0) {
+            const AdjFilmDev &G = A.af[fr];
+            aD0 = (T)G.aDr[(F * 2) * G.nr + lr];
+            aD1 = (T)G.aDr[(F * 2 + 1) * G.nr + lr];
+            return;
+        }
+    }
+    const T lH = A.lH[F][p.slot(f[0], f[1], f[2])];
+    const T g1 = -p.hc * lH, g2 = p.hc * lH;
+    aD0 = g1;
+    aD1 = g2;
+    const int a1 = f[F1], a2 = f[F2];
+    if (p.psiH[F][F1] && (a1 < p.nlo[F1] || a1 >= p.n[F1] - p.nhi[F1])) {
+        const long long qq = p.psi_index(F1, f);
+        const T aps = A.lpsiH[F][F1][qq] + g1;
+        if (own) A.lpsiHo[F][F1][qq] = p.bH[F1][a1] * aps;
+        aD0 = g1 + p.cH[F1][a1] * aps;
+    }
+    if (p.psiH[F][F2] && (a2 < p.nlo[F2] || a2 >= p.n[F2] - p.nhi[F2])) {
+        const long long qq = p.psi_index(F2, f);
+        const T aps = A.lpsiH[F][F2][qq] + g2;
+        if (own) A.lpsiHo[F][F2][qq] = p.bH[F2][a2] * aps;
+        aD1 = g2 + p.cH[F2][a2] * aps;
+    }
+}
+
+// the loss term of the state at the start of the step (film-energy
+// gradient, scaled) for the slot t: added to its three lambda E values (in
+// registers) and to lambda H of its three faces (film faces: no other thread
+// of the pass reads them)
+template <typename T>
+__device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, long long q, T &l0, T &l1, T &l2) {
+    const KParams<T> &p = A.p;
+    const FilmDev &F = p.films[A.lfilm];
+    const int b0[3] = {F.cb[0], F.cb[1], F.cb[2]}, r[3] = {F.cb[3] + 1, F.cb[4] + 1, F.cb[5] + 1};
+    const long long ri = region_index_folded(p.n, p.per, b0, r, t);
+    if (ri < 0) return;
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    T le[3] = {l0, l1, l2};
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        double se = 0.0, eps;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int cc[3] = {t[0], t[1], t[2]};
+                cc[C1] -= u;
+                cc[C2] -= v;
+                for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+                if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) se += eps;
+            }
+        if (se != 0.0) le[C] += (T)(A.lscale * p.dV * p.eps0 * se * 0.25 * A.ltape[C * tb + ri]);
+        int nc = 0;
+        for (int u = 0; u < 2; u++) {
+            int cc[3] = {t[0], t[1], t[2]};
+            cc[C] -= u;
+            for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
+            if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) nc++;
+        }
+        if (nc) A.lH[C][q] += (T)(A.lscale * p.dV * p.mu0 * 0.5 * nc * A.ltape[(3 + C) * tb + ri]);
+    }
+    l0 = le[0];
+    l1 = le[1];
+    l2 = le[2];
+}
+
+// the nine face values a slot's half-step pass reads, in a tile near a CPML
+// slab (FILM = 0) or a film's reach (FILM = 1)
+template <typename T, int FILM>
+__device__ __forceinline__ void hfield_general(const AdjParams<T> &A, const int *t, T *o0, T *o1, T &n1m2, T &n2m1,
+                                               T &n2m0, T &n0m2, T &n0m1, T &n1m0) {
+    const KParams<T> &p = A.p;
+    hface<T, 0, FILM>(A, t, true, o0[0], o1[0]);
+    hface<T, 1, FILM>(A, t, true, o0[1], o1[1]);
+    hface<T, 2, FILM>(A, t, true, o0[2], o1[2]);
+    T x0, x1;
+    int u[3];
+    if (nb<-1>(p.n, p.per, t, 2, u)) {
+        hface<T, 1, FILM>(A, u, false, x0, x1);
+        n1m2 = x0;
+        hface<T, 0, FILM>(A, u, false, x0, x1);
+        n0m2 = x1;
+    }
+    if (nb<-1>(p.n, p.per, t, 1, u)) {
+        hface<T, 2, FILM>(A, u, false, x0, x1);
+        n2m1 = x1;
+        hface<T, 0, FILM>(A, u, false, x0, x1);
+        n0m1 = x0;
+    }
+    if (nb<-1>(p.n, p.per, t, 0, u)) {
+        hface<T, 2, FILM>(A, u, false, x0, x1);
+        n2m0 = x0;
+        hface<T, 1, FILM>(A, u, false, x0, x1);
+        n1m0 = x1;
+    }
+}
+
+// the transposed half step on the E side: lambda E_C += the transposed curl
+// of the faces' curl-part adjoints (lambda E = ca lambda E' first when SCALE)
+template <typename T, int SCALE>
+__global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
+    const KParams<T> &p = A.p;
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= p.n[0] || j >= p.n[1]) return;
+    const int t[3] = {i, j, k};
+    const long long q = p.slot(i, j, k);
+    const uint8_t fl = A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)];
+    // own faces: aD0, aD1 of each family; neighbours, named by family and the
+    // axis of the -1 offset
+    T o0[3], o1[3];
+    T n1m2 = T(0), n2m1 = T(0), n2m0 = T(0), n0m2 = T(0), n0m1 = T(0), n1m0 = T(0);
+    int u[3];
+    if (fl == 0) {
+#pragma unroll
+        for (int F = 0; F < 3; F++) {
+            const T l = A.lH[F][q];
+            o0[F] = -(p.hc * l);
+            o1[F] = p.hc * l;
+        }
+        if (nb<-1>(p.n, p.per, t, 2, u)) n1m2 = -(p.hc * A.lH[1][p.slot(u[0], u[1], u[2])]);
+        if (nb<-1>(p.n, p.per, t, 1, u)) n2m1 = p.hc * A.lH[2][p.slot(u[0], u[1], u[2])];
+        if (nb<-1>(p.n, p.per, t, 0, u)) n2m0 = -(p.hc * A.lH[2][p.slot(u[0], u[1], u[2])]);
+        if (nb<-1>(p.n, p.per, t, 2, u)) n0m2 = p.hc * A.lH[0][p.slot(u[0], u[1], u[2])];
+        if (nb<-1>(p.n, p.per, t, 1, u)) n0m1 = -(p.hc * A.lH[0][p.slot(u[0], u[1], u[2])]);
+        if (nb<-1>(p.n, p.per, t, 0, u)) n1m0 = p.hc * A.lH[1][p.slot(u[0], u[1], u[2])];
+    } else if (fl & 4) {
+        hfield_general<T, 1>(A, t, o0, o1, n1m2, n2m1, n2m0, n0m2, n0m1, n1m0);
+    } else {
+        hfield_general<T, 0>(A, t, o0, o1, n1m2, n2m1, n2m0, n0m2, n0m1, n1m0);
+    }
+    T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
+    if (SCALE && A.btape) {
+        // dL/dca += lambda E' E^n, dL/dcb += lambda E' x^n over the eps box
+        const int r[3] = {A.bs[0] + 1, A.bs[1] + 1, A.bs[2] + 1};
+        const long long ri = region_index_folded(p.n, p.per, A.bb, r, t);
+        if (ri >= 0) {
+            const long long tb = (long long)r[0] * r[1] * r[2];
+            const T lv[3] = {l0, l1, l2};
+#pragma unroll
+            for (int C = 0; C < 3; C++) {
+                A.gca_box[C * tb + ri] += (double)lv[C] * A.btape[C * tb + ri];
+                A.gcb_box[C * tb + ri] += (double)lv[C] * A.btape[(3 + C) * tb + ri];
+            }
+        }
+    }
+    T ca0, cb0, ca1, cb1, ca2, cb2;
+    const bool v0 = edge_coef<T, 0>(p, t, q, ca0, cb0);
+    const bool v1 = edge_coef<T, 1>(p, t, q, ca1, cb1);
+    const bool v2 = edge_coef<T, 2>(p, t, q, ca2, cb2);
+    if (SCALE) {
+        l0 = v0 ? ca0 * l0 : T(0);
+        l1 = v1 ? ca1 * l1 : T(0);
+        l2 = v2 ? ca2 * l2 : T(0);
+    }
+    l0 = l0 + (dif(n1m2 - o0[1], T(0), p.dT[2], p.invd[2]) + dif(n2m1 - o1[2], T(0), p.dT[1], p.invd[1]));
+    l1 = l1 + (dif(n2m0 - o0[2], T(0), p.dT[0], p.invd[0]) + dif(n0m2 - o1[0], T(0), p.dT[2], p.invd[2]));
+    l2 = l2 + (dif(n0m1 - o0[0], T(0), p.dT[1], p.invd[1]) + dif(n1m0 - o1[1], T(0), p.dT[0], p.invd[0]));
+    if (SCALE && A.ltape && (fl & 4) && A.seg0[0] + A.m > A.loss_from)
+        loss_term(A, t, q, l0, l1, l2);
+    A.lE[0][q] = l0;
+    A.lE[1][q] = l1;
+    A.lE[2][q] = l2;
+    if (!SCALE) {
+        // the E-step adjoint's input: cb lambda E' (zero on a wall or PEC edge)
+        A.mu[0][q] = v0 ? cb0 * l0 : T(0);
+        A.mu[1][q] = v1 ? cb1 * l1 : T(0);
+        A.mu[2][q] = v2 ? cb2 * l2 : T(0);
+    }
+}
+
+// curl-part adjoints (eD0, eD1) of the E edge of family X at slot e (in the
+// domain): mu = cb lambda E' with the CPML recursions along X+1 (in1 -> out1)
+// and X+2 (in2 -> out2); own: store lambda psiE after the map.  (On a wall or
+// PEC edge mu is zero, and so stays its lambda psiE.)
+template <typename T, int X, int PML>
+__device__ __forceinline__ void eedge(const AdjParams<T> &A, const int *e, bool own, const T *in1, const T *in2,
+                                      T *out1, T *out2, T &eD0, T &eD1) {
+    constexpr int X1 = (X + 1) % 3, X2 = (X + 2) % 3;
+    const KParams<T> &p = A.p;
+    const T lx = A.mu[X][p.slot(e[0], e[1], e[2])];
+    eD0 = lx;
+    eD1 = -lx;
+    if (PML) {
+        const int a1 = e[X1], a2 = e[X2];
+        if (p.psiE[X][X1] && (a1 < p.nlo[X1] || a1 >= p.n[X1] - p.nhi[X1])) {
+            const long long q1 = p.psi_index(X1, e);
+            const T aps = in1[q1] + lx;
+            if (own) out1[q1] = p.bE[X1][a1] * aps;
+            eD0 = lx + p.cE[X1][a1] * aps;
+        }
+        if (p.psiE[X][X2] && (a2 < p.nlo[X2] || a2 >= p.n[X2] - p.nhi[X2])) {
+            const long long q2 = p.psi_index(X2, e);
+            const T aps = in2[q2] - lx;
+            if (own) out2[q2] = p.bE[X2][a2] * aps;
+            eD1 = -lx + p.cE[X2][a2] * aps;
+        }
+    }
+}
+
+// the transposed E step on the H side: lambda H_C += the transposed curl of
+// the edges' curl-part adjoints; lambda E' itself is scaled by ca in the
+// next half-step pass
+template <typename T, int PML>
+__device__ __forceinline__ void efield_body(const AdjParams<T> &A, const int *t, long long q) {
+    const KParams<T> &p = A.p;
+    const bool par = PML ? (((A.seg0[0] + A.m) & 1) != 0) : false;
+    // lambda psiE of step n: read set n & 1, write the other (one select per
+    // pointer: indexing the parameter block through a pointer would copy it
+    // to scratch)
+    const T *i0a = par ? A.lpsiE2[0][1] : A.lpsiE[0][1], *i0b = par ? A.lpsiE2[0][2] : A.lpsiE[0][2];
+    const T *i1a = par ? A.lpsiE2[1][2] : A.lpsiE[1][2], *i1b = par ? A.lpsiE2[1][0] : A.lpsiE[1][0];
+    const T *i2a = par ? A.lpsiE2[2][0] : A.lpsiE[2][0], *i2b = par ? A.lpsiE2[2][1] : A.lpsiE[2][1];
+    T *o0a = par ? A.lpsiE[0][1] : A.lpsiE2[0][1], *o0b = par ? A.lpsiE[0][2] : A.lpsiE2[0][2];
+    T *o1a = par ? A.lpsiE[1][2] : A.lpsiE2[1][2], *o1b = par ? A.lpsiE[1][0] : A.lpsiE2[1][0];
+    T *o2a = par ? A.lpsiE[2][0] : A.lpsiE2[2][0], *o2b = par ? A.lpsiE[2][1] : A.lpsiE2[2][1];
+    T o0[3], o1[3], x0, x1;
+    eedge<T, 0, PML>(A, t, true, i0a, i0b, o0a, o0b, o0[0], o1[0]);
+    eedge<T, 1, PML>(A, t, true, i1a, i1b, o1a, o1b, o0[1], o1[1]);
+    eedge<T, 2, PML>(A, t, true, i2a, i2b, o2a, o2b, o0[2], o1[2]);
+    T n1p2 = T(0), n2p1 = T(0), n2p0 = T(0), n0p2 = T(0), n0p1 = T(0), n1p0 = T(0);
+    int u[3];
+    if (nb<1>(p.n, p.per, t, 2, u)) {
+        eedge<T, 1, PML>(A, u, false, i1a, i1b, o1a, o1b, x0, x1);
+        n1p2 = x0;
+        eedge<T, 0, PML>(A, u, false, i0a, i0b, o0a, o0b, x0, x1);
+        n0p2 = x1;
+    }
+    if (nb<1>(p.n, p.per, t, 1, u)) {
+        eedge<T, 2, PML>(A, u, false, i2a, i2b, o2a, o2b, x0, x1);
+        n2p1 = x1;
+        eedge<T, 0, PML>(A, u, false, i0a, i0b, o0a, o0b, x0, x1);
+        n0p1 = x0;
+    }
+    if (nb<1>(p.n, p.per, t, 0, u)) {
+        eedge<T, 2, PML>(A, u, false, i2a, i2b, o2a, o2b, x0, x1);
+        n2p0 = x0;
+        eedge<T, 1, PML>(A, u, false, i1a, i1b, o1a, o1b, x0, x1);
+        n1p0 = x1;
+    }
+    A.lH[0][q] = A.lH[0][q] + (dif(o0[1] - n1p2, T(0), p.dT[2], p.invd[2]) + dif(o1[2] - n2p1, T(0), p.dT[1], p.invd[1]));
+    A.lH[1][q] = A.lH[1][q] + (dif(o0[2] - n2p0, T(0), p.dT[0], p.invd[0]) + dif(o1[0] - n0p2, T(0), p.dT[2], p.invd[2]));
+    A.lH[2][q] = A.lH[2][q] + (dif(o0[0] - n0p1, T(0), p.dT[1], p.invd[1]) + dif(o1[1] - n1p0, T(0), p.dT[0], p.invd[0]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_efield(AdjParams<T> A) {
+    const KParams<T> &p = A.p;
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= p.n[0] || j >= p.n[1]) return;
+    const int t[3] = {i, j, k};
+    const long long q = p.slot(i, j, k);
+    if (A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] & 1)
+        efield_body<T, 1>(A, t, q);
+    else
+        efield_body<T, 0>(A, t, q);
 }
 
 __global__ void __launch_bounds__(256) k_copy_segs(const CopySeg *segs) {
@@ -1017,21 +1319,6 @@ hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hi
 long long film_tape_size(const int *cb) { return 6LL * (cb[3] + 1) * (cb[4] + 1) * (cb[5] + 1); }
 long long box_tape_size(const int *box) { return 6LL * (box[3] + 1) * (box[4] + 1) * (box[5] + 1); }
 
-template <typename T>
-hipError_t launch_adj_half_tape(const AdjParams<T> &A, int nblk, hipStream_t s) {
-    if (nblk) k_adj_film<T><<<dim3(nblk), dim3(256), 0, s>>>(A);
-    k_adj_face<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
-    k_adj_curlE<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_adj_estep_lean(const AdjParams<T> &A, hipStream_t s) {
-    k_adj_estep_lean<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
-    k_adj_curlH<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
-    return hipGetLastError();
-}
-
 // cb: the film's cell box (it sizes the grid)
 template <typename T>
 hipError_t launch_tape_loss(const KParams<T> &p, int film, int merged, double *dst, hipStream_t s, const int *cb) {
@@ -1058,21 +1345,32 @@ hipError_t launch_tape_box(const KParams<T> &p, const int *box, double *dst, hip
 }
 
 template <typename T>
-hipError_t launch_adj_box(const AdjParams<T> &A, const int *box, const double *tape, double *gca, double *gcb,
-                          hipStream_t s) {
-    const long long tb = box_tape_size(box) / 6;
-    k_adj_box<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(
-        A, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), tape, gca, gcb);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double *gca, const double *gcb, double *out,
                               hipStream_t s) {
     const long long nc = (long long)box[3] * box[4] * box[5];
     if (nc == 0) return hipSuccess;
     k_adj_eps_box<T><<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s>>>(
         p, make_int4(box[0], box[1], box[2], 0), make_int4(box[3], box[4], box[5], 0), gca, gcb, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_half_fused(const AdjParams<T> &A, int nblk, int scale, const long long *film_nr,
+                                 hipStream_t s) {
+    if (nblk) k_adj_film<T><<<dim3(nblk), dim3(256), 0, s>>>(A);
+    for (int f = 0; f < A.p.nfilm; f++)
+        if (film_nr[f] > 0)
+            k_adj_film_faces<T><<<dim3((unsigned)((film_nr[f] + 255) / 256), 3), dim3(256), 0, s>>>(A, f);
+    if (scale)
+        k_adj_hfield<T, 1><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    else
+        k_adj_hfield<T, 0><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_estep_fused(const AdjParams<T> &A, hipStream_t s) {
+    k_adj_efield<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
     return hipGetLastError();
 }
 
@@ -1088,14 +1386,12 @@ hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t
     template hipError_t launch_adj_loss<T>(const AdjParams<T> &, int, double, hipStream_t);    \
     template hipError_t launch_adj_eps<T>(const AdjParams<T> &, const int *, double *, hipStream_t);      \
     template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t); \
-    template hipError_t launch_adj_half_tape<T>(const AdjParams<T> &, int, hipStream_t);                        \
-    template hipError_t launch_adj_estep_lean<T>(const AdjParams<T> &, hipStream_t);                            \
+    template hipError_t launch_adj_half_fused<T>(const AdjParams<T> &, int, int, const long long *, hipStream_t); \
+    template hipError_t launch_adj_estep_fused<T>(const AdjParams<T> &, hipStream_t);                           \
     template hipError_t launch_tape_loss<T>(const KParams<T> &, int, int, double *, hipStream_t, const int *);   \
     template hipError_t launch_adj_loss_tape<T>(const AdjParams<T> &, int, double, const double *,              \
                                                 const long long *, int, long long, hipStream_t, const int *);   \
     template hipError_t launch_tape_box<T>(const KParams<T> &, const int *, double *, hipStream_t);             \
-    template hipError_t launch_adj_box<T>(const AdjParams<T> &, const int *, const double *, double *, double *, \
-                                          hipStream_t);                                                         \
     template hipError_t launch_adj_eps_box<T>(const KParams<T> &, const int *, const double *, const double *,   \
                                               double *, hipStream_t);
 MPX_ADJ(float)

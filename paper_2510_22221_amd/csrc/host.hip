@@ -960,6 +960,11 @@ struct AdjHost {
     double *d_part = nullptr, *d_loss = nullptr, *d_out = nullptr;
     double *gbox_a = nullptr, *gbox_b = nullptr; // tape schedule: dL/dca, dL/dcb over the eps box's edges
     long long *d_seg0 = nullptr;                 // tape schedule: first step of the segment in hand
+    void *lpsiH2[3][3] = {}, *lpsiE2[3][3] = {};  // tape schedule: second lambda psi sets
+    uint8_t *d_aflags = nullptr;
+    void *mu[3] = {};
+    std::vector<double *> aDr;
+    std::vector<long long> film_nr;
 };
 
 void adj_free(AdjHost &h) {
@@ -987,6 +992,14 @@ void adj_free(AdjHost &h) {
     }
     (void)hipFree(h.d_af);
     (void)hipFree(h.d_af2);
+    for (int c = 0; c < 3; c++)
+        for (int a = 0; a < 3; a++) {
+            (void)hipFree(h.lpsiH2[c][a]);
+            (void)hipFree(h.lpsiE2[c][a]);
+        }
+    (void)hipFree(h.d_aflags);
+    for (int c = 0; c < 3; c++) (void)hipFree(h.mu[c]);
+    for (double *d : h.aDr) (void)hipFree(d);
     (void)hipFree(h.gbox_a);
     (void)hipFree(h.gbox_b);
     (void)hipFree(h.d_seg0);
@@ -996,6 +1009,9 @@ void adj_free(AdjHost &h) {
     h = AdjHost();
 }
 
+// full_eps: the plain schedule's per-edge dL/dca, dL/dcb and curl-part
+// adjoint arrays (the tape schedule keeps box accumulators and computes the
+// curl parts on the fly)
 mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout, bool full_eps = true) {
     const size_t fb = s->nslot * s->esz;
     auto z = [&](void **p, size_t bytes) -> mpx_status {
@@ -1010,8 +1026,9 @@ mpx_status adj_alloc(mpx_sim *s, AdjHost &h, long long nout, bool full_eps = tru
             if ((r = z((void **)&h.gca[c], s->nslot * sizeof(double))) != MPX_OK) return r;
             if ((r = z((void **)&h.gcb[c], s->nslot * sizeof(double))) != MPX_OK) return r;
         }
-        for (int w = 0; w < 2; w++)
-            if ((r = z(&h.aD[c][w], fb)) != MPX_OK || (r = z(&h.eD[c][w], fb)) != MPX_OK) return r;
+        if (full_eps)
+            for (int w = 0; w < 2; w++)
+                if ((r = z(&h.aD[c][w], fb)) != MPX_OK || (r = z(&h.eD[c][w], fb)) != MPX_OK) return r;
         for (int a = 0; a < 3; a++)
             if (s->psiE[c][a]) {
                 if ((r = z(&h.lpsiE[c][a], psi_count(s, a) * s->esz)) != MPX_OK) return r;
@@ -1442,7 +1459,71 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
     auto body = [&]() -> mpx_status {
         mpx_status q;
         if ((q = adj_alloc(s, h, neps, false)) != MPX_OK) return q;
+        for (int c = 0; c < 3; c++) {
+            CK(hipMalloc(&h.mu[c], s->nslot * s->esz));
+            CK(hipMemsetAsync(h.mu[c], 0, s->nslot * s->esz, st));
+        }
+        // second lambda psi sets (the field passes read one and write the other)
+        for (int c = 0; c < 3; c++)
+            for (int a = 0; a < 3; a++)
+                if (s->psiE[c][a]) {
+                    const size_t b = psi_count(s, a) * s->esz;
+                    CK(hipMalloc(&h.lpsiH2[c][a], b));
+                    CK(hipMalloc(&h.lpsiE2[c][a], b));
+                    CK(hipMemsetAsync(h.lpsiH2[c][a], 0, b, st));
+                    CK(hipMemsetAsync(h.lpsiE2[c][a], 0, b, st));
+                }
+        // each film's reach: its face box grown by one slot (a whole periodic
+        // axis), with the table of its faces' curl-part adjoints
+        for (size_t f = 0; f < h.af.size(); f++) {
+            const FilmHost &F = s->films[f];
+            AdjFilmDev &g = h.af[f];
+            long long nr = 1;
+            for (int a = 0; a < 3; a++) {
+                if (s->per[a]) {
+                    g.r0[a] = 0;
+                    g.rn[a] = s->n[a];
+                } else {
+                    const int lo = std::max(0, F.b0[a] - 1), hi = std::min(s->n[a] - 1, F.b0[a] + F.bn[a]);
+                    g.r0[a] = lo;
+                    g.rn[a] = hi - lo + 1;
+                }
+                nr *= g.rn[a];
+            }
+            g.nr = nr;
+            double *d = nullptr;
+            CK(hipMalloc(&d, 6 * nr * sizeof(double)));
+            h.aDr.push_back(d);
+            g.aDr = d;
+            h.film_nr.push_back(nr);
+        }
+        // per-tile flags of the field passes: 1 CPML, 4 a film's reach, each
+        // within two slots of the tile
+        {
+            const int nxt = (s->n[0] + kPassTX - 1) / kPassTX, nyt = (s->n[1] + kPassTY - 1) / kPassTY;
+            const int nt = pass_tiles(s->n);
+            std::vector<uint8_t> fl(nt, 0);
+            for (int t = 0; t < nt; t++) {
+                const int i0 = (t % nxt) * kPassTX, j0 = ((t / nxt) % nyt) * kPassTY, k = t / (nxt * nyt);
+                const int lo[3] = {i0 - 2, j0 - 2, k - 2}, hi[3] = {i0 + kPassTX + 1, j0 + kPassTY + 1, k + 2};
+                uint8_t fv = 0;
+                for (int a = 0; a < 3; a++) {
+                    if (s->nlo[a] > 0 && lo[a] < s->nlo[a]) fv |= 1;
+                    if (s->nhi[a] > 0 && hi[a] >= s->n[a] - s->nhi[a]) fv |= 1;
+                }
+                for (auto &g : h.af) {
+                    bool in = true;
+                    for (int a = 0; a < 3; a++)
+                        if (g.r0[a] + g.rn[a] <= lo[a] || g.r0[a] > hi[a]) in = false;
+                    if (in) fv |= 4;
+                }
+                fl[t] = fv;
+            }
+            CK(hipMalloc(&h.d_aflags, std::max(1, nt)));
+            CK(hipMemcpy(h.d_aflags, fl.data(), nt, hipMemcpyHostToDevice));
+        }
         if (!h.af.empty()) {
+            CK(hipMemcpy(h.d_af, h.af.data(), h.af.size() * sizeof(AdjFilmDev), hipMemcpyHostToDevice));
             // lambda M ping-pong: the first map of a step reads lM and writes
             // lMout, the second reads lMout and writes lM
             std::vector<AdjFilmDev> af2 = h.af;
@@ -1555,15 +1636,43 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
             for (int m = len - 1; m >= 0; m--) {
                 AdjParams<T> A;
                 adj_params<T>(s, h, A);
+                A.aflags = h.d_aflags;
+                A.seg0 = h.d_seg0;
+                A.m = m;
+                A.btape = neps > 0 ? tp.boxp(m) : nullptr;
+                A.gca_box = h.gbox_a;
+                A.gcb_box = h.gbox_b;
+                for (int a = 0; a < 3; a++) {
+                    A.bb[a] = eps_box[a];
+                    A.bs[a] = eps_box[3 + a];
+                }
+                A.ltape = tp.lossp(m);
+                A.lfilm = film;
+                A.lscale = dt * S;
+                A.loss_from = loss_from;
+                for (int c = 0; c < 3; c++) {
+                    A.mu[c] = (T *)h.mu[c];
+                    for (int a = 0; a < 3; a++) {
+                        A.lpsiE2[c][a] = (T *)h.lpsiE2[c][a];
+                        A.lpsiHo[c][a] = (T *)h.lpsiH2[c][a];
+                    }
+                }
+                // the second half step: lambda psiH set 1 -> set 2
                 A.p.films = tvar(tp, m, V_P1);
                 A.af = h.d_af;
-                CK(launch_adj_half_tape<T>(A, nblk, st));
-                if (neps > 0) CK(launch_adj_box<T>(A, eps_box, tp.boxp(m), h.gbox_a, h.gbox_b, st));
-                CK(launch_adj_estep_lean<T>(A, st));
+                CK(launch_adj_half_fused<T>(A, nblk, 0, h.film_nr.data(), st));
+                CK(launch_adj_estep_fused<T>(A, st));
+                // the first half step (with the E step's lambda E = ca lambda E',
+                // the eps-box sums and the loss term of the step's input
+                // state): lambda psiH set 2 -> set 1
+                for (int c = 0; c < 3; c++)
+                    for (int a = 0; a < 3; a++) {
+                        A.lpsiH[c][a] = (T *)h.lpsiH2[c][a];
+                        A.lpsiHo[c][a] = (T *)h.lpsiH[c][a];
+                    }
                 A.p.films = tvar(tp, m, V_R1);
                 A.af = h.d_af2;
-                CK(launch_adj_half_tape<T>(A, nblk, st));
-                CK(launch_adj_loss_tape<T>(A, film, dt * S, tp.lossp(m), h.d_seg0, m, loss_from, st, LF.cb));
+                CK(launch_adj_half_fused<T>(A, nblk, 1, h.film_nr.data(), st));
             }
             return MPX_OK;
         };
@@ -1574,7 +1683,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
             s->step = cp[g].step;
             CK(launch_set_step(s->d_step, cp[g].step, st));
             CK(launch_set_step(h.d_seg0, c0, st));
-            if (len == K && ncp > 1) {
+            if (len == K && ncp > 1 && s->graph_steps > 0) {
                 if (!gexec) {
                     CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                     q = segment(len);

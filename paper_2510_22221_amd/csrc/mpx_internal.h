@@ -137,6 +137,12 @@ struct AdjFilmDev {
     double *lq;    // the same for Q
     double *gMs;   // [family][site] accumulated dL/dMs of the face
     double *gH0;   // [family][component][site] accumulated dL/dH0 parts
+    // fused schedule: the film's reach (faces within one slot of its face
+    // box; a whole periodic axis) and the curl-part adjoints of its faces,
+    // [family][aD0 | aD1][region slot]
+    double *aDr;
+    long long nr;
+    int r0[3], rn[3];
 };
 
 template <typename T>
@@ -148,14 +154,31 @@ struct AdjParams {
     T *eD[3][2];           // per edge: lambda of the two curl parts of H
     double *gca[3], *gcb[3]; // per edge: accumulated dL/dca, dL/dcb
     const AdjFilmDev *af;
+    // fused schedule: destination set of lambda psiH (read from lpsiH), the
+    // second lambda psiE set (the E-step adjoint of step n reads set n & 1
+    // and writes the other), per-tile flags (1 CPML, 4 film reach, with a
+    // two-slot halo), the segment's first step on the device, the step's
+    // index in the segment
+    T *lpsiHo[3][3];
+    T *lpsiE2[3][3];
+    T *mu[3];              // per edge: cb lambda E' (written by the second half-step pass)
+    // folded into the first half-step pass: dL/dca, dL/dcb over the eps box
+    // (btape: E^n and x^n of the box's edges; null for no box), and the loss
+    // term of the state at the step's start (ltape: the film region's E and H)
+    const double *btape;
+    double *gca_box, *gcb_box;
+    int bb[3], bs[3];
+    const double *ltape;
+    int lfilm;
+    double lscale;
+    long long loss_from;
+    const uint8_t *aflags;
+    const long long *seg0;
+    int m;
 };
 
 template <typename T> hipError_t launch_adj_half(const AdjParams<T> &A, int nblk, hipStream_t s);
-// tape schedule: the half-step adjoint without the lambda-M commit (the caller
-// alternates the two lambda-M buffers), the lean E-step adjoint, and the
-// film-region and box-region tapes and their adjoint kernels
-template <typename T> hipError_t launch_adj_half_tape(const AdjParams<T> &A, int nblk, hipStream_t s);
-template <typename T> hipError_t launch_adj_estep_lean(const AdjParams<T> &A, hipStream_t s);
+// tape schedule: the film-region and box-region tapes and their adjoint kernels
 template <typename T>
 hipError_t launch_tape_loss(const KParams<T> &p, int film, int merged, double *dst, hipStream_t s, const int *cb);
 template <typename T>
@@ -163,14 +186,16 @@ hipError_t launch_adj_loss_tape(const AdjParams<T> &A, int film, double scale, c
                                 const long long *seg0, int m, long long loss_from, hipStream_t s, const int *cb);
 template <typename T> hipError_t launch_tape_box(const KParams<T> &p, const int *box, double *dst, hipStream_t s);
 template <typename T>
-hipError_t launch_adj_box(const AdjParams<T> &A, const int *box, const double *tape, double *gca, double *gcb,
-                          hipStream_t s);
-template <typename T>
 hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double *gca, const double *gcb, double *out,
                               hipStream_t s);
 hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s);
 long long film_tape_size(const int *cb);
 long long box_tape_size(const int *box);
+// fused schedule: the half-step adjoint (scale = 1: first apply the E step's
+// lambda E = ca lambda E') and the E-step adjoint as one stencil pass each
+template <typename T>
+hipError_t launch_adj_half_fused(const AdjParams<T> &A, int nblk, int scale, const long long *film_nr, hipStream_t s);
+template <typename T> hipError_t launch_adj_estep_fused(const AdjParams<T> &A, hipStream_t s);
 template <typename T> hipError_t launch_adj_estep(const AdjParams<T> &A, hipStream_t s);
 template <typename T> hipError_t launch_adj_loss(const AdjParams<T> &A, int film, double scale, hipStream_t s);
 template <typename T> hipError_t launch_adj_eps(const AdjParams<T> &A, const int *box, double *out, hipStream_t s);
