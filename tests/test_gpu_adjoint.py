@@ -199,3 +199,65 @@ def test_adjoint_resonator_full_size_gpu_fd():
     ge = fd.derivative(lambda d: gpu_loss(with_material(4, 0, d)), 2e-3 * w.materials[4][0])
     say(f"  sum dL/deps adjoint {res['deps'].sum():.9e} fd {ge:.9e}")
     assert abs(res["deps"].sum() - ge) <= 1e-4 * abs(ge)
+
+
+def c4_param_workload(n, h0, eps_patch, f):
+    """The resonator with its eps_r patch at eps_patch (one material) and the
+    film's top layer at Ms f (a material of its own, same film)."""
+    w = W.c4(n)
+    w.m_dir = (0.25, 0.0, 1.0)
+    w.H0 = tuple(h0)
+    mats = list(w.materials)
+    m3 = mats[3]
+    mats[4] = (float(eps_patch),) + tuple(mats[4][1:])
+    mats.append((m3[0], m3[1], m3[2], m3[3] * f, m3[4], m3[5]))
+    ids = w.ids.copy()
+    ft = w.film_top
+    ids[ft[2], ft[1]:ft[1] + ft[4], ft[0]:ft[0] + ft[3]] = len(mats) - 1
+    w.materials = mats
+    w.ids = ids
+    return w
+
+
+def test_autograd_film_energy_loss_resonator():
+    """torch.autograd.Function over the 128 x 64 x 64 resonator, 400 steps:
+    dL/dH0_z, dL/deps_r of the patch (one parameter) and dL/df of the
+    film-thickness fraction (top layer at Ms f) against Richardson central
+    differences of the GPU forward run (float64)."""
+    import torch
+    from paper_2510_22221_amd import grad as G
+
+    n, n0 = 400, 200
+    w0 = W.c4(n)
+    ms_top = w0.materials[3][3]
+    h0 = (0.0, 0.0, w0.H0[2])
+
+    def make_sim(h, e, f):
+        return mpx.from_workload(c4_param_workload(n, h, float(e), f), precision=mpx.F64)
+
+    spec = G.FilmEnergySpec(make_sim, n, n0, eps_box=w0.patch_box, top_box=w0.film_top, ms_top=ms_top)
+    H0 = torch.tensor(h0, dtype=torch.float64, requires_grad=True)
+    eps = torch.tensor(11.7, dtype=torch.float64, requires_grad=True)
+    f = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    say("autograd C4: forward + adjoint")
+    L = G.film_energy_loss(H0, eps, f, spec)
+    (2.0 * L).backward()  # the upstream gradient scales every result
+
+    def gpu_loss(h, e, fv):
+        s = make_sim(h, e, fv)
+        s.step(n)
+        tr = s.read_probe(0, 1)
+        s.close()
+        return w0.dt * float(np.sum(tr[n0:n]))
+
+    assert L.item() == pytest.approx(gpu_loss(h0, 11.7, 1.0), rel=1e-12)
+    gz = fd.derivative(lambda d: gpu_loss((0.0, 0.0, h0[2] + d), 11.7, 1.0), 2e-4 * h0[2])
+    gf = fd.derivative(lambda d: gpu_loss(h0, 11.7, 1.0 + d), 2e-3)
+    ge = fd.derivative(lambda d: gpu_loss(h0, 11.7 + d, 1.0), 2e-3 * 11.7)
+    say(f"  dL/dH0z {H0.grad[2].item() / 2:.9e} fd {gz:.9e}")
+    say(f"  dL/df   {f.grad.item() / 2:.9e} fd {gf:.9e}")
+    say(f"  dL/deps {eps.grad.item() / 2:.9e} fd {ge:.9e}")
+    assert close(H0.grad[2].item() / 2, gz, abs(gz))
+    assert close(f.grad.item() / 2, gf, abs(gf))
+    # the patch's weak coupling: see the resonator test above
+    assert abs(eps.grad.item() / 2 - ge) <= 1e-4 * abs(ge)
