@@ -9,8 +9,10 @@ strips, a 400 x 60 x 4-cell film, PML 10 on every face (synthetic, seeded).
 
 Prints one JSON line: Gcell-updates/s in float32 (float64 in "secondary"),
 the roofline of the dominant kernel measured with HIP events on the
-library's stream over the timed region, and the float64 CPU oracle timed on
-a bounded sample of the same workload.
+library's stream over the timed region, the batched bias sweep against
+sequential runs, the adjoint's cost against the forward run on the
+128 x 64 x 64 resonator, and the float64 CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -165,6 +167,42 @@ def batched_sweep(steps, n_inst, variant=None, kchunk=None):
             "schedule": ("separate E and H/M passes" if not variant else f"fused pass, variant {variant}")}
 
 
+def adjoint_cost(steps, window, graphs=True):
+    """The adjoint of the 128 x 64 x 64 resonator + film + eps_r patch
+    workload: loss = film EM energy summed over the last `window` of `steps`
+    time steps, gradients w.r.t. H0, eps_r of each of the 32 x 16 x 4 patch
+    cells and Ms of the film's top layer (the thickness fraction), sqrt(N)
+    checkpoints; its wall time against the forward run of the same steps."""
+    from paper_2510_22221_amd import mpx
+    from synth import workloads as W
+
+    w = W.c4(steps + 10)
+    out = {"workload": f"resonator + film + eps_r patch, {w.nx}x{w.ny}x{w.nz} cells, d=(40,2,2) um, PML 8",
+           "steps": steps, "loss_window": window, "eps_cells": int(w.patch_box[3] * w.patch_box[4] * w.patch_box[5]),
+           "schedule": "tape, fused field passes"}
+    gs = None if graphs else 0
+    for name, prec in (("f32", mpx.F32), ("f64", mpx.F64)):
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        s.step(50)
+        s.sync()
+        s.close()
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        fwd = time.perf_counter() - t0
+        s.close()
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        t0 = time.perf_counter()
+        r = s.adjoint(steps, steps - window, eps_box=w.patch_box, ms_box=w.film_top)
+        adj = time.perf_counter() - t0
+        s.close()
+        out[name] = {"forward_s": round(fwd, 4), "adjoint_s": round(adj, 4), "adjoint_over_forward": round(adj / fwd, 3),
+                     "loss": r["loss"], "dL_dH0z": float(r["dH0"][2])}
+        log(f"  adjoint {name}: forward {fwd:.3f} s, adjoint {adj:.3f} s, ratio {adj / fwd:.2f}")
+    return out
+
+
 def cpu_baseline(w, nsteps):
     import oracle.oracle as O
     O.build()
@@ -199,6 +237,10 @@ def main():
                     help="0: separate E and H/M passes (default); 1-5: fused pass variants")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
     ap.add_argument("--sweep-instances", type=int, default=64)
+    ap.add_argument("--adjoint-steps", type=int, default=20000, help="steps of the adjoint cost run (0: skip)")
+    ap.add_argument("--adjoint-window", type=int, default=5000)
+    ap.add_argument("--adjoint-no-graphs", action="store_true",
+                    help="launch the adjoint's kernels directly (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
@@ -246,6 +288,10 @@ def main():
     if args.sweep_steps > 0:
         log(f"batched bias sweep: {args.sweep_instances} instances, {args.sweep_steps} steps")
         out["batched_sweep"] = batched_sweep(args.sweep_steps, args.sweep_instances)
+    if args.adjoint_steps > 0:
+        log(f"adjoint: {args.adjoint_steps} steps, loss over the last {args.adjoint_window}")
+        out["adjoint"] = adjoint_cost(args.adjoint_steps, min(args.adjoint_window, args.adjoint_steps),
+                                      graphs=not args.adjoint_no_graphs)
     if not args.no_cpu:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
