@@ -211,9 +211,11 @@ __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by,
 
 // grid (x tiles, y tiles, planes) in natural order: the blocks resident at
 // one time cover a few consecutive planes, so neighbour rows and planes are
-// cache hits, and no block decodes its tile with divisions
+// cache hits, and no block decodes its tile with divisions.  In float32 the
+// E pass is held to 64 VGPRs (8 waves per SIMD; it fits without spilling).
 template <typename T>
-__global__ void __launch_bounds__(PTX *PTY) k_epass(KParams<T> p) {
+__global__ void __launch_bounds__(PTX *PTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
+k_epass(KParams<T> p) {
     epass_block<T>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
