@@ -261,3 +261,61 @@ def test_autograd_film_energy_loss_resonator():
     assert close(f.grad.item() / 2, gf, abs(gf))
     # the patch's weak coupling: see the resonator test above
     assert abs(eps.grad.item() / 2 - ge) <= 1e-4 * abs(ge)
+
+
+def two_film_case():
+    """The PML box with a second, separate one-layer film two cells above the
+    first (its own connected set of magnetic cells, so a film of its own;
+    one cell clear of the z slab)."""
+    w = small_case(True)
+    ids = w.ids.copy()
+    assert not np.any(ids[9:12] == 3)
+    ids[10, 5:10, 6:12] = 3
+    w.ids = ids
+    return w
+
+
+def test_adjoint_two_films_oracle_fd():
+    """Loss on the second film of two: dL/dH0 and dL/dMs of a cell of each
+    film against the oracle's central differences (the films' reaches, the
+    gathers across films and the per-film tables)."""
+    w = two_film_case()
+    n, n0 = 50, 20
+    g = mpx.from_workload(w, precision=mpx.F64)
+    boxes = g.films()
+    assert len(boxes) == 2, boxes
+    # films are numbered by their lowest cell: film 1 is the new upper one
+    lf = 1
+    say(f"adjoint two films: boxes {boxes}")
+    cell_lo, cell_hi = (8, 7, 10), (8, 6, 7)
+    ms_box = (8, 6, 7, 1, 2, 4)
+    res = g.adjoint(n, n0, film=lf, ms_box=ms_box, checkpoint_every=6)
+    L = fd.loss(w, n, n0, film=lf)
+    assert res["loss"] == pytest.approx(L, rel=1e-12)
+    gh = [fd.grad_H0(w, n, n0, c, film=lf) for c in range(3)]
+    say(f"  dL/dH0 adjoint {res['dH0']} fd {gh}")
+    sc = max(abs(v) for v in gh)
+    for c in range(3):
+        assert close(res["dH0"][c], gh[c], sc), c
+    for cell in (cell_lo, cell_hi):
+        got = res["dMs"][cell[2] - ms_box[2], cell[1] - ms_box[1], cell[0] - ms_box[0]]
+        ref = fd.grad_Ms(w, n, n0, cell, film=lf)
+        say(f"  dL/dMs {cell} adjoint {got:.9e} fd {ref:.9e}")
+        assert close(got, ref, abs(ref)), cell
+
+
+def test_tape_schedule_eps_box_at_periodic_face():
+    """An eps box ending on the upper face of a periodic axis (its edge
+    region wraps to index 0): tape and plain schedules agree."""
+    w = periodic_case()
+    eps_box = (w.nx - 3, 2, 2, 3, 4, 3)
+    out = []
+    for sched in (0, 1):
+        g = mpx.from_workload(w, precision=mpx.F64)
+        g.set_adjoint_schedule(sched)
+        out.append(g.adjoint(30, 5, film=0, checkpoint_every=4, eps_box=eps_box))
+        g.close()
+    a, b = out
+    sc = float(np.abs(b["deps"]).max())
+    assert sc > 0
+    assert float(np.abs(a["deps"] - b["deps"]).max()) <= 1e-10 * sc
