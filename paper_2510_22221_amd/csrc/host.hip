@@ -97,6 +97,7 @@ struct mpx_sim {
     int probe_maxpart = 0; // most partial-sum blocks of a film-energy probe
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
+    uint8_t *d_pflags_w = nullptr; // the same for the wide tiles (when nx >= kWideMinNx)
     int4 *d_mixed = nullptr;     // slots whose eight cells do not share one id
     int nmixed = 0;
     long long *d_step = nullptr;
@@ -261,6 +262,8 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     for (int i = 0; i < p.nsrc; i++) p.src[i] = s->srcs[i].dev;
     p.srcs = s->d_srcs;
     p.pflags = s->d_pflags;
+    p.pflags_w = s->d_pflags_w;
+    p.wide = s->d_pflags_w != nullptr;
     p.mixed = s->d_mixed;
     p.nmixed = s->nmixed;
     p.probes = s->d_probes;
@@ -587,17 +590,17 @@ mpx_status check_live(mpx_sim *s) {
     return MPX_OK;
 }
 
-// per-tile flags of the separate passes (64 x 4 slots of one plane, with a
+// per-tile flags of the separate passes (tx x ty slots of one plane, with a
 // one-slot halo): 1 = touches a CPML slab, 2 = a source box, 4 = a film's
 // face box; with a periodic axis every tile may see index 0 through the wrap
-mpx_status update_pass_flags(mpx_sim *s) {
-    const int nxt = (s->n[0] + kPassTX - 1) / kPassTX, nyt = (s->n[1] + kPassTY - 1) / kPassTY;
-    const int nt = pass_tiles(s->n);
+std::vector<uint8_t> tile_flags(const mpx_sim *s, int tx, int ty) {
+    const int nxt = (s->n[0] + tx - 1) / tx, nyt = (s->n[1] + ty - 1) / ty;
+    const int nt = nxt * nyt * s->n[2];
     std::vector<uint8_t> fl(nt, 0);
     const bool wrap = s->per[0] || s->per[1] || s->per[2];
     for (int t = 0; t < nt; t++) {
-        const int i0 = (t % nxt) * kPassTX, j0 = ((t / nxt) % nyt) * kPassTY, k = t / (nxt * nyt);
-        const int lo[3] = {i0 - 1, j0 - 1, k - 1}, hi[3] = {i0 + kPassTX, j0 + kPassTY, k + 1};
+        const int i0 = (t % nxt) * tx, j0 = ((t / nxt) % nyt) * ty, k = t / (nxt * nyt);
+        const int lo[3] = {i0 - 1, j0 - 1, k - 1}, hi[3] = {i0 + tx, j0 + ty, k + 1};
         uint8_t f = 0;
         for (int a = 0; a < 3; a++) {
             if (s->nlo[a] > 0 && lo[a] < s->nlo[a]) f |= 1;
@@ -617,10 +620,22 @@ mpx_status update_pass_flags(mpx_sim *s) {
         }
         fl[t] = f;
     }
+    return fl;
+}
+
+mpx_status update_pass_flags(mpx_sim *s) {
+    const std::vector<uint8_t> fl = tile_flags(s, kPassTX, kPassTY);
     (void)hipFree(s->d_pflags);
     s->d_pflags = nullptr;
-    CK(hipMalloc(&s->d_pflags, std::max(1, nt)));
-    CK(hipMemcpy(s->d_pflags, fl.data(), nt, hipMemcpyHostToDevice));
+    CK(hipMalloc(&s->d_pflags, std::max<size_t>(1, fl.size())));
+    CK(hipMemcpy(s->d_pflags, fl.data(), fl.size(), hipMemcpyHostToDevice));
+    (void)hipFree(s->d_pflags_w);
+    s->d_pflags_w = nullptr;
+    if (s->n[0] >= kWideMinNx) {
+        const std::vector<uint8_t> fw = tile_flags(s, kWideTX, kWideTY);
+        CK(hipMalloc(&s->d_pflags_w, std::max<size_t>(1, fw.size())));
+        CK(hipMemcpy(s->d_pflags_w, fw.data(), fw.size(), hipMemcpyHostToDevice));
+    }
     return MPX_OK;
 }
 
@@ -1865,6 +1880,7 @@ mpx_status mpx_destroy(mpx_sim *s) {
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_srcs);
     (void)hipFree(s->d_pflags);
+    (void)hipFree(s->d_pflags_w);
     (void)hipFree(s->d_mixed);
     (void)hipFree(s->d_id);
     (void)hipFree(s->d_cls);

@@ -84,6 +84,10 @@ struct KParams {
     const uint8_t *id;
     const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
     const uint8_t *pflags; // per separate-pass tile: 1 CPML, 2 source, 4 film within reach
+    // wide = 1: the single-instance passes use 256 x 1 tiles (rows of at least
+    // two tiles), with their flags in pflags_w; batches keep the 64 x 4 tiles
+    const uint8_t *pflags_w;
+    int wide;
     const int4 *mixed;     // slots whose eight cells do not share one id (i, j, k, -)
     int nmixed;
     const MatDev *mat;
@@ -216,6 +220,8 @@ hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwo
                               hipStream_t s);
 int pass_tiles(const int *n);
 constexpr int kPassTX = 64, kPassTY = 4; // separate-pass tile: 64 x 4 slots of one plane
+constexpr int kWideTX = 256, kWideTY = 1; // the wide tile of the single-instance passes
+constexpr int kWideMinNx = 512;           // grids this wide use it
 
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
