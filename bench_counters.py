@@ -28,6 +28,7 @@ import csv
 import glob
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -81,7 +82,7 @@ def pick(counters, key):
 # kernels whose traffic is recorded: the bench's roofline key and a
 # predicate on the rocprofv3 kernel name
 KERNELS = {"e_pass": lambda k: "k_epass<" in k and "batch" not in k,
-           "h_pass": lambda k: "k_hbulk<" in k and ", 2>" in k and "batch" not in k,
+           "h_pass": lambda k: re.search(r"k_hbulk<\w+, 2[,>]", k) is not None and "batch" not in k,
            "fused": lambda k: ("k_sweep<" in k or "k_fused<" in k) and "batch" not in k}
 
 
