@@ -207,13 +207,13 @@ __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by,
 // narrow ones).  In float32 the E pass is held to 64 VGPRs (8 waves per
 // SIMD; it fits without spilling).
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
 k_epass(KParams<T> p) {
     epass_block<T, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int NHALF, int TX, int TY>
-__global__ void __launch_bounds__(256) k_hbulk(KParams<T> p, int inc_step) {
+__global__ void __launch_bounds__(TX *TY) k_hbulk(KParams<T> p, int inc_step) {
     if (inc_step && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0)
         p.step[0] = p.step[0] + 1;
     hpass_block<T, NHALF, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
