@@ -319,3 +319,27 @@ def test_tape_schedule_eps_box_at_periodic_face():
     sc = float(np.abs(b["deps"]).max())
     assert sc > 0
     assert float(np.abs(a["deps"] - b["deps"]).max()) <= 1e-10 * sc
+
+
+def test_tape_schedule_from_a_later_step():
+    """The adjoint started after some forward steps (the source tables and
+    the step counter are absolute, the loss window relative; no initial-M
+    term): tape and plain schedules agree, and both equal stepping on."""
+    w = small_case(True)
+    fc = np.argwhere(w.ids == 3)
+    lo = fc.min(axis=0)
+    eps_box = (int(lo[2]), int(lo[1]), int(lo[0]) - 3, 4, 3, 2)
+    out = []
+    for sched in (0, 1):
+        g = mpx.from_workload(w, precision=mpx.F64)
+        g.step(7)
+        g.set_adjoint_schedule(sched)
+        out.append(g.adjoint(26, 9, film=0, checkpoint_every=5, eps_box=eps_box))
+        assert g.info()["step"] == 33
+        g.close()
+    a, b = out
+    assert a["loss"] == pytest.approx(b["loss"], rel=1e-13)
+    for key in ("dH0", "deps"):
+        sc = float(np.abs(b[key]).max())
+        assert sc > 0, key
+        assert float(np.abs(a[key] - b[key]).max()) <= 1e-10 * sc, key
