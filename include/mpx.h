@@ -273,6 +273,29 @@ mpx_status mpx_adjoint(mpx_sim *sim, int64_t nsteps, int64_t loss_from, int32_t 
                        const int32_t eps_box[6], const int32_t ms_box[6], double *loss, double *dL_dH0,
                        double *dL_deps, double *dL_dMs);
 
+/* The same gradients (dL_dH0[3], dL_deps over eps_box, dL_dMs over ms_box,
+ * as for mpx_adjoint) of a weighted trace of one E component at one edge:
+ *   L = sum over i = 0 .. nsteps-1 of weights[i] * E_field(i, j, k) after
+ *       step i+1,
+ * i.e. the inner product of a field probe's record with a weight sequence.
+ * Spectral functionals of a probe trace (a mode's amplitude at a frequency,
+ * the frequency split of the two hybrid modes) are functions of the record;
+ * their gradients follow by the chain rule with weights = dF/d(record) (the
+ * anti-crossing splitting of Results, "Numerically Predicted Strong
+ * Magnon-Photon Coupling Phenomena", is one: its derivative with respect to
+ * the trace gives the weights).
+ *   field      0, 1, 2 for E_x, E_y, E_z;
+ *   ijk        a stored site (0 <= ijk[a] < the grid's size on axis a);
+ *   weights    nsteps finite host values (read during the call only).
+ * Tape schedule only (mpx_set_adjoint_schedule 0).  Memory, checkpoints and
+ * the state on return as for mpx_adjoint.  Synchronous.
+ * Errors: MPX_E_INVALID (arguments, a non-finite weight), MPX_E_STATE,
+ * MPX_E_UNSUPPORTED under schedule 1, MPX_E_NOMEM / MPX_E_DEVICE. */
+mpx_status mpx_adjoint_probe(mpx_sim *sim, int64_t nsteps, int32_t field, const int32_t ijk[3],
+                             const double *weights, int32_t checkpoint_every, const int32_t eps_box[6],
+                             const int32_t ms_box[6], double *loss, double *dL_dH0, double *dL_deps,
+                             double *dL_dMs);
+
 /* Reverse-sweep schedule of mpx_adjoint (same gradients up to rounding):
  *   0 (default) tape: each checkpoint segment is recomputed once while the
  *     values the adjoint maps read are taped, then its adjoint steps run

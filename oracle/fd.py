@@ -1,9 +1,11 @@
-"""The film-energy loss of a workload on the FP64 oracle and its central
-finite differences (TEST INFRASTRUCTURE ONLY: the reference the adjoint
-gradients are checked against; shares no code with the HIP library).
+"""Two losses of a workload on the FP64 oracle and their central finite
+differences (TEST INFRASTRUCTURE ONLY: the reference the adjoint gradients
+are checked against; shares no code with the HIP library).
 
-L = dt * sum over steps n = loss_from+1 .. nsteps of W_f(n), W_f the film
-EM energy the oracle's film-energy probe records at integer time n.
+Film energy: L = dt * sum over steps n = loss_from+1 .. nsteps of W_f(n),
+W_f the film EM energy the oracle's film-energy probe records at integer
+time n.  Weighted trace: L = sum_i weights[i] * E_c(i, j, k) after step
+i+1, the oracle's field probe record dotted with a weight sequence.
 Parameters: the bias H0 (component w), eps_r of one cell, Ms of one cell
 (each perturbed cell gets a material of its own).
 """
@@ -24,6 +26,16 @@ def loss(w, nsteps: int, loss_from: int, film: int = 0, threads=None) -> float:
     s.step(nsteps)
     tr = np.asarray(s.read_probe(pid, 1), dtype=np.float64).ravel()
     return float(w.dt * tr[loss_from:nsteps].sum())
+
+
+def trace_loss(w, nsteps: int, field: int, ijk, weights, threads=None) -> float:
+    w = copy.copy(w)
+    w.probes = []
+    s = O.from_workload(w, threads=threads)
+    pid = s.add_probe(O.PROBE_FIELD, field=field, ijk=tuple(ijk), cap=nsteps)
+    s.step(nsteps)
+    tr = np.asarray(s.read_probe(pid, 1), dtype=np.float64).ravel()
+    return float(np.dot(np.asarray(weights, dtype=np.float64), tr[:nsteps]))
 
 
 def _with_cell_material(w, cell, **change):
@@ -60,26 +72,39 @@ def derivative(f, h: float) -> float:
 
 
 def grad_H0(w, nsteps, loss_from, comp, rel=2e-3, film=0, threads=None) -> float:
+    return grad_H0_of(lambda w2: loss(w2, nsteps, loss_from, film, threads), w, comp, rel)
+
+
+def grad_eps(w, nsteps, loss_from, cell, rel=2e-3, film=0, threads=None) -> float:
+    return grad_eps_of(lambda w2: loss(w2, nsteps, loss_from, film, threads), w, cell, rel)
+
+
+def grad_Ms(w, nsteps, loss_from, cell, rel=2e-3, film=0, threads=None) -> float:
+    return grad_Ms_of(lambda w2: loss(w2, nsteps, loss_from, film, threads), w, cell, rel)
+
+
+# the same derivatives of any loss f(workload) -> float
+
+
+def grad_H0_of(f, w, comp, rel=2e-3) -> float:
     h = rel * max(abs(v) for v in w.H0)
 
-    def f(d):
+    def g(d):
         w2 = copy.copy(w)
         H0 = list(w.H0)
         H0[comp] += d
         w2.H0 = tuple(H0)
-        return loss(w2, nsteps, loss_from, film, threads)
-    return derivative(f, h)
+        return f(w2)
+    return derivative(g, h)
 
 
-def grad_eps(w, nsteps, loss_from, cell, rel=2e-3, film=0, threads=None) -> float:
+def grad_eps_of(f, w, cell, rel=2e-3) -> float:
     i, j, k = cell
     e0 = w.materials[int(w.ids[k, j, i])][0]
-    return derivative(lambda d: loss(_with_cell_material(w, cell, eps_r=e0 + d), nsteps, loss_from, film, threads),
-                      rel * e0)
+    return derivative(lambda d: f(_with_cell_material(w, cell, eps_r=e0 + d)), rel * e0)
 
 
-def grad_Ms(w, nsteps, loss_from, cell, rel=2e-3, film=0, threads=None) -> float:
+def grad_Ms_of(f, w, cell, rel=2e-3) -> float:
     i, j, k = cell
     m0 = w.materials[int(w.ids[k, j, i])][3]
-    return derivative(lambda d: loss(_with_cell_material(w, cell, Ms=m0 + d), nsteps, loss_from, film, threads),
-                      rel * m0)
+    return derivative(lambda d: f(_with_cell_material(w, cell, Ms=m0 + d)), rel * m0)

@@ -1149,6 +1149,19 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
     l2 = l2 + (dif(n0m1 - o0[0], T(0), p.dT[1], p.invd[1]) + dif(n1m0 - o1[1], T(0), p.dT[0], p.invd[0]));
     if (SCALE && A.ltape && (fl & 4) && A.seg0[0] + A.m > A.loss_from)
         loss_term(A, t, q, l0, l1, l2);
+    if (SCALE && A.pw && q == A.pw_slot) {
+        // the weighted trace's term of the state at the step's start (time n)
+        const long long n = A.seg0[0] + A.m;
+        if (n >= 1) {
+            const T v = (T)(A.pw_scale * A.pw[n - 1]);
+            if (A.pw_comp == 0)
+                l0 += v;
+            else if (A.pw_comp == 1)
+                l1 += v;
+            else
+                l2 += v;
+        }
+    }
     A.lE[0][q] = l0;
     A.lE[1][q] = l1;
     A.lE[2][q] = l2;
@@ -1374,6 +1387,18 @@ hipError_t launch_adj_estep_fused(const AdjParams<T> &A, hipStream_t s) {
     return hipGetLastError();
 }
 
+// a[q] += v on the stream (one thread)
+template <typename T>
+__global__ void __launch_bounds__(64) k_add_one(T *a, long long q, double v) {
+    if (threadIdx.x == 0) a[q] += (T)v;
+}
+
+template <typename T>
+hipError_t launch_add_one(T *a, long long q, double v, hipStream_t s) {
+    k_add_one<T><<<dim3(1), dim3(64), 0, s>>>(a, q, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s) {
     if (nseg == 0) return hipSuccess;
     k_copy_segs<<<dim3(nblk, nseg), dim3(256), 0, s>>>(segs);
@@ -1388,6 +1413,7 @@ hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t
     template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t); \
     template hipError_t launch_adj_half_fused<T>(const AdjParams<T> &, int, int, const long long *, hipStream_t); \
     template hipError_t launch_adj_estep_fused<T>(const AdjParams<T> &, hipStream_t);                           \
+    template hipError_t launch_add_one<T>(T *, long long, double, hipStream_t);                                 \
     template hipError_t launch_tape_loss<T>(const KParams<T> &, int, int, double *, hipStream_t, const int *);   \
     template hipError_t launch_adj_loss_tape<T>(const AdjParams<T> &, int, double, const double *,              \
                                                 const long long *, int, long long, hipStream_t, const int *);   \

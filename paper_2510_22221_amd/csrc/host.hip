@@ -1453,9 +1453,20 @@ mpx_status snap_tables(mpx_sim *s, Tape &t, const SnapLayout &L, const std::vect
     return MPX_OK;
 }
 
+// the loss of an adjoint run: kind 0, dt times the film-energy sum over the
+// steps after loss_from; kind 1, a weighted sum of one E component's values at
+// one edge, L = sum_i w[i] E(t_{i+1}) (host weights, one per step)
+struct AdjLoss {
+    int kind = 0;
+    int film = 0;
+    long long loss_from = 0;
+    int field = 0, ijk[3] = {0, 0, 0};
+    const double *w = nullptr;
+};
+
 template <typename T>
-mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int film, int K, const int *eps_box,
-                            const int *ms_box, double *loss, double *gH0, double *geps, double *gms) {
+mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, const int *eps_box, const int *ms_box,
+                            double *loss, double *gH0, double *geps, double *gms) {
     hipStream_t st = s->stream;
     const int saved_fused = s->fused;
     s->fused = 0;
@@ -1463,7 +1474,12 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
     const int ncp = (int)((N + K - 1) / K);
     const long long neps = (long long)eps_box[3] * eps_box[4] * eps_box[5];
     const int nblk = s->nblk;
-    const FilmHost &LF = s->films[film];
+    const int film = ls.film;
+    const long long loss_from = ls.loss_from;
+    const bool floss = ls.kind == 0; // the film-energy loss (its tapes and terms)
+    static const FilmHost no_film{};
+    const FilmHost &LF = floss ? s->films[film] : no_film;
+    double *d_w = nullptr;
     std::vector<Snap2> cp(ncp);
     Snap2 fin;
     AdjHost h;
@@ -1568,17 +1584,26 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
         auto tab = [&](int z, int kind) { return tp.d_tab + ((size_t)z * 3 + kind) * ns; };
         const double dt = s->dt;
 
-        // forward: the loss through a temporary film-energy probe
+        // forward: the loss through a temporary probe (film energy, or the
+        // weighted E component)
         {
             ProbeHost ph{};
-            ph.dev.kind = MPX_PROBE_FILM_ENERGY;
-            ph.dev.film = film;
+            if (floss) {
+                ph.dev.kind = MPX_PROBE_FILM_ENERGY;
+                ph.dev.film = film;
+                ph.dev.npart = ((long long)LF.cb[3] * LF.cb[4] * LF.cb[5] + 255) / 256;
+            } else {
+                ph.dev.kind = MPX_PROBE_FIELD;
+                ph.dev.field = ls.field;
+                ph.dev.i = ls.ijk[0];
+                ph.dev.j = ls.ijk[1];
+                ph.dev.k = ls.ijk[2];
+            }
             ph.dev.nval = 1;
             ph.dev.cap = N;
             ph.dev.start = s->step;
-            ph.dev.npart = ((long long)LF.cb[3] * LF.cb[4] * LF.cb[5] + 255) / 256;
             CK(hipMalloc(&ph.dev.data, N * sizeof(double)));
-            CK(hipMalloc(&ph.dev.part, ph.dev.npart * sizeof(double)));
+            if (ph.dev.npart) CK(hipMalloc(&ph.dev.part, ph.dev.npart * sizeof(double)));
             s->probes.push_back(ph);
             probe_added = true;
             drop_graph(s);
@@ -1605,20 +1630,37 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
             drop_graph(s);
             if ((q = upload_probes(s)) != MPX_OK) return q;
         }
-        double Lsum = 0.0;
-        for (long long i = loss_from; i < N; i++) Lsum += tr[i];
-        *loss = dt * Lsum;
         // the seed is scaled by a power of two near 1/L (see the plain
-        // schedule); exact in float64
-        double S = 1.0;
-        if (std::isfinite(*loss) && *loss > 0.0) S = std::ldexp(1.0, -std::ilogb(*loss));
+        // schedule; for a weighted trace, near 1 / sum |w_i E_i|); exact in
+        // float64
+        double S = 1.0, mag = 0.0;
+        if (floss) {
+            double Lsum = 0.0;
+            for (long long i = loss_from; i < N; i++) Lsum += tr[i];
+            *loss = dt * Lsum;
+            mag = *loss;
+        } else {
+            double Lsum = 0.0;
+            for (long long i = 0; i < N; i++) {
+                Lsum += ls.w[i] * tr[i];
+                mag += std::fabs(ls.w[i] * tr[i]);
+            }
+            *loss = Lsum;
+        }
+        if (std::isfinite(mag) && mag > 0.0) S = std::ldexp(1.0, -std::ilogb(mag));
 
         // the loss term of the final state
-        {
+        long long pw_slot = -1;
+        if (floss) {
             AdjParams<T> A;
             adj_params<T>(s, h, A);
             CK(launch_tape_loss<T>(A.p, film, 0, tp.lossp(0), st, LF.cb));
             CK(launch_adj_loss_tape<T>(A, film, dt * S, tp.lossp(0), nullptr, 0, loss_from, st, LF.cb));
+        } else {
+            pw_slot = (long long)ls.ijk[0] + (long long)s->px * ((long long)ls.ijk[1] + (long long)s->n[1] * ls.ijk[2]);
+            CK(hipMalloc(&d_w, N * sizeof(double)));
+            CK(hipMemcpyAsync(d_w, ls.w, N * sizeof(double), hipMemcpyHostToDevice, st));
+            CK(launch_add_one<T>((T *)h.lE[ls.field], pw_slot, S * ls.w[N - 1], st));
         }
 
         // recompute a segment of len steps with the tape, then its adjoint
@@ -1626,7 +1668,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
             KParams<T> p;
             fill_params<T>(s, p, MODE_INPLACE, s->parity);
             p.films = tvar(tp, 0, V_R1);
-            CK(launch_tape_loss<T>(p, film, 0, tp.lossp(0), st, LF.cb));
+            if (floss) CK(launch_tape_loss<T>(p, film, 0, tp.lossp(0), st, LF.cb));
             p.films = tvar(tp, 0, V_BR);
             CK(launch_film<T>(p, nblk, 1, 0, st));
             p.films = tvar(tp, 0, V_BRC);
@@ -1638,7 +1680,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
                 p.films = tvar(tp, m, V_P1);
                 CK(launch_film<T>(p, nblk, 1, 0, st));
                 if (m + 1 < len) {
-                    CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
+                    if (floss) CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
                     p.films = tvar(tp, m, V_P2);
                     CK(launch_film<T>(p, nblk, 2, 0, st));
                     CK(launch_hbulk<T>(p, 2, 1, st));
@@ -1661,10 +1703,14 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
                     A.bb[a] = eps_box[a];
                     A.bs[a] = eps_box[3 + a];
                 }
-                A.ltape = tp.lossp(m);
+                A.ltape = floss ? tp.lossp(m) : nullptr;
                 A.lfilm = film;
                 A.lscale = dt * S;
                 A.loss_from = loss_from;
+                A.pw = d_w;
+                A.pw_slot = pw_slot;
+                A.pw_comp = ls.field;
+                A.pw_scale = S;
                 for (int c = 0; c < 3; c++) {
                     A.mu[c] = (T *)h.mu[c];
                     for (int a = 0; a < 3; a++) {
@@ -1745,6 +1791,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, long long loss_from, int fi
         (void)upload_probes(s);
     }
     if (r != MPX_OK) (void)hipStreamSynchronize(st);
+    (void)hipFree(d_w);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     s->fused = saved_fused;
@@ -2525,15 +2572,52 @@ mpx_status mpx_adjoint(mpx_sim *s, int64_t nsteps, int64_t loss_from, int32_t fi
     if (K == 0) K = std::max(1, (int)std::ceil(std::sqrt((double)nsteps)));
     K = (int)std::min<int64_t>(K, nsteps);
     drop_graph(s);
+    AdjLoss ls;
+    ls.film = film;
+    ls.loss_from = loss_from;
     if (s->adj_schedule == 0)
-        r = s->prec == MPX_F64
-                ? run_adjoint_tape<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
-                : run_adjoint_tape<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
+        r = s->prec == MPX_F64 ? run_adjoint_tape<double>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
+                               : run_adjoint_tape<float>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
     else
         r = s->prec == MPX_F64
                 ? run_adjoint<double>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
                 : run_adjoint<float>(s, nsteps, loss_from, film, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
     return r;
+}
+
+mpx_status mpx_adjoint_probe(mpx_sim *s, int64_t nsteps, int32_t field, const int32_t ijk[3], const double *weights,
+                             int32_t checkpoint_every, const int32_t eps_box[6], const int32_t ms_box[6], double *loss,
+                             double *dL_dH0, double *dL_deps, double *dL_dMs) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "adjoint before set_materials");
+    if (!s->films.empty() && !s->have_u) return fail(s, MPX_E_STATE, "adjoint before init_magnetization");
+    if (s->adj_schedule != 0) return fail(s, MPX_E_UNSUPPORTED, "a weighted-trace loss needs the tape schedule");
+    if (nsteps < 1 || field < 0 || field > 2 || !ijk || !weights || checkpoint_every < 0 || !eps_box || !ms_box ||
+        !loss || !dL_dH0)
+        return fail(s, MPX_E_INVALID, "adjoint arguments");
+    for (int a = 0; a < 3; a++)
+        if (ijk[a] < 0 || ijk[a] >= s->n[a]) return fail(s, MPX_E_INVALID, "probe edge outside the stored sites");
+    for (int a = 0; a < 3; a++)
+        if (eps_box[3 + a] < 0 || ms_box[3 + a] < 0 || eps_box[a] < 0 || ms_box[a] < 0 ||
+            eps_box[a] + eps_box[3 + a] > s->n[a] || ms_box[a] + ms_box[3 + a] > s->n[a])
+            return fail(s, MPX_E_INVALID, "adjoint box outside the grid");
+    if ((long long)eps_box[3] * eps_box[4] * eps_box[5] > 0 && !dL_deps) return fail(s, MPX_E_INVALID, "dL_deps");
+    if ((long long)ms_box[3] * ms_box[4] * ms_box[5] > 0 && !dL_dMs) return fail(s, MPX_E_INVALID, "dL_dMs");
+    for (int64_t i = 0; i < nsteps; i++)
+        if (!std::isfinite(weights[i])) return fail(s, MPX_E_INVALID, "weights must be finite");
+    int K = checkpoint_every;
+    if (K == 0) K = std::max(1, (int)std::ceil(std::sqrt((double)nsteps)));
+    K = (int)std::min<int64_t>(K, nsteps);
+    drop_graph(s);
+    AdjLoss ls;
+    ls.kind = 1;
+    ls.field = field;
+    for (int a = 0; a < 3; a++) ls.ijk[a] = ijk[a];
+    ls.w = weights;
+    return s->prec == MPX_F64
+               ? run_adjoint_tape<double>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
+               : run_adjoint_tape<float>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
 }
 
 mpx_status mpx_set_adjoint_schedule(mpx_sim *s, int32_t schedule) {

@@ -176,6 +176,12 @@ struct AdjParams {
     int lfilm;
     double lscale;
     long long loss_from;
+    // a weighted-trace loss: weight pw[n - 1] of E component pw_comp at slot
+    // pw_slot for the state at time n (pw null: none), scaled by pw_scale
+    const double *pw = nullptr;
+    long long pw_slot = -1;
+    int pw_comp = 0;
+    double pw_scale = 1.0;
     const uint8_t *aflags;
     const long long *seg0;
     int m;
@@ -193,6 +199,7 @@ template <typename T>
 hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double *gca, const double *gcb, double *out,
                               hipStream_t s);
 hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s);
+template <typename T> hipError_t launch_add_one(T *a, long long q, double v, hipStream_t s);
 long long film_tape_size(const int *cb);
 long long box_tape_size(const int *box);
 // fused schedule: the half-step adjoint (scale = 1: first apply the E step's

@@ -35,7 +35,7 @@ EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "m
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
            "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
-           "mpx_last_error", "mpx_adjoint", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
+           "mpx_last_error", "mpx_adjoint", "mpx_adjoint_probe", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
            "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
 
 
@@ -108,6 +108,8 @@ def load(path: str = LIB_PATH):
         "mpx_last_error": (C.c_char_p, [P]),
         "mpx_adjoint": (I32, [P, I64, I64, I32, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(D), C.POINTER(D),
                               P, P]),
+        "mpx_adjoint_probe": (I32, [P, I64, I32, C.POINTER(I32), P, I32, C.POINTER(I32), C.POINTER(I32),
+                                    C.POINTER(D), C.POINTER(D), P, P]),
         "mpx_set_adjoint_schedule": (I32, [P, I32]),
         "mpx_batch_create": (I32, [C.POINTER(P), I32, C.POINTER(P)]),
         "mpx_batch_destroy": (I32, [P]),
@@ -310,6 +312,26 @@ class Sim:
         self._ck(self._L.mpx_adjoint(self._h, int(nsteps), int(loss_from), int(film), int(checkpoint_every), eb, mb,
                                      C.byref(loss), dh0, deps.ctypes.data if deps.size else None,
                                      dms.ctypes.data if dms.size else None), "adjoint")
+        return {"loss": loss.value, "dH0": np.array(dh0[:]), "deps": deps, "dMs": dms}
+
+    def adjoint_probe(self, nsteps, field, ijk, weights, checkpoint_every=0, eps_box=(0, 0, 0, 0, 0, 0),
+                      ms_box=(0, 0, 0, 0, 0, 0)):
+        """Run nsteps forward and return L = sum_i weights[i] E_field(ijk)
+        after step i+1 with its gradients (same keys as adjoint)."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.shape != (int(nsteps),):
+            raise ValueError(f"weights must have shape ({int(nsteps)},), got {w.shape}")
+        eb = (C.c_int32 * 6)(*(int(v) for v in eps_box))
+        mb = (C.c_int32 * 6)(*(int(v) for v in ms_box))
+        at = (C.c_int32 * 3)(*(int(v) for v in ijk))
+        loss = C.c_double()
+        dh0 = (C.c_double * 3)()
+        deps = np.zeros((eps_box[5], eps_box[4], eps_box[3]), dtype=np.float64)
+        dms = np.zeros((ms_box[5], ms_box[4], ms_box[3]), dtype=np.float64)
+        self._ck(self._L.mpx_adjoint_probe(self._h, int(nsteps), int(field), at, w.ctypes.data,
+                                           int(checkpoint_every), eb, mb, C.byref(loss), dh0,
+                                           deps.ctypes.data if deps.size else None,
+                                           dms.ctypes.data if dms.size else None), "adjoint_probe")
         return {"loss": loss.value, "dH0": np.array(dh0[:]), "deps": deps, "dMs": dms}
 
     def set_adjoint_schedule(self, schedule: int):
