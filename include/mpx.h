@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MPX_ABI_VERSION 1u
+#define MPX_ABI_VERSION 2u
 
 typedef struct mpx_sim mpx_sim;
 
@@ -69,7 +69,8 @@ typedef enum {
 typedef enum {
     MPX_PROBE_FIELD = 0,       /* one E or H component at one site, 1 value */
     MPX_PROBE_MEAN_M = 1,      /* film-averaged M, 3 values per sample */
-    MPX_PROBE_FILM_ENERGY = 2  /* EM energy inside the film's cells, 1 value */
+    MPX_PROBE_FILM_ENERGY = 2, /* EM energy inside the film's cells, 1 value */
+    MPX_PROBE_EM_ENERGY = 3    /* discrete EM energy of the whole grid, 1 value */
 } mpx_probe_kind;
 
 /* Grid.  dt <= 0 selects dt = courant / (c sqrt(dx^-2 + dy^-2 + dz^-2))
@@ -111,15 +112,22 @@ typedef struct {
     int64_t n_table;
 } mpx_source_desc;
 
-/* Probe sampled after every full step (at t_{n+1}) into a ring buffer of
- * `capacity` samples.  FIELD: field = MPX_EX..MPX_HZ at natural index
- * (i,j,k) (H probes must lie outside PML slabs).  MEAN_M and FILM_ENERGY
- * use `film` (films are numbered by their lowest linear cell index). */
+/* Probe sampled after every `every`-th full step (at t_{n+1}: the steps
+ * n+1 = every, 2 every, ... counted from the step it was added at; 0 means
+ * 1) into a ring buffer of `capacity` samples.  FIELD: field =
+ * MPX_EX..MPX_HZ at natural index (i,j,k) (H probes must lie outside PML
+ * slabs).  MEAN_M and FILM_ENERGY use `film` (films are numbered by their
+ * lowest linear cell index).  EM_ENERGY records the W_EM of mpx_energy at
+ * that time (the exactly conserved discrete energy of the leap-frog scheme
+ * without sources, losses and films; not defined with PML faces); it reads
+ * every field value of the grid once per sample, so a stride keeps its cost
+ * small. */
 typedef struct {
     int32_t kind;
     int32_t field;
     int32_t i, j, k;
     int32_t film;
+    int32_t every;
     int64_t capacity;
 } mpx_probe_desc;
 
@@ -164,7 +172,11 @@ mpx_status mpx_init_magnetization(mpx_sim *sim, double ux, double uy, double uz)
 /* Add a source (at most 16).  *id receives its index. */
 mpx_status mpx_add_source(mpx_sim *sim, const mpx_source_desc *src, int32_t *id);
 
-/* Add a probe (at most 64).  Samples start with the next step. */
+/* Add a probe (at most 64).  Samples start with the next step.
+ * Errors: MPX_E_INVALID (kind, index, film, capacity < 1, every < 0),
+ * MPX_E_STATE (film or energy probe before mpx_set_materials),
+ * MPX_E_UNSUPPORTED (an H probe inside a PML slab, EM_ENERGY with PML
+ * faces). */
 mpx_status mpx_add_probe(mpx_sim *sim, const mpx_probe_desc *probe, int32_t *id);
 
 /* Advance nsteps full steps: H/M half step, E step, H/M half step each

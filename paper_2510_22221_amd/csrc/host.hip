@@ -94,7 +94,7 @@ struct mpx_sim {
     std::vector<SrcHost> srcs;
     std::vector<ProbeHost> probes;
     ProbeDev *d_probes = nullptr;
-    int probe_maxpart = 0; // most partial-sum blocks of a film-energy probe
+    int probe_maxpart = 0; // most partial-sum blocks of an energy probe
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
     uint8_t *d_pflags_w = nullptr; // the same for the wide tiles (when nx >= kWideMinNx)
@@ -2217,7 +2217,8 @@ mpx_status mpx_add_source(mpx_sim *s, const mpx_source_desc *src, int32_t *id) {
 mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
     mpx_status r = check_live(s);
     if (r != MPX_OK) return r;
-    if (!pd || pd->capacity < 1 || pd->kind < 0 || pd->kind > 2) return fail(s, MPX_E_INVALID, "bad probe");
+    if (!pd || pd->capacity < 1 || pd->kind < 0 || pd->kind > 3 || pd->every < 0)
+        return fail(s, MPX_E_INVALID, "bad probe");
     if ((int)s->probes.size() >= kMaxProbes) return fail(s, MPX_E_INVALID, "too many probes");
     ProbeHost h{};
     h.dev.kind = pd->kind;
@@ -2229,6 +2230,7 @@ mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
     h.dev.nval = pd->kind == MPX_PROBE_MEAN_M ? 3 : 1;
     h.dev.cap = pd->capacity;
     h.dev.start = s->step;
+    h.dev.every = std::max(1, (int)pd->every);
     if (pd->kind == MPX_PROBE_FIELD) {
         if (pd->field < 0 || pd->field > 5) return fail(s, MPX_E_INVALID, "probe field");
         const int idx[3] = {pd->i, pd->j, pd->k};
@@ -2240,6 +2242,9 @@ mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
                 if (a != c && idx[a] < s->n[a] && in_pml_cell(s, a, idx[a]))
                     return fail(s, MPX_E_UNSUPPORTED, "H probe inside a PML slab");
         }
+    } else if (pd->kind == MPX_PROBE_EM_ENERGY) {
+        if (!s->have_mat) return fail(s, MPX_E_STATE, "energy probe before set_materials");
+        if (s->any_pml) return fail(s, MPX_E_UNSUPPORTED, "energy probe with PML faces");
     } else {
         if (!s->have_mat) return fail(s, MPX_E_STATE, "film probe before set_materials");
         if (pd->film < 0 || pd->film >= (int)s->films.size()) return fail(s, MPX_E_INVALID, "probe film");
@@ -2250,6 +2255,9 @@ mpx_status mpx_add_probe(mpx_sim *s, const mpx_probe_desc *pd, int32_t *id) {
         const int *cb = s->films[pd->film].cb;
         h.dev.npart = ((long long)cb[3] * cb[4] * cb[5] + 255) / 256;
         CK(hipMalloc(&h.dev.part, h.dev.npart * sizeof(double)));
+    } else if (pd->kind == MPX_PROBE_EM_ENERGY) {
+        h.dev.npart = ((long long)s->n[0] * s->n[1] * s->n[2] + 255) / 256;
+        CK(hipMalloc(&h.dev.part, 2 * h.dev.npart * sizeof(double)));
     }
     s->probes.push_back(h);
     drop_graph(s);
@@ -2455,7 +2463,7 @@ mpx_status mpx_read_probe(mpx_sim *s, int32_t id, double *dst, int64_t capacity,
     if (r != MPX_OK) return r;
     if (id < 0 || id >= (int)s->probes.size() || !n_written) return fail(s, MPX_E_INVALID, "bad probe id");
     const ProbeDev &P = s->probes[id].dev;
-    const long long samples = s->step - P.start;
+    const long long samples = (s->step - P.start) / std::max(1, P.every);
     const long long have = std::min<long long>(samples, P.cap);
     *n_written = have;
     if (capacity < have || (!dst && have > 0)) return fail(s, MPX_E_RANGE, "probe destination too small");

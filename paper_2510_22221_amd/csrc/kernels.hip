@@ -320,11 +320,63 @@ __device__ double h_integer_time(const KParams<T> &p, int c, const int *idx) {
     return (double)(h - p.hc * (d1 - d2));
 }
 
+// the two energy sums of the slot idx: eps E^2 over its three edges (PEC and
+// lower-wall edges excluded) and H^2 - (hc curl E)^2 over its three faces (H
+// at the integer time times the product of the two neighbouring half-step
+// values), H being the stored field between steps (MID = 0) or, during the
+// merged pass, the integer-time value of h_integer_time rounded to the field
+// type (MID = 1), which is what the bracket half step would store
+template <typename T, int MID>
+__device__ __forceinline__ void energy_site(const KParams<T> &p, const int *idx, double &we, double &wh) {
+    const long long q = p.slot(idx[0], idx[1], idx[2]);
+    for (int c = 0; c < 3; c++) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        if (!((!p.per[c1] && idx[c1] == 0) || (!p.per[c2] && idx[c2] == 0))) {
+            double se = 0.0;
+            int cnt = 0;
+            bool pec = false;
+            for (int u = -1; u <= 0; u++)
+                for (int v = -1; v <= 0; v++) {
+                    int cc[3];
+                    cc[c] = idx[c];
+                    cc[c1] = idx[c1] + u;
+                    cc[c2] = idx[c2] + v;
+                    const int m = cell_id(p.n, p.per, p.px, p.id, cc[0], cc[1], cc[2]);
+                    if (m < 0) continue;
+                    se += p.mat[m].eps_r;
+                    pec = pec || p.mat[m].is_pec;
+                    cnt++;
+                }
+            if (!pec && cnt) {
+                const double eps = p.eps0 * (se / cnt);
+                const double e = (double)p.E[c][q];
+                we += eps * e * e;
+            }
+        }
+        double d1, d2;
+        curl_e64(p, c, idx, d1, d2);
+        const double cu = p.hcd * (d1 - d2);
+        const double h = MID ? (double)(T)h_integer_time(p, c, idx) : (double)p.H[c][q];
+        wh += h * h - cu * cu;
+    }
+}
+
+// whether a probe samples at the step in progress (its counter `step`), and
+// the sample's index
+__device__ __forceinline__ bool probe_due(const ProbeDev &P, long long step, long long &sample) {
+    const long long ev = P.every > 1 ? P.every : 1;
+    const long long ks = step - P.start + 1;
+    if (ks % ev) return false;
+    sample = ks / ev - 1;
+    return true;
+}
+
 template <typename T>
 __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
     __shared__ double red[256];
     const ProbeDev &P = p.probes[pb];
-    const long long step = p.step[0];
+    long long sample;
+    if (!probe_due(P, p.step[0], sample)) return; // uniform over the block
     double v[3] = {0.0, 0.0, 0.0};
     if (P.kind == 0) {
         if (threadIdx.x == 0) {
@@ -355,7 +407,7 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
             v[w] = red[0] / F.ncells;
             __syncthreads();
         }
-    } else {
+    } else if (P.kind == 2) {
         // film EM energy: the partial sums of k_probe_parts, in block order
         double s = 0.0;
         for (long long b = threadIdx.x; b < P.npart; b += blockDim.x) s += P.part[b];
@@ -366,9 +418,25 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
             __syncthreads();
         }
         v[0] = red[0] * p.dV;
+    } else {
+        // the grid's EM energy: the (E, H) partial pairs of k_probe_parts
+        double sum[2];
+        for (int w = 0; w < 2; w++) {
+            double s = 0.0;
+            for (long long b = threadIdx.x; b < P.npart; b += blockDim.x) s += P.part[2 * b + w];
+            red[threadIdx.x] = s;
+            __syncthreads();
+            for (int st = 128; st > 0; st >>= 1) {
+                if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+                __syncthreads();
+            }
+            sum[w] = red[0];
+            __syncthreads();
+        }
+        v[0] = 0.5 * p.dV * (sum[0] + p.mu0 * sum[1]);
     }
     if (threadIdx.x == 0) {
-        const long long slot = (step - P.start) % P.cap;
+        const long long slot = sample % P.cap;
         bool bad = false;
         for (int w = 0; w < P.nval; w++) {
             P.data[slot * P.nval + w] = v[w];
@@ -412,23 +480,46 @@ __device__ double film_cell_energy(const KParams<T> &p, const FilmDev &F, long l
     return 0.5 * p.eps0 * p.mat[m].eps_r * we + 0.5 * p.mu0 * wh;
 }
 
-// film-energy probes: block b of probe pb sums cells [256 b, 256 b + 256) of
-// the film's cell box into P.part[b]
+// energy probes: block b of probe pb sums cells [256 b, 256 b + 256) of the
+// film's cell box into P.part[b] (film energy), or slots [256 b, 256 b + 256)
+// of the grid (x fastest) into P.part[2 b], P.part[2 b + 1] (grid energy)
 template <typename T>
 __device__ __forceinline__ void probe_parts_body(const KParams<T> &p, int pb) {
-    __shared__ double red[256];
+    __shared__ double red[2][256];
     const ProbeDev &P = p.probes[pb];
-    if (P.kind != 2 || (long long)blockIdx.x >= P.npart) return;
-    const FilmDev &F = p.films[P.film];
-    const long long ncell = (long long)F.cb[3] * F.cb[4] * F.cb[5];
+    if ((P.kind != 2 && P.kind != 3) || (long long)blockIdx.x >= P.npart) return;
+    long long sample;
+    if (!probe_due(P, p.step[0], sample)) return;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    red[threadIdx.x] = t < ncell ? film_cell_energy(p, F, t) : 0.0;
+    const int nw = P.kind == 2 ? 1 : 2;
+    if (P.kind == 2) {
+        const FilmDev &F = p.films[P.film];
+        const long long ncell = (long long)F.cb[3] * F.cb[4] * F.cb[5];
+        red[0][threadIdx.x] = t < ncell ? film_cell_energy(p, F, t) : 0.0;
+    } else {
+        double we = 0.0, wh = 0.0;
+        if (t < (long long)p.n[0] * p.n[1] * p.n[2]) {
+            const int idx[3] = {(int)(t % p.n[0]), (int)((t / p.n[0]) % p.n[1]),
+                                (int)(t / ((long long)p.n[0] * p.n[1]))};
+            energy_site<T, 1>(p, idx, we, wh);
+        }
+        red[0][threadIdx.x] = we;
+        red[1][threadIdx.x] = wh;
+    }
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        if (threadIdx.x < st)
+            for (int w = 0; w < nw; w++) red[w][threadIdx.x] += red[w][threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) P.part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        if (P.kind == 2)
+            P.part[blockIdx.x] = red[0][0];
+        else {
+            P.part[2 * blockIdx.x] = red[0][0];
+            P.part[2 * blockIdx.x + 1] = red[1][0];
+        }
+    }
 }
 
 template <typename T>
@@ -468,37 +559,7 @@ __global__ void __launch_bounds__(256) k_energy(KParams<T> p, double *part) {
     double we = 0.0, wh = 0.0;
     if (i < p.n[0] && j < p.n[1]) {
         const int idx[3] = {i, j, k};
-        const long long q = p.slot(i, j, k);
-        for (int c = 0; c < 3; c++) {
-            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-            if (!((!p.per[c1] && idx[c1] == 0) || (!p.per[c2] && idx[c2] == 0))) {
-                double se = 0.0;
-                int cnt = 0;
-                bool pec = false;
-                for (int u = -1; u <= 0; u++)
-                    for (int v = -1; v <= 0; v++) {
-                        int cc[3];
-                        cc[c] = idx[c];
-                        cc[c1] = idx[c1] + u;
-                        cc[c2] = idx[c2] + v;
-                        const int m = cell_id(p.n, p.per, p.px, p.id, cc[0], cc[1], cc[2]);
-                        if (m < 0) continue;
-                        se += p.mat[m].eps_r;
-                        pec = pec || p.mat[m].is_pec;
-                        cnt++;
-                    }
-                if (!pec && cnt) {
-                    const double eps = p.eps0 * (se / cnt);
-                    const double e = (double)p.E[c][q];
-                    we += eps * e * e;
-                }
-            }
-            double d1, d2;
-            curl_e64(p, c, idx, d1, d2);
-            const double cu = p.hcd * (d1 - d2);
-            const double h = (double)p.H[c][q];
-            wh += h * h - cu * cu;
-        }
+        energy_site<T, 0>(p, idx, we, wh);
     }
     red[0][t] = we;
     red[1][t] = wh;

@@ -46,10 +46,11 @@ struct SrcDev {
 };
 
 struct ProbeDev {
-    int kind, field, i, j, k, film, nval, pad;
+    int kind, field, i, j, k, film, nval, every; // every <= 1: each step
     long long cap, start;
     double *data;
-    double *part;    // film-energy probes: one partial sum per 256 cells of the film's cell box
+    double *part;    // film-energy probes: one partial sum per 256 cells of the film's cell box;
+                     // EM-energy probes: two (E and H sums) per 256 cells of the grid
     long long npart;
 };
 

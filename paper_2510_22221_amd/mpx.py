@@ -24,8 +24,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mpx.h")
 F64, F32 = 0, 1
 PEC, PML, PERIODIC = 0, 1, 2
 EX, EY, EZ, HX, HY, HZ, MXF, MYF, MZF, DMXF, DMYF, DMZF = range(12)
-PROBE_FIELD, PROBE_MEAN_M, PROBE_FILM_ENERGY = 0, 1, 2
-ABI_VERSION = 1
+PROBE_FIELD, PROBE_MEAN_M, PROBE_FILM_ENERGY, PROBE_EM_ENERGY = 0, 1, 2, 3
+ABI_VERSION = 2
 
 STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4: "MPX_E_DEVICE",
           5: "MPX_E_UNSUPPORTED", 6: "MPX_E_RANGE", 7: "MPX_E_NONFINITE"}
@@ -66,7 +66,7 @@ class SourceDesc(C.Structure):
 
 class ProbeDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("field", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
-                ("k", C.c_int32), ("film", C.c_int32), ("capacity", C.c_int64)]
+                ("k", C.c_int32), ("film", C.c_int32), ("every", C.c_int32), ("capacity", C.c_int64)]
 
 
 _lib = None
@@ -203,8 +203,9 @@ class Sim:
         self._ck(self._L.mpx_add_source(self._h, C.byref(sd), C.byref(sid)), "add_source")
         return sid.value
 
-    def add_probe(self, kind, field=0, ijk=(0, 0, 0), film=0, cap=1 << 16):
-        pd = ProbeDesc(int(kind), int(field), *(int(v) for v in ijk), int(film), int(cap))
+    def add_probe(self, kind, field=0, ijk=(0, 0, 0), film=0, cap=1 << 16, every=1):
+        """A probe sampled after every `every`-th step (see mpx_probe_desc)."""
+        pd = ProbeDesc(int(kind), int(field), *(int(v) for v in ijk), int(film), int(every), int(cap))
         pid = C.c_int32()
         self._ck(self._L.mpx_add_probe(self._h, C.byref(pd), C.byref(pid)), "add_probe")
         return pid.value
@@ -408,7 +409,8 @@ def from_workload(w, precision=F64, device=0, stream=None, graph_steps=None, fus
     for src in w.sources:
         s.add_source(src.comp, src.box, src.table)
     for p in w.probes:
-        kind = {"field": PROBE_FIELD, "mean_m": PROBE_MEAN_M, "film_energy": PROBE_FILM_ENERGY}[p.kind]
+        kind = {"field": PROBE_FIELD, "mean_m": PROBE_MEAN_M, "film_energy": PROBE_FILM_ENERGY,
+                "em_energy": PROBE_EM_ENERGY}[p.kind]
         s.add_probe(kind, p.field, p.ijk, p.film, cap=max(1, p.cap or w.nsteps))
     if graph_steps is not None:
         s.set_graph_steps(graph_steps)

@@ -44,7 +44,7 @@ class Source:
 
 @dataclass
 class Probe:
-    kind: str                      # "field" | "mean_m" | "film_energy"
+    kind: str                      # "field" | "mean_m" | "film_energy" | "em_energy"
     field: int = 0                 # 0..5 = Ex..Hz for kind "field"
     ijk: Tuple[int, int, int] = (0, 0, 0)
     film: int = 0

@@ -37,7 +37,8 @@ def test_struct_layouts():
     assert ctypes.sizeof(mpx.GridDesc) == 3 * 4 + 4 + 5 * 8 + 12 * 4 + 2 * 8
     assert ctypes.sizeof(mpx.Material) == 8 * 2 + 8 + 8 * 3
     assert ctypes.sizeof(mpx.SourceDesc) == 7 * 4 + 4 + 8 + 8
-    assert ctypes.sizeof(mpx.ProbeDesc) == 6 * 4 + 8
+    assert ctypes.sizeof(mpx.ProbeDesc) == 7 * 4 + 4 + 8
+    assert mpx.ProbeDesc.capacity.offset == 32
 
 
 def test_create_rejects_bad_grid_without_touching_the_device():
