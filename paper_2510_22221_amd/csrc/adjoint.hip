@@ -904,7 +904,7 @@ __device__ __forceinline__ bool edge_coef(const KParams<T> &p, const int *idx, l
         if (a != C && !p.per[a] && idx[a] == 0) return false;
     const uint8_t cl = p.cls[q];
     if (cl != kMixed) {
-        const CoefDev<T> cd = p.coef[cl];
+        const CoefDev<T> cd = p.coef[kCoefPerClass * cl + C];
         ca = cd.ca;
         cb = cd.cb;
         return !cd.pec;

@@ -5,9 +5,6 @@
 
 namespace mpx {
 
-// class byte of a slot whose eight cells do not share one material id
-constexpr int kMixed = 255;
-
 // index along an axis of extent n: wrapped once on a periodic axis; -1 when
 // outside the domain (or still outside after one wrap)
 __device__ __forceinline__ int fold(int i, int n, int per) {

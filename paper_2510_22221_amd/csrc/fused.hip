@@ -255,9 +255,9 @@ __device__ __forceinline__ void fused_body(const KParams<T> &p, int t, int kchun
         if (p.nfilm && (p.per[0] || p.per[1] || p.per[2])) tfilm = true;
     }
 
-    // coefficient table of single-id edges
+    // coefficient table of single-id edges (a material's three entries are equal)
     for (int q = tid; q < 256; q += FNT) {
-        const CoefDev<T> cf = p.coef[q];
+        const CoefDev<T> cf = p.coef[kCoefPerClass * q];
         L.ca[q] = cf.ca;
         L.cb[q] = cf.cb;
         L.pec[q] = (uint8_t)cf.pec;

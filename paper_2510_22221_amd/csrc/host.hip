@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <array>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -98,7 +100,7 @@ struct mpx_sim {
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
     uint8_t *d_pflags_w = nullptr; // the same for the wide tiles (when nx >= kWideMinNx)
-    int4 *d_mixed = nullptr;     // slots whose eight cells do not share one id
+    int4 *d_mixed = nullptr;     // slots of the mixed class (the general path)
     int nmixed = 0;
     long long *d_step = nullptr;
     int *d_flag = nullptr;
@@ -1874,7 +1876,7 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
             CK(hipMemset(s->E2[c], 0, s->nslot * s->esz));
             CK(hipMemset(s->H2[c], 0, s->nslot * s->esz));
         }
-        CK(hipMalloc(&s->d_coef, 256 * (prec == MPX_F64 ? sizeof(CoefDev<double>) : sizeof(CoefDev<float>))));
+        CK(hipMalloc(&s->d_coef, kCoefEntries * (prec == MPX_F64 ? sizeof(CoefDev<double>) : sizeof(CoefDev<float>))));
         CK(hipMalloc(&s->d_id, s->nslot));
         CK(hipMemset(s->d_id, 0, s->nslot));
         CK(hipMalloc(&s->d_cls, s->nslot));
@@ -2006,34 +2008,33 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         md[q].is_pec = mats[q].is_pec ? 1 : 0;
     }
     CK(hipMemcpy(s->d_mat, md.data(), 256 * sizeof(MatDev), hipMemcpyHostToDevice));
-    // coefficients of edges whose four cells share one id: the same sequence
-    // of operations as for any edge (sum of four in order, mean, ca, cb)
-    {
-        std::vector<CoefDev<double>> cd(256);
-        std::vector<CoefDev<float>> cf(256);
-        memset(cd.data(), 0, cd.size() * sizeof(cd[0]));
-        memset(cf.data(), 0, cf.size() * sizeof(cf[0]));
-        for (int q = 0; q < n; q++) {
-            double se = 0.0, ss = 0.0;
-            for (int r4 = 0; r4 < 4; r4++) {
-                se += mats[q].eps_r;
-                ss += mats[q].sigma;
-            }
-            const double eps = EPS0 * (se / 4);
-            const double sig = ss / 4;
-            const double den = sig / 2.0 + eps / s->dt;
-            cd[q].ca = -(sig / 2.0 - eps / s->dt) / den;
-            cd[q].cb = 1.0 / den;
-            cd[q].pec = mats[q].is_pec ? 1 : 0;
-            if (cd[q].pec) cd[q].ca = cd[q].cb = 0.0; // a PEC edge stays zero
-            cf[q].ca = (float)cd[q].ca;
-            cf[q].cb = (float)cd[q].cb;
-            cf[q].pec = cd[q].pec;
+    // edge coefficients from the four cells around an edge, in the device's
+    // order and operations (sum of four in order, mean, ca, cb); a PEC edge
+    // stays zero
+    auto coef_of = [&](const int *m4) {
+        CoefDev<double> c{};
+        double se = 0.0, ss = 0.0;
+        bool pec = false;
+        for (int r4 = 0; r4 < 4; r4++) {
+            se += mats[m4[r4]].eps_r;
+            ss += mats[m4[r4]].sigma;
+            pec = pec || mats[m4[r4]].is_pec;
         }
-        if (s->prec == MPX_F64)
-            CK(hipMemcpy(s->d_coef, cd.data(), 256 * sizeof(cd[0]), hipMemcpyHostToDevice));
-        else
-            CK(hipMemcpy(s->d_coef, cf.data(), 256 * sizeof(cf[0]), hipMemcpyHostToDevice));
+        const double eps = EPS0 * (se / 4);
+        const double sig = ss / 4;
+        const double den = sig / 2.0 + eps / s->dt;
+        c.ca = -(sig / 2.0 - eps / s->dt) / den;
+        c.cb = 1.0 / den;
+        c.pec = pec ? 1 : 0;
+        if (pec) c.ca = c.cb = 0.0;
+        return c;
+    };
+    std::vector<CoefDev<double>> cd(kCoefEntries);
+    memset(cd.data(), 0, cd.size() * sizeof(cd[0]));
+    for (int q = 0; q < n; q++) {
+        const int m4[4] = {q, q, q, q};
+        const CoefDev<double> c = coef_of(m4);
+        for (int C = 0; C < kCoefPerClass; C++) cd[kCoefPerClass * q + C] = c;
     }
     std::vector<uint8_t> slots(s->nslot, 0);
     for (int k = 0; k < s->n[2]; k++)
@@ -2042,6 +2043,98 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
                    s->n[0]);
     CK(hipMemcpy(s->d_id, slots.data(), s->nslot, hipMemcpyHostToDevice));
     CK(launch_classify(s->d_id, s->d_cls, s->n, s->per, s->px, s->stream));
+    {
+        // compound classes: the distinct triples of edge coefficients among
+        // the slots the classifier left mixed, most frequent first (ties in
+        // key order), get the class ids from n up to 254; their slots then
+        // take the table path, the others keep the general one
+        std::vector<uint8_t> hc(s->nslot);
+        CK(hipMemcpyAsync(hc.data(), s->d_cls, s->nslot, hipMemcpyDeviceToHost, s->stream));
+        CK(hipStreamSynchronize(s->stream));
+        using Key = std::array<unsigned long long, 9>;
+        struct Entry {
+            long long count = 0;
+            int cls = kMixed;
+            CoefDev<double> e[3];
+        };
+        std::map<Key, Entry> seen;
+        std::vector<std::pair<long long, Entry *>> slot_key; // mixed slot -> its triple (map nodes are stable)
+        for (int k = 0; k < s->n[2]; k++)
+            for (int j = 0; j < s->n[1]; j++)
+                for (int i = 0; i < s->n[0]; i++) {
+                    const long long q = (long long)i + (long long)s->px * ((long long)j + (long long)s->n[1] * k);
+                    if (hc[q] != kMixed) continue;
+                    const int idx[3] = {i, j, k};
+                    CoefDev<double> e[3];
+                    std::array<unsigned long long, 9> key{};
+                    for (int C = 0; C < 3; C++) {
+                        bool wall = false;
+                        for (int a = 0; a < 3; a++)
+                            if (a != C && !s->per[a] && idx[a] == 0) wall = true;
+                        if (wall) {
+                            // tangential to a lower wall: never updated
+                            e[C] = CoefDev<double>{};
+                            e[C].pec = 1;
+                        } else {
+                            const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+                            int m4[4];
+                            for (int u = 0; u < 2; u++)
+                                for (int v = 0; v < 2; v++) {
+                                    int cc[3] = {i, j, k};
+                                    cc[C1] -= 1 - u;
+                                    cc[C2] -= 1 - v;
+                                    for (int a = 0; a < 3; a++)
+                                        if (cc[a] < 0) cc[a] += s->n[a]; // periodic (walls excluded above)
+                                    m4[2 * u + v] = ids[(size_t)cc[0] + (size_t)s->n[0] * (cc[1] + (size_t)s->n[1] * cc[2])];
+                                }
+                            e[C] = coef_of(m4);
+                        }
+                        memcpy(&key[3 * C], &e[C].ca, 8);
+                        memcpy(&key[3 * C + 1], &e[C].cb, 8);
+                        key[3 * C + 2] = (unsigned long long)e[C].pec;
+                    }
+                    auto it = seen.find(key);
+                    if (it == seen.end()) {
+                        it = seen.emplace(key, Entry{}).first;
+                        for (int C = 0; C < 3; C++) it->second.e[C] = e[C];
+                    }
+                    it->second.count++;
+                    slot_key.emplace_back(q, &it->second);
+                }
+        std::vector<std::pair<long long, Entry *>> order;
+        for (auto &kv : seen) order.emplace_back(kv.second.count, &kv.second);
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<long long, Entry *> &a, const std::pair<long long, Entry *> &b) {
+                             return a.first > b.first;
+                         });
+        int next = n;
+        for (auto &o : order) {
+            if (next >= kMixed) break; // table full: the rest keep the mixed path
+            o.second->cls = next;
+            for (int C = 0; C < 3; C++) cd[kCoefPerClass * next + C] = o.second->e[C];
+            next++;
+        }
+        bool changed = false;
+        for (auto &sk : slot_key) {
+            const int cl = sk.second->cls;
+            if (cl == kMixed) continue;
+            hc[sk.first] = (uint8_t)cl;
+            changed = true;
+        }
+        if (changed) CK(hipMemcpy(s->d_cls, hc.data(), s->nslot, hipMemcpyHostToDevice));
+        if (s->prec == MPX_F64) {
+            CK(hipMemcpy(s->d_coef, cd.data(), kCoefEntries * sizeof(cd[0]), hipMemcpyHostToDevice));
+        } else {
+            std::vector<CoefDev<float>> cf(kCoefEntries);
+            memset(cf.data(), 0, cf.size() * sizeof(cf[0]));
+            for (int q = 0; q < kCoefEntries; q++) {
+                cf[q].ca = (float)cd[q].ca;
+                cf[q].cb = (float)cd[q].cb;
+                cf[q].pec = cd[q].pec;
+            }
+            CK(hipMemcpy(s->d_coef, cf.data(), kCoefEntries * sizeof(cf[0]), hipMemcpyHostToDevice));
+        }
+    }
     {
         // the list of mixed slots (count, then fill)
         int *cnt = nullptr;

@@ -54,14 +54,21 @@ struct ProbeDev {
     long long npart;
 };
 
-// Coefficients of an edge whose four cells share one material id, computed
-// on the host with the same operation sequence the device uses for mixed
-// edges (so the fast path is bitwise identical to the general one).
+// Coefficients of an edge, computed on the host with the same operation
+// sequence the device uses for mixed edges (so the table path is bitwise
+// identical to the general one).  The table holds kCoefPerClass entries per
+// slot class, one per edge component: a class below the number of materials
+// is that material (its three entries equal); a class from there up to 254 is
+// a compound class, one distinct triple of edge coefficients of slots whose
+// eight cells do not share one id; 255 (kMixed) has no entries.
 template <typename T>
 struct CoefDev {
     T ca, cb;
     int pec, pad;
 };
+constexpr int kMixed = 255; // class byte of a slot whose edges take the general path
+constexpr int kCoefPerClass = 3;
+constexpr int kCoefEntries = kCoefPerClass * 256;
 
 template <typename T>
 struct KParams {
@@ -89,7 +96,7 @@ struct KParams {
     // two tiles), with their flags in pflags_w; batches keep the 64 x 4 tiles
     const uint8_t *pflags_w;
     int wide;
-    const int4 *mixed;     // slots whose eight cells do not share one id (i, j, k, -)
+    const int4 *mixed;     // slots of the mixed class, kMixed (i, j, k, -)
     int nmixed;
     const MatDev *mat;
     int nlo[3], nhi[3];

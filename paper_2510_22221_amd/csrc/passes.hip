@@ -40,9 +40,11 @@ constexpr int kOOB = 0x7ffffff0; // a byte offset past every resource: the load 
 // (i, j, k); reads H at the slot and at its -x, -y, -z neighbours.  One path
 // for every tile: a -1 neighbour wraps on a periodic axis and is, at a wall,
 // any in-range value (only edges held at zero would read it); lanes past the
-// domain (partial tiles) compute nothing that is stored.  Slots whose eight
-// cells do not share one id are skipped: the mixed-slot kernel updates them
-// afterwards from the same old values.
+// domain (partial tiles) compute nothing that is stored.  Each edge takes its
+// coefficients from the table entry of its slot's class and component (a
+// material, or a compound class of a slot whose eight cells differ); slots of
+// the mixed class (255: the table had no room) are skipped, and the
+// mixed-slot kernel updates them afterwards from the same old values.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tsrc) {

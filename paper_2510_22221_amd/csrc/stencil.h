@@ -13,14 +13,14 @@
 
 namespace mpx {
 
-// coefficient table of edges whose four cells share one id, staged in LDS;
-// PEC ids hold ca = cb = 0 (the edge stays zero)
+// coefficient table by slot class and edge component, staged in LDS; PEC
+// edges hold ca = cb = 0 (the edge stays zero)
 template <typename T>
 struct CoefLds {
-    T ca[256], cb[256];
-    __device__ __forceinline__ void get(int cls, T &a, T &b) const {
-        a = ca[cls];
-        b = cb[cls];
+    T ca[kCoefEntries], cb[kCoefEntries];
+    __device__ __forceinline__ void get(int cls, int C, T &a, T &b) const {
+        a = ca[kCoefPerClass * cls + C];
+        b = cb[kCoefPerClass * cls + C];
     }
 };
 
@@ -29,15 +29,15 @@ struct CoefLds {
 template <typename T>
 struct CoefMem {
     const CoefDev<T> *c;
-    __device__ __forceinline__ void get(int cls, T &a, T &b) const {
-        a = c[cls].ca;
-        b = c[cls].cb;
+    __device__ __forceinline__ void get(int cls, int C, T &a, T &b) const {
+        a = c[kCoefPerClass * cls + C].ca;
+        b = c[kCoefPerClass * cls + C].cb;
     }
 };
 
 template <typename T>
 __device__ __forceinline__ void stage_coef(const KParams<T> &p, CoefLds<T> &L, int tid, int nthreads) {
-    for (int q = tid; q < 256; q += nthreads) {
+    for (int q = tid; q < kCoefEntries; q += nthreads) {
         const CoefDev<T> cf = p.coef[q];
         L.ca[q] = cf.pec ? T(0) : cf.ca;
         L.cb[q] = cf.pec ? T(0) : cf.cb;
@@ -184,13 +184,13 @@ __device__ __forceinline__ bool e_site(const KParams<T> &p, int gi, int gj, int 
 // the class byte of its slot, the two raw curl differences d1 (along C1) and
 // d2 (along C2) and its loaded CPML state (advanced here; r.upd tells the
 // caller to store it: a PEC edge, cb = 0, stays zero and keeps its psi)
-// (MIXED = false: the caller guarantees a uniform class, no mixed path)
+// (MIXED = false: the caller guarantees a table class, no mixed path)
 template <typename T, int C, class TAB, bool MIXED = true>
 __device__ __forceinline__ T e_apply(const KParams<T> &p, const TAB &L, const int *idx, int cls, T eold, T d1, T d2,
                                      Psi2<T> &r, bool tsrc, long long step) {
     T ca, cb;
     if (!MIXED || cls != kMixed) {
-        L.get(cls, ca, cb);
+        L.get(cls, C, ca, cb);
     } else {
         const CaCb<T> m = mixed_coef<T, C>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.px, p.per[0], p.per[1], p.per[2],
                                            p.eps0, p.dt, p.inv_dt, idx[0], idx[1], idx[2]);

@@ -222,8 +222,31 @@ def test_nonfinite_watchdog():
 
 
 # ------------------------------------------------------------------ schedules
+def many_materials_case(nsteps):
+    """150 lossy dielectrics and one PEC id on random cells: far more distinct
+    triples of edge coefficients than free class ids, so the first triples
+    met get compound classes (the table path) and the remaining mixed slots
+    keep the general path."""
+    w = W.random_case(8, nx=40, ny=17, nz=13, bc=(W.PML,) * 6, npml=(3,) * 6, film=False, nsteps=nsteps)
+    rng = np.random.default_rng(8)
+    mats = [(float(rng.uniform(1.0, 12.0)), float(rng.uniform(0.0, 5e3)), 0, 0.0, 0.0, 0.0) for _ in range(150)]
+    mats[7] = W.PEC_METAL
+    w.materials = mats
+    w.ids = rng.integers(0, 150, size=(w.nz, w.ny, w.nx)).astype(np.uint8)
+    return w
+
+
+@pytest.mark.parametrize("prec,tol", [(mpx.F64, F64_TOL), (mpx.F32, F32_TOL)])
+def test_many_materials_matches_oracle(prec, tol):
+    w = many_materials_case(40)
+    say(f"150 materials, compound and mixed slots, prec={prec}")
+    g, o = run_pair(w, 40, prec, threads=THREADS, chunks=2)
+    check(g, o, w, tol)
+
+
 SCHED_CASES = [
     ("c1", lambda: W.c1(120), 120),
+    ("many-materials", lambda: many_materials_case(30), 30),
     ("random-pml", lambda: W.random_case(3, nx=70, ny=19, nz=23, bc=(W.PML,) * 6, npml=(3,) * 6, film=False,
                                          nsteps=40), 40),
     ("random-periodic", lambda: W.random_case(4, nx=13, ny=11, nz=9,
