@@ -29,6 +29,7 @@ struct FilmHost {
     long long ncells;
     long long lowest;
     double *M = nullptr, *M1 = nullptr, *H1 = nullptr, *prm = nullptr, *Bn = nullptr, *Bs = nullptr;
+    double *Bn2 = nullptr, *Bs2 = nullptr;
     int blk0[3], nblk[3];
     int e0[3], en[3];
     long long nse;
@@ -281,6 +282,8 @@ void free_films(mpx_sim *s) {
         (void)hipFree(f.prm);
         (void)hipFree(f.Bn);
         (void)hipFree(f.Bs);
+        (void)hipFree(f.Bn2);
+        (void)hipFree(f.Bs2);
     }
     s->films.clear();
     (void)hipFree(s->d_films);
@@ -1391,19 +1394,23 @@ mpx_status tape_alloc(mpx_sim *s, Tape &t, int K, const int *film_cb, const int 
             auto B1n = [&](int mm) { return t.B1n[(size_t)f * K + std::min(mm, K - 1)]; };
             const size_t i0 = (size_t)m * NV * nf + f;
             FilmDev d;
-            // HALF2 of step m: reads M^{n+1/2}, writes M^{n+1} and its prepass
+            // HALF2 of step m: reads M^{n+1/2}, writes M^{n+1}, its prepass and
+            // (unless it ends the segment) the prepass of HALF1 of step m + 1
             d = base[f];
             d.M = Mh(m);
             d.M1 = Mf(m + 1);
             d.Bs = t.B2s[(size_t)f * K + m];
             d.Bn = t.B2n[(size_t)f * K + m];
+            d.Bs2 = m + 1 < K ? B1s(m + 1) : nullptr;
+            d.Bn2 = m + 1 < K ? B1n(m + 1) : nullptr;
             var[i0 + V_P1 * nf] = d;
-            // HALF1 of step m + 1 (merged pair): reads M^{n+1}, writes M^{n+3/2}
+            // HALF1 of step m + 1 (merged pair): reads M^{n+1} and its prepass,
+            // writes M^{n+3/2}
             d = base[f];
             d.M = Mh(m + 1);
             d.M1 = Mf(m + 1);
-            d.Bs = B1s(m + 1);
-            d.Bn = B1n(m + 1);
+            d.Bs = d.Bs2 = B1s(m + 1);
+            d.Bn = d.Bn2 = B1n(m + 1);
             var[i0 + V_P2 * nf] = d;
             // commit after the segment's last HALF2 (copies M^{n+1} onto itself)
             d = base[f];
@@ -1414,6 +1421,7 @@ mpx_status tape_alloc(mpx_sim *s, Tape &t, int K, const int *film_cb, const int 
             d.M = Mf(m);
             d.Bs = B1s(m);
             d.Bn = B1n(m);
+            d.Bs2 = d.Bn2 = nullptr;
             var[i0 + V_R1 * nf] = d;
             // the bracket (HALF1 of the segment's first step) and its commit
             d = base[f];
@@ -1421,6 +1429,7 @@ mpx_status tape_alloc(mpx_sim *s, Tape &t, int K, const int *film_cb, const int 
             d.M1 = Mh(0);
             d.Bs = B1s(0);
             d.Bn = B1n(0);
+            d.Bs2 = d.Bn2 = nullptr;
             var[i0 + V_BR * nf] = d;
             d = base[f];
             d.M = d.M1 = Mh(0);
@@ -2197,6 +2206,10 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         CK(hipMalloc(&f.Bs, 3 * f.nse * sizeof(double)));
         CK(hipMemset(f.Bn, 0, 3 * f.nse * sizeof(double)));
         CK(hipMemset(f.Bs, 0, 3 * f.nse * sizeof(double)));
+        CK(hipMalloc(&f.Bn2, 3 * f.nse * sizeof(double)));
+        CK(hipMalloc(&f.Bs2, 3 * f.nse * sizeof(double)));
+        CK(hipMemset(f.Bn2, 0, 3 * f.nse * sizeof(double)));
+        CK(hipMemset(f.Bs2, 0, 3 * f.nse * sizeof(double)));
         for (int c = 0; c < 3; c++)
             for (long long t = 0; t < (f.nse + 255) / 256; t++) bte.push_back(make_int4(fi, c, (int)(t * 256), 0));
         FilmDev d{};
@@ -2220,6 +2233,8 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         d.nse = f.nse;
         d.Bn = f.Bn;
         d.Bs = f.Bs;
+        d.Bn2 = f.Bn2;
+        d.Bs2 = f.Bs2;
         fd.push_back(d);
     }
     s->nblk = (int)bt.size();

@@ -111,10 +111,14 @@ __device__ __forceinline__ void curl_e64(const KParams<T> &p, int c, const int *
     d2 = (e1b - e1a) / p.d[c2];
 }
 
-// B^ and B^* at the face of family cq at idx (folded), for film f
+// B^ and B^* at the face of family cq at idx (folded), for film f; for a
+// non-magnetic face in phase 1 also those of phase 2 (bn2, bs2: the phase-2
+// expressions, from the same H and E); mag tells whether the face is magnetic
 template <typename T>
 __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int cq, const int *idx, double &bn,
-                                     double &bs) {
+                                     double &bs, double &bn2, double &bs2, bool &mag) {
+    bn2 = bs2 = 0.0;
+    mag = false;
     if (idx[0] < 0 || idx[1] < 0 || idx[2] < 0) { // outside the domain (cannot happen for the
         bn = bs = 0.0;                             // film placements set_materials accepts)
         return;
@@ -124,7 +128,7 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     const FilmDev &F = p.films[f];
     bool inside;
     const long long l = film_local<T>(F, idx, inside);
-    const bool mag = inside && F.prm[(cq * 3) * F.ns + l] > 0.0;
+    mag = inside && F.prm[(cq * 3) * F.ns + l] > 0.0;
     double b;
     if (mag) {
         if (phase == 1)
@@ -132,9 +136,15 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
         else
             b = F.H1[cq * F.ns + l] + F.M1[(cq * 3 + cq) * F.ns + l];
     } else {
-        double h = (double)p.H[cq][p.slot(idx[0], idx[1], idx[2])];
+        const double h0 = (double)p.H[cq][p.slot(idx[0], idx[1], idx[2])];
+        double h = h0;
         if (phase == 2) h = h - p.hcd * (d1 - d2);
         b = h + 0.0;
+        if (phase == 1) {
+            const double h2 = h0 - p.hcd * (d1 - d2);
+            bn2 = h2 + 0.0;
+            bs2 = bn2 - p.hcd * (d1 - d2);
+        }
     }
     bn = b;
     bs = b - p.hcd * (d1 - d2);
@@ -160,10 +170,15 @@ __device__ __forceinline__ void bhat_body(const KParams<T> &p, int phase, int bl
     if (l >= F.nse) return;
     const int idx[3] = {F.e0[0] + (int)(l % F.en[0]), F.e0[1] + (int)((l / F.en[0]) % F.en[1]),
                         F.e0[2] + (int)(l / ((long long)F.en[0] * F.en[1]))};
-    double bn, bs;
-    bhat(p, phase, f, c, idx, bn, bs);
+    double bn, bs, bn2, bs2;
+    bool mag;
+    bhat(p, phase, f, c, idx, bn, bs, bn2, bs2, mag);
     F.Bn[c * F.nse + l] = bn;
     F.Bs[c * F.nse + l] = bs;
+    if (phase == 1 && !mag && F.Bn2) { // magnetic faces: the film kernel writes them
+        F.Bn2[c * F.nse + l] = bn2;
+        F.Bs2[c * F.nse + l] = bs2;
+    }
 }
 
 template <typename T>
@@ -204,7 +219,8 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
                 return (long long)r0 + (long long)F.en[0] * ((long long)r1 + (long long)F.en[1] * r2);
             };
             const long long le = ext(idx);
-            const double bn = le >= 0 ? F.Bn[c * F.nse + le] : 0.0, bs = le >= 0 ? F.Bs[c * F.nse + le] : 0.0;
+            const double *Bn = phase == 1 ? F.Bn : F.Bn2, *Bs = phase == 1 ? F.Bs : F.Bs2;
+            const double bn = le >= 0 ? Bn[c * F.nse + le] : 0.0, bs = le >= 0 ? Bs[c * F.nse + le] : 0.0;
             double P[3], Q[3], M[3];
             P[c] = bs;
             Q[c] = bn;
@@ -220,8 +236,8 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
                         q[cp] += v;
                         for (int a = 0; a < 3; a++) q[a] = fold(q[a], p.n[a], p.per[a]);
                         const long long lq = ext(q);
-                        vn[u][v] = lq >= 0 ? F.Bn[cp * F.nse + lq] : 0.0;
-                        vs[u][v] = lq >= 0 ? F.Bs[cp * F.nse + lq] : 0.0;
+                        vn[u][v] = lq >= 0 ? Bn[cp * F.nse + lq] : 0.0;
+                        vs[u][v] = lq >= 0 ? Bs[cp * F.nse + lq] : 0.0;
                     }
                 Q[cp] = ((vn[0][0] + vn[1][0]) + (vn[0][1] + vn[1][1])) * 0.25;
                 P[cp] = ((vs[0][0] + vs[1][0]) + (vs[0][1] + vs[1][1])) * 0.25;
@@ -250,6 +266,15 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
             if (phase == 1) {
                 for (int w = 0; w < 3; w++) F.M1[(c * 3 + w) * F.ns + l] = Mn[w];
                 F.H1[c * F.ns + l] = hnew;
+                if (F.Bn2 && le >= 0) {
+                    // the phase-2 prepass of this face: B^ = H1 + M1_c, B^* =
+                    // B^ - dt/(2 mu0) curl E with the same E
+                    double d1, d2;
+                    curl_e64(p, c, idx, d1, d2);
+                    const double b2 = hnew + Mn[c];
+                    F.Bn2[c * F.nse + le] = b2;
+                    F.Bs2[c * F.nse + le] = b2 - p.hcd * (d1 - d2);
+                }
             } else {
                 for (int w = 0; w < 3; w++) F.M[(c * 3 + w) * F.ns + l] = Mn[w];
                 p.Hw[c][p.slot(idx[0], idx[1], idx[2])] = (T)hnew;
@@ -653,7 +678,8 @@ hipError_t launch_bhat(const KParams<T> &p, int phase, hipStream_t s) {
 template <typename T>
 hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s) {
     if (nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bhat<T>, dim3(p.nblk_ext), dim3(256), 0, s, p, phase);
+    // phase 2 follows a phase 1 whose kernels wrote its prepass
+    if (phase == 1) hipLaunchKernelGGL(k_bhat<T>, dim3(p.nblk_ext), dim3(256), 0, s, p, phase);
     hipLaunchKernelGGL(k_film<T>, dim3(nblk), dim3(256), 0, s, p, phase, inc);
     return hipGetLastError();
 }
@@ -705,7 +731,7 @@ template <typename T>
 hipError_t launch_film_batch(const KParams<T> *plist, const int2 *work_ext, int n_ext, const int2 *work, int n,
                              int phase, int inc, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bhat_batch<T>, dim3(n_ext), dim3(256), 0, s, plist, work_ext, phase);
+    if (phase == 1) hipLaunchKernelGGL(k_bhat_batch<T>, dim3(n_ext), dim3(256), 0, s, plist, work_ext, phase);
     hipLaunchKernelGGL(k_film_batch<T>, dim3(n), dim3(256), 0, s, plist, work, phase, inc);
     return hipGetLastError();
 }

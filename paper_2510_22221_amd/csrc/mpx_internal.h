@@ -36,6 +36,11 @@ struct FilmDev {
     int e0[3], en[3];
     long long nse;
     double *Bn, *Bs;
+    // the same for the next half step of a merged pair, written by the
+    // kernels of the first (both half steps use one E, so the first knows
+    // every input of the second's prepass): the second reads these and runs
+    // no prepass of its own (null: not written)
+    double *Bn2, *Bs2;
 };
 
 struct SrcDev {
