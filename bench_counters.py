@@ -80,9 +80,12 @@ def pick(counters, key):
 
 
 # kernels whose traffic is recorded: the bench's roofline key and a
-# predicate on the rocprofv3 kernel name
+# predicate on the rocprofv3 kernel name (the merged H/M pass runs as
+# k_hbulk_film, which also holds the film's second half step, on 256 x 1
+# tiles, else as k_hbulk<T, 2, ...>)
 KERNELS = {"e_pass": lambda k: "k_epass<" in k and "batch" not in k,
-           "h_pass": lambda k: re.search(r"k_hbulk<\w+, 2[,>]", k) is not None and "batch" not in k,
+           "h_pass": lambda k: (re.search(r"k_hbulk<\w+, 2[,>]", k) is not None or "k_hbulk_film<" in k)
+           and "batch" not in k,
            "fused": lambda k: ("k_sweep<" in k or "k_fused<" in k) and "batch" not in k}
 
 

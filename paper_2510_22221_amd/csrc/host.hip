@@ -488,8 +488,9 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
         par ^= 1;
         return MPX_OK;
     }
-    // two-pass schedule, in place: E pass, film half steps and probes, then
-    // the bulk H pass (the film kernels read H before the bulk pass moves it)
+    // two-pass schedule, in place: E pass, the film's first half step (its
+    // prepass reads H before the bulk pass moves it) and probes, then the
+    // film's second half step with the bulk H pass
     KParams<T> p;
     fill_params<T>(s, p, MODE_INPLACE, par);
     if ((r = rec(0, 0)) != MPX_OK) return r;
@@ -498,10 +499,9 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
     if ((r = rec(2, 0)) != MPX_OK) return r;
     CK(launch_film<T>(p, nblk, 1, 0, st));
     CK(launch_probes<T>(p, np, s->probe_maxpart, st));
-    CK(launch_film<T>(p, nblk, 2, 0, st));
     if ((r = rec(2, 1)) != MPX_OK) return r;
     if ((r = rec(1, 0)) != MPX_OK) return r;
-    CK(launch_hbulk<T>(p, 2, 1, st));
+    CK(launch_hbulk_film<T>(p, nblk, 1, st));
     if ((r = rec(1, 1)) != MPX_OK) return r;
     return MPX_OK;
 }

@@ -243,6 +243,7 @@ constexpr int kPassTX = 64, kPassTY = 4; // separate-pass tile: 64 x 4 slots of 
 constexpr int kWideTX = 256, kWideTY = 1; // the wide tile of the single-instance passes
 constexpr int kWideMinNx = 512;           // grids this wide use it
 
+template <typename T> hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s);
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
 template <typename T> hipError_t launch_sweep(const KParams<T> &p, int kchunk, hipStream_t s);

@@ -14,6 +14,7 @@
 // boundary use folded, zero-filled loads.  Per-tile CPML / source / film
 // flags come from a host table (one per tile shape); edge coefficients come
 // from the material table by the slot's class byte (no per-block staging).
+#include "film.h"
 #include "stencil.h"
 
 namespace mpx {
@@ -221,6 +222,24 @@ __global__ void __launch_bounds__(TX *TY) k_hbulk(KParams<T> p, int inc_step) {
     hpass_block<T, NHALF, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// the merged H/M pass and the film kernel's second half step in one launch
+// (256 x 1 tiles): the first zf planes of the grid are the film blocks,
+// dispatched first so that the latency-bound LLG solves overlap the bulk
+// planes.  The two touch disjoint data: the film blocks read the prepass the
+// first half step wrote and write M and H of magnetic faces, which the bulk
+// blocks load but never store or use.
+template <typename T>
+__global__ void __launch_bounds__(kWideTX) k_hbulk_film(KParams<T> p, int inc_step, int zf, int nfb) {
+    if ((int)blockIdx.z < zf) {
+        const int fb = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+        if (fb < nfb) film_body(p, 2, 0, fb);
+        return;
+    }
+    const int k = (int)blockIdx.z - zf;
+    if (inc_step && blockIdx.x == 0 && blockIdx.y == 0 && k == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
+    hpass_block<T, 2, kWideTX, kWideTY>(p, blockIdx.x, blockIdx.y, k);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_emixed(KParams<T> p) {
     const int m = blockIdx.x * 256 + threadIdx.x;
@@ -314,6 +333,24 @@ hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s) 
     return hipGetLastError();
 }
 
+// the film's second half step (nblk blocks) and the merged H/M pass; on
+// 256 x 1 tiles one launch, else two
+template <typename T>
+hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s) {
+    if (nblk == 0) return launch_hbulk<T>(p, 2, inc, s);
+    if (!p.wide) {
+        hipError_t e = launch_film<T>(p, nblk, 2, 0, s);
+        if (e != hipSuccess) return e;
+        return launch_hbulk<T>(p, 2, inc, s);
+    }
+    static_assert(kWideTX == 256 && kWideTY == 1, "film blocks are 256 threads along x");
+    const dim3 g = pass_grid<kWideTX, kWideTY>(p.n);
+    const int per_plane = (int)(g.x * g.y);
+    const int zf = (nblk + per_plane - 1) / per_plane;
+    k_hbulk_film<T><<<dim3(g.x, g.y, g.z + zf), dim3(kWideTX, kWideTY), 0, s>>>(p, inc, zf, nblk);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
                               hipStream_t s) {
@@ -338,6 +375,7 @@ hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwo
 #define MPX_PASSES(T)                                                                                      \
     template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                                 \
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);                       \
+    template hipError_t launch_hbulk_film<T>(const KParams<T> &, int, int, hipStream_t);                  \
     template hipError_t launch_epass_batch<T>(const KParams<T> *, const int4 *, int, const int2 *, int,   \
                                               hipStream_t);                                               \
     template hipError_t launch_hbulk_batch<T>(const KParams<T> *, const int4 *, int, int, int, hipStream_t);
