@@ -140,7 +140,9 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
             own = Mn[c];
         }
     }
-    // block partial of the own component (mean-M probes)
+    // block partial of the own component (mean-M probes, which read it
+    // between the two half steps: the second half step's would go unread)
+    if (phase != 1) return;
     red[threadIdx.x] = own;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
