@@ -1,0 +1,101 @@
+"""Grids at least 512 slots wide: the passes run on 256 x 1 tiles, and the
+film's second half step shares one launch with the merged H/M pass.
+
+A thin 520-wide box with a film, CPML slabs on the x faces and a source is
+checked against the FP64 oracle in both precisions, and a batch holding it
+(whose kernels launch the film and H/M work separately) must end bitwise
+equal to stepping it alone.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from paper_2510_22221_amd import mpx
+from synth import workloads as W
+from tests.parity import group_errors, rel, run_pair
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+CALLS = (7, 12, 1, 5)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _libs():
+    O.build()
+    mpx.load()
+
+
+def wide_case(nsteps):
+    w = W.random_case(41, nx=520, ny=12, nz=10, bc=(W.PML, W.PML, W.PEC, W.PEC, W.PEC, W.PEC),
+                      npml=(2, 2, 0, 0, 0, 0), nsteps=nsteps)
+    w.H0 = (3e6, 0.0, 5e6)
+    w.probes = [W.Probe("field", 1, (260, 6, 5)), W.Probe("mean_m", film=0), W.Probe("film_energy", film=0)]
+    return w
+
+
+@pytest.mark.parametrize("prec,tol", [(mpx.F64, 1e-11), (mpx.F32, 1e-4)])
+def test_wide_grid_matches_oracle(prec, tol):
+    n = 30
+    w = wide_case(n)
+    say(f"520-wide box, film, x CPML, {n} steps prec={prec}")
+    g, o = run_pair(w, n, prec, threads=THREADS, chunks=3)
+    errs = group_errors(g, o)
+    say(f"  groups {errs}")
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    # probes: the field trace and the film energy to the same relative L2;
+    # the film-mean M in float64 to the summation-order bound of a mean of
+    # n_sum terms of magnitude <= Ms (each partial order rounds differently):
+    # n_sum 2^-53 max Ms, n_sum = 2 faces per family and cell, 3 families
+    n_mag = int(sum(np.count_nonzero(w.ids == m) for m, mat in enumerate(w.materials) if mat[3] > 0))
+    ms_max = max(mat[3] for mat in w.materials)
+    for pid, p in enumerate(w.probes):
+        nval = 3 if p.kind == "mean_m" else 1
+        a, b = g.read_probe(pid, nval), o.read_probe(pid, nval)
+        if p.kind == "mean_m" and prec == mpx.F64:
+            bound = 6 * n_mag * 2.0 ** -53 * ms_max
+            say(f"  mean M: max |diff| {float(np.abs(a - b).max()):.3e} (bound {bound:.3e})")
+            assert float(np.abs(a - b).max()) <= bound
+        else:
+            e = rel(np.asarray(a, dtype=np.float64).ravel(), np.asarray(b, dtype=np.float64).ravel())
+            say(f"  {p.kind}: rel L2 {e:.2e}")
+            assert e <= tol, p.kind
+
+
+def state(sim, w):
+    out = [sim.get(f).copy() for f in range(12)]
+    for pid, p in enumerate(w.probes):
+        out.append(sim.read_probe(pid, 3 if p.kind == "mean_m" else 1).copy())
+    return out
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+def test_wide_member_of_a_batch_bitwise(prec):
+    n = sum(CALLS) + 2
+    ws = [wide_case(n), W.c3_instance(64, 40, 32, 1.05, n)]
+    ref = []
+    for w in ws:
+        s = mpx.from_workload(w, precision=prec, graph_steps=4)
+        for c in CALLS:
+            s.step(c)
+        s.sync()
+        ref.append(state(s, w))
+        s.close()
+    sims = [mpx.from_workload(w, precision=prec) for w in ws]
+    b = mpx.Batch(sims)
+    b.set_graph_steps(4)
+    for c in CALLS:
+        b.step(c)
+    b.sync()
+    for q, (s, w) in enumerate(zip(sims, ws)):
+        for k, (a, r) in enumerate(zip(state(s, w), ref[q])):
+            assert np.array_equal(a, r), (q, k)
+    b.close()
+    for s in sims:
+        s.close()
