@@ -126,12 +126,12 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
                 F.H1[c * F.ns + l] = hnew;
                 if (F.Bn2 && le >= 0) {
                     // the phase-2 prepass of this face: B^ = H1 + M1_c, B^* =
-                    // B^ - dt/(2 mu0) curl E with the same E
-                    double d1, d2;
-                    curl_e64(p, c, idx, d1, d2);
+                    // B^ - dt/(2 mu0) curl E with the same E (the prepass
+                    // left that term in this face's B^* slot)
+                    const double cu = F.Bs2[c * F.nse + le];
                     const double b2 = hnew + Mn[c];
                     F.Bn2[c * F.nse + le] = b2;
-                    F.Bs2[c * F.nse + le] = b2 - p.hcd * (d1 - d2);
+                    F.Bs2[c * F.nse + le] = b2 - cu;
                 }
             } else {
                 for (int w = 0; w < 3; w++) F.M[(c * 3 + w) * F.ns + l] = Mn[w];

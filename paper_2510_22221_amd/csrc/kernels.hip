@@ -84,11 +84,12 @@ __device__ __forceinline__ void site_params(const KParams<T> &p, int c, const in
 
 // B^ and B^* at the face of family cq at idx (folded), for film f; for a
 // non-magnetic face in phase 1 also those of phase 2 (bn2, bs2: the phase-2
-// expressions, from the same H and E); mag tells whether the face is magnetic
+// expressions, from the same H and E); mag tells whether the face is
+// magnetic, cu is its dt/(2 mu0) (curl E)_cq term
 template <typename T>
 __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int cq, const int *idx, double &bn,
-                                     double &bs, double &bn2, double &bs2, bool &mag) {
-    bn2 = bs2 = 0.0;
+                                     double &bs, double &bn2, double &bs2, bool &mag, double &cu) {
+    bn2 = bs2 = cu = 0.0;
     mag = false;
     if (idx[0] < 0 || idx[1] < 0 || idx[2] < 0) { // outside the domain (cannot happen for the
         bn = bs = 0.0;                             // film placements set_materials accepts)
@@ -100,6 +101,7 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     bool inside;
     const long long l = film_local<T>(F, idx, inside);
     mag = inside && F.prm[(cq * 3) * F.ns + l] > 0.0;
+    cu = p.hcd * (d1 - d2);
     double b;
     if (mag) {
         if (phase == 1)
@@ -109,16 +111,16 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     } else {
         const double h0 = (double)p.H[cq][p.slot(idx[0], idx[1], idx[2])];
         double h = h0;
-        if (phase == 2) h = h - p.hcd * (d1 - d2);
+        if (phase == 2) h = h - cu;
         b = h + 0.0;
         if (phase == 1) {
-            const double h2 = h0 - p.hcd * (d1 - d2);
+            const double h2 = h0 - cu;
             bn2 = h2 + 0.0;
-            bs2 = bn2 - p.hcd * (d1 - d2);
+            bs2 = bn2 - cu;
         }
     }
     bn = b;
-    bs = b - p.hcd * (d1 - d2);
+    bs = b - cu;
 }
 
 // B^ prepass: B^n and B^* of every face of the grown face box
@@ -131,14 +133,20 @@ __device__ __forceinline__ void bhat_body(const KParams<T> &p, int phase, int bl
     if (l >= F.nse) return;
     const int idx[3] = {F.e0[0] + (int)(l % F.en[0]), F.e0[1] + (int)((l / F.en[0]) % F.en[1]),
                         F.e0[2] + (int)(l / ((long long)F.en[0] * F.en[1]))};
-    double bn, bs, bn2, bs2;
+    double bn, bs, bn2, bs2, cu;
     bool mag;
-    bhat(p, phase, f, c, idx, bn, bs, bn2, bs2, mag);
+    bhat(p, phase, f, c, idx, bn, bs, bn2, bs2, mag, cu);
     F.Bn[c * F.nse + l] = bn;
     F.Bs[c * F.nse + l] = bs;
-    if (phase == 1 && !mag && F.Bn2) { // magnetic faces: the film kernel writes them
-        F.Bn2[c * F.nse + l] = bn2;
-        F.Bs2[c * F.nse + l] = bs2;
+    if (phase == 1 && F.Bn2) {
+        if (!mag) {
+            F.Bn2[c * F.nse + l] = bn2;
+            F.Bs2[c * F.nse + l] = bs2;
+        } else {
+            // a magnetic face: the film kernel completes it from its solve;
+            // it finds the curl term here (only its own thread reads it)
+            F.Bs2[c * F.nse + l] = cu;
+        }
     }
 }
 
