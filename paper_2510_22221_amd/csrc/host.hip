@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace mpx;
@@ -2060,6 +2061,70 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         std::vector<uint8_t> hc(s->nslot);
         CK(hipMemcpyAsync(hc.data(), s->d_cls, s->nslot, hipMemcpyDeviceToHost, s->stream));
         CK(hipStreamSynchronize(s->stream));
+        // per mixed slot, the ids of the four cells of each edge (a wall
+        // edge, never updated, as a flag) key a first table; the edge
+        // coefficients are computed once per distinct id key, and id keys
+        // with equal coefficient triples share a class
+        struct IdKey {
+            unsigned long long lo = 0, hi = 0; // 12 ids, then the wall flags
+            bool operator==(const IdKey &o) const { return lo == o.lo && hi == o.hi; }
+        };
+        struct IdKeyHash {
+            size_t operator()(const IdKey &k) const {
+                return (size_t)(k.lo * 0x9e3779b97f4a7c15ULL ^ (k.hi + 0x632be59bd9b4e019ULL) * 0xbf58476d1ce4e5b9ULL);
+            }
+        };
+        std::unordered_map<IdKey, int, IdKeyHash> id_index;
+        std::vector<IdKey> id_keys;
+        std::vector<long long> id_count;
+        std::vector<std::pair<long long, int>> slot_key; // mixed slot -> its id key
+        for (int k = 0; k < s->n[2]; k++)
+            for (int j = 0; j < s->n[1]; j++)
+                for (int i = 0; i < s->n[0]; i++) {
+                    const long long q = (long long)i + (long long)s->px * ((long long)j + (long long)s->n[1] * k);
+                    if (hc[q] != kMixed) continue;
+                    const int idx[3] = {i, j, k};
+                    uint8_t m12[12] = {};
+                    unsigned wall_bits = 0;
+                    for (int C = 0; C < 3; C++) {
+                        bool wall = false;
+                        for (int a = 0; a < 3; a++)
+                            if (a != C && !s->per[a] && idx[a] == 0) wall = true;
+                        if (wall) {
+                            wall_bits |= 1u << C;
+                            continue;
+                        }
+                        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+                        for (int u = 0; u < 2; u++)
+                            for (int v = 0; v < 2; v++) {
+                                int cc[3] = {i, j, k};
+                                cc[C1] -= 1 - u;
+                                cc[C2] -= 1 - v;
+                                for (int a = 0; a < 3; a++)
+                                    if (cc[a] < 0) cc[a] += s->n[a]; // periodic (walls excluded above)
+                                m12[4 * C + 2 * u + v] =
+                                    ids[(size_t)cc[0] + (size_t)s->n[0] * (cc[1] + (size_t)s->n[1] * cc[2])];
+                            }
+                    }
+                    IdKey key;
+                    memcpy(&key.lo, m12, 8);
+                    unsigned tail = 0;
+                    memcpy(&tail, m12 + 8, 4);
+                    key.hi = (unsigned long long)tail | ((unsigned long long)wall_bits << 32);
+                    auto it = id_index.find(key);
+                    int ki;
+                    if (it == id_index.end()) {
+                        ki = (int)id_keys.size();
+                        id_index.emplace(key, ki);
+                        id_keys.push_back(key);
+                        id_count.push_back(0);
+                    } else {
+                        ki = it->second;
+                    }
+                    id_count[ki]++;
+                    slot_key.emplace_back(q, ki);
+                }
+        // the coefficient triple of each id key, merged by value
         using Key = std::array<unsigned long long, 9>;
         struct Entry {
             long long count = 0;
@@ -2067,49 +2132,35 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             CoefDev<double> e[3];
         };
         std::map<Key, Entry> seen;
-        std::vector<std::pair<long long, Entry *>> slot_key; // mixed slot -> its triple (map nodes are stable)
-        for (int k = 0; k < s->n[2]; k++)
-            for (int j = 0; j < s->n[1]; j++)
-                for (int i = 0; i < s->n[0]; i++) {
-                    const long long q = (long long)i + (long long)s->px * ((long long)j + (long long)s->n[1] * k);
-                    if (hc[q] != kMixed) continue;
-                    const int idx[3] = {i, j, k};
-                    CoefDev<double> e[3];
-                    std::array<unsigned long long, 9> key{};
-                    for (int C = 0; C < 3; C++) {
-                        bool wall = false;
-                        for (int a = 0; a < 3; a++)
-                            if (a != C && !s->per[a] && idx[a] == 0) wall = true;
-                        if (wall) {
-                            // tangential to a lower wall: never updated
-                            e[C] = CoefDev<double>{};
-                            e[C].pec = 1;
-                        } else {
-                            const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-                            int m4[4];
-                            for (int u = 0; u < 2; u++)
-                                for (int v = 0; v < 2; v++) {
-                                    int cc[3] = {i, j, k};
-                                    cc[C1] -= 1 - u;
-                                    cc[C2] -= 1 - v;
-                                    for (int a = 0; a < 3; a++)
-                                        if (cc[a] < 0) cc[a] += s->n[a]; // periodic (walls excluded above)
-                                    m4[2 * u + v] = ids[(size_t)cc[0] + (size_t)s->n[0] * (cc[1] + (size_t)s->n[1] * cc[2])];
-                                }
-                            e[C] = coef_of(m4);
-                        }
-                        memcpy(&key[3 * C], &e[C].ca, 8);
-                        memcpy(&key[3 * C + 1], &e[C].cb, 8);
-                        key[3 * C + 2] = (unsigned long long)e[C].pec;
-                    }
-                    auto it = seen.find(key);
-                    if (it == seen.end()) {
-                        it = seen.emplace(key, Entry{}).first;
-                        for (int C = 0; C < 3; C++) it->second.e[C] = e[C];
-                    }
-                    it->second.count++;
-                    slot_key.emplace_back(q, &it->second);
+        std::vector<Entry *> entry_of(id_keys.size(), nullptr);
+        for (size_t ki = 0; ki < id_keys.size(); ki++) {
+            uint8_t m12[12];
+            memcpy(m12, &id_keys[ki].lo, 8);
+            const unsigned tail = (unsigned)(id_keys[ki].hi & 0xffffffffULL);
+            memcpy(m12 + 8, &tail, 4);
+            const unsigned wall_bits = (unsigned)(id_keys[ki].hi >> 32);
+            CoefDev<double> e[3];
+            Key key{};
+            for (int C = 0; C < 3; C++) {
+                if (wall_bits & (1u << C)) {
+                    e[C] = CoefDev<double>{};
+                    e[C].pec = 1;
+                } else {
+                    const int m4[4] = {m12[4 * C], m12[4 * C + 1], m12[4 * C + 2], m12[4 * C + 3]};
+                    e[C] = coef_of(m4);
                 }
+                memcpy(&key[3 * C], &e[C].ca, 8);
+                memcpy(&key[3 * C + 1], &e[C].cb, 8);
+                key[3 * C + 2] = (unsigned long long)e[C].pec;
+            }
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(key, Entry{}).first;
+                for (int C = 0; C < 3; C++) it->second.e[C] = e[C];
+            }
+            it->second.count += id_count[ki];
+            entry_of[ki] = &it->second; // map nodes are stable
+        }
         std::vector<std::pair<long long, Entry *>> order;
         for (auto &kv : seen) order.emplace_back(kv.second.count, &kv.second);
         std::stable_sort(order.begin(), order.end(),
@@ -2125,7 +2176,7 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         }
         bool changed = false;
         for (auto &sk : slot_key) {
-            const int cl = sk.second->cls;
+            const int cl = entry_of[sk.second]->cls;
             if (cl == kMixed) continue;
             hc[sk.first] = (uint8_t)cl;
             changed = true;
