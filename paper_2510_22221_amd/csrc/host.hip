@@ -597,8 +597,8 @@ mpx_status check_live(mpx_sim *s) {
 }
 
 // per-tile flags of the separate passes (tx x ty slots of one plane, with a
-// one-slot halo): 1 = touches a CPML slab, 2 = a source box, 4 = a film's
-// face box; with a periodic axis every tile may see index 0 through the wrap
+// one-slot halo): 1 = touches a CPML slab, 8 = a y or z CPML slab (1 without
+// 8: x slabs only), 2 = a source box, 4 = a film's face box; with a periodic axis every tile may see index 0 through the wrap
 std::vector<uint8_t> tile_flags(const mpx_sim *s, int tx, int ty) {
     const int nxt = (s->n[0] + tx - 1) / tx, nyt = (s->n[1] + ty - 1) / ty;
     const int nt = nxt * nyt * s->n[2];
@@ -609,8 +609,8 @@ std::vector<uint8_t> tile_flags(const mpx_sim *s, int tx, int ty) {
         const int lo[3] = {i0 - 1, j0 - 1, k - 1}, hi[3] = {i0 + tx, j0 + ty, k + 1};
         uint8_t f = 0;
         for (int a = 0; a < 3; a++) {
-            if (s->nlo[a] > 0 && lo[a] < s->nlo[a]) f |= 1;
-            if (s->nhi[a] > 0 && hi[a] >= s->n[a] - s->nhi[a]) f |= 1;
+            const bool slab = (s->nlo[a] > 0 && lo[a] < s->nlo[a]) || (s->nhi[a] > 0 && hi[a] >= s->n[a] - s->nhi[a]);
+            if (slab) f |= a == 0 ? 1 : 1 | 8;
         }
         for (auto &src : s->srcs) {
             bool in = true;

@@ -101,13 +101,25 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     }
 }
 
+// whether this wave takes the CPML path: a wide tile that reaches CPML slabs
+// only along x (flag 1 without 8) needs it only in the waves whose 64 slots,
+// with the one-slot halo, reach an x slab (the same test as the tile's, on
+// the wave's range; uniform over the wave, so the other waves skip it)
+template <typename T, int TX>
+__device__ __forceinline__ bool wave_pml(const KParams<T> &p, int bx, int f) {
+    if (!(f & 1)) return false;
+    if (TX != kWideTX || (f & 8)) return true;
+    const int w0 = bx * TX + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
+    return (p.nlo[0] > 0 && w0 - 1 < p.nlo[0]) || (p.nhi[0] > 0 && w0 + 64 >= p.n[0] - p.nhi[0]);
+}
+
 // a block: the TX x TY slots (bx, by) of plane k, flags from the table of
 // that tile shape
 template <typename T, int TX = PTX, int TY = PTY>
 __device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + TX - 1) / TX, nyt = (p.n[1] + TY - 1) / TY;
     const int f = (TX == PTX ? p.pflags : p.pflags_w)[bx + nxt * (by + nyt * k)];
-    epass_tile<T>(p, bx * TX, by * TY, k, (f & 1) != 0, (f & 2) != 0);
+    epass_tile<T>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 2) != 0);
 }
 
 // the mixed slots, one thread each: the general path (folded loads, edge
@@ -198,7 +210,7 @@ template <typename T, int NHALF, int TX = PTX, int TY = PTY>
 __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + TX - 1) / TX, nyt = (p.n[1] + TY - 1) / TY;
     const int f = (TX == PTX ? p.pflags : p.pflags_w)[bx + nxt * (by + nyt * k)];
-    hpass_tile<T, NHALF>(p, bx * TX, by * TY, k, (f & 1) != 0, (f & 4) != 0);
+    hpass_tile<T, NHALF>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 4) != 0);
 }
 
 // grid (x tiles, y tiles, planes) in natural order: the blocks resident at
