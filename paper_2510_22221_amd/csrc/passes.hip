@@ -71,10 +71,46 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
     const long long step = tsrc ? p.step[0] : 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
-    // every load of the thread before any store: CPML state of the three edges
     int q0[3], q1[3], q2[3];
     const bool v0 = inside && e_site<T, 0, true>(p, i, j, k, q0), v1 = inside && e_site<T, 1, true>(p, i, j, k, q1),
                v2 = inside && e_site<T, 2, true>(p, i, j, k, q2);
+    if constexpr (sizeof(T) == 8) {
+        // float64: the CPML state of one edge at a time (each thread alone
+        // reads and writes its edges' psi and E), which keeps the kernel's
+        // registers, and with them its occupancy, near the bulk path's
+        if (!inside || c0 == kMixed) return;
+        T n0 = T(0), n1 = T(0), n2 = T(0);
+        {
+            Psi2<T> r;
+            if (tpml && v0) r = psi_load<T, 0, true>(p, q0);
+            if (v0)
+                n0 = e_apply<T, 0, CoefMem<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy), dif(hy0, hy_km, dz, iz),
+                                                     r, tsrc, step);
+            if (tpml) psi_store<T, 0>(p.psiE[0], r);
+        }
+        {
+            Psi2<T> r;
+            if (tpml && v1) r = psi_load<T, 1, true>(p, q1);
+            if (v1)
+                n1 = e_apply<T, 1, CoefMem<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz), dif(hz0, hz_xm, dx, ix),
+                                                     r, tsrc, step);
+            if (tpml) psi_store<T, 1>(p.psiE[1], r);
+        }
+        {
+            Psi2<T> r;
+            if (tpml && v2) r = psi_load<T, 2, true>(p, q2);
+            if (v2)
+                n2 = e_apply<T, 2, CoefMem<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix), dif(hx0, hx_ym, dy, iy),
+                                                     r, tsrc, step);
+            if (tpml) psi_store<T, 2>(p.psiE[2], r);
+        }
+        ex[o] = n0;
+        ey[o] = n1;
+        ez[o] = n2;
+        return;
+    }
+    // float32: every load of the thread before any store (the CPML state of
+    // the three edges too)
     Psi2<T> r0, r1, r2;
     if (tpml) {
         if (v0) r0 = psi_load<T, 0, true>(p, q0);
@@ -180,10 +216,12 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
     const int idx[3] = {ic, jc, k};
     Psi2<T> r0, r1, r2;
-    if (tpml && inside) {
-        r0 = psi_load<T, 0, false>(p, idx);
-        r1 = psi_load<T, 1, false>(p, idx);
-        r2 = psi_load<T, 2, false>(p, idx);
+    if constexpr (sizeof(T) == 4) {
+        if (tpml && inside) {
+            r0 = psi_load<T, 0, false>(p, idx);
+            r1 = psi_load<T, 1, false>(p, idx);
+            r2 = psi_load<T, 2, false>(p, idx);
+        }
     }
     bool mag[3] = {false, false, false};
     if (tfilm && inside) {
@@ -192,6 +230,38 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
         mag[2] = face_is_magnetic(p, 2, idx);
     }
     if (!inside) return;
+    if constexpr (sizeof(T) == 8) {
+        // float64: the CPML state of one face at a time (as in the E pass)
+        T *hx = p.H[0] + k * sz, *hy = p.H[1] + k * sz, *hz = p.H[2] + k * sz;
+        {
+            Psi2<T> r;
+            if (tpml) r = psi_load<T, 0, false>(p, idx);
+            const T n = h_apply<T, 0, NHALF>(p, h0, dif(ez_yp, ez0, dy, iy), dif(ey_kp, ey0, dz, iz), r);
+            if (!mag[0]) {
+                hx[o] = n;
+                if (tpml) psi_store<T, 0>(p.psiH[0], r);
+            }
+        }
+        {
+            Psi2<T> r;
+            if (tpml) r = psi_load<T, 1, false>(p, idx);
+            const T n = h_apply<T, 1, NHALF>(p, h1, dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), r);
+            if (!mag[1]) {
+                hy[o] = n;
+                if (tpml) psi_store<T, 1>(p.psiH[1], r);
+            }
+        }
+        {
+            Psi2<T> r;
+            if (tpml) r = psi_load<T, 2, false>(p, idx);
+            const T n = h_apply<T, 2, NHALF>(p, h2, dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), r);
+            if (!mag[2]) {
+                hz[o] = n;
+                if (tpml) psi_store<T, 2>(p.psiH[2], r);
+            }
+        }
+        return;
+    }
     const T n0 = h_apply<T, 0, NHALF>(p, h0, dif(ez_yp, ez0, dy, iy), dif(ey_kp, ey0, dz, iz), r0);
     const T n1 = h_apply<T, 1, NHALF>(p, h1, dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), r1);
     const T n2 = h_apply<T, 2, NHALF>(p, h2, dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), r2);
