@@ -88,6 +88,35 @@ def test_trace_adjoint_matches_oracle_finite_differences(pml, field):
         assert close(a, b, sc), (a, b)
 
 
+def test_trace_adjoint_without_films():
+    """No magnetic cell: the bias enters nothing, so dL/dH0 is exactly zero,
+    and dL/deps_r still matches the oracle's differences."""
+    w = W.random_case(12, nx=18, ny=14, nz=12, nsteps=40, film=False)
+    n, K, ijk = 40, 6, (9, 7, 6)
+    wt = np.random.default_rng(12).standard_normal(n)
+    eb = (7, 5, 4, 3, 2, 2)
+    g = mpx.from_workload(w, precision=mpx.F64)
+    res = g.adjoint_probe(n, 1, ijk, wt, checkpoint_every=K, eps_box=eb)
+    g.close()
+
+    def lossf(w2):
+        return fd.trace_loss(w2, n, 1, ijk, wt)
+
+    assert res["loss"] == pytest.approx(lossf(w), rel=1e-11)
+    assert np.all(res["dH0"] == 0.0)
+    ge = []
+    for (di, dj, dk) in ((0, 0, 0), (2, 1, 1), (1, 0, 1)):
+        cell = (eb[0] + di, eb[1] + dj, eb[2] + dk)
+        if w.materials[int(w.ids[cell[2], cell[1], cell[0]])][2]:
+            continue
+        ge.append((res["deps"][dk, dj, di], fd.grad_eps_of(lossf, w, cell)))
+    say(f"no film: dL/deps (adjoint, fd) {ge}")
+    sc = max(abs(b) for _, b in ge)
+    assert sc > 0
+    for a, b in ge:
+        assert close(a, b, sc), (a, b)
+
+
 def run(w, prec, n, field, ijk, wt, K, eps_box, ms_box, graphs=True):
     g = mpx.from_workload(w, precision=prec, graph_steps=None if graphs else 0)
     res = g.adjoint_probe(n, field, ijk, wt, checkpoint_every=K, eps_box=eps_box, ms_box=ms_box)
