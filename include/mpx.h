@@ -241,13 +241,15 @@ mpx_status mpx_set_graph_steps(mpx_sim *sim, int32_t steps);
 mpx_status mpx_set_schedule(mpx_sim *sim, int32_t fused, int32_t kchunk);
 
 /* Kernel timing with HIP events on the handle's stream.  With every > 0,
- * mpx_step launches each step's kernels directly (no graph) and brackets
- * three groups of every `every`-th step with events; 0 turns timing off.
+ * mpx_step launches every `every`-th step's kernels directly and brackets
+ * three groups of them with events; the every - 1 steps between two timed
+ * ones replay a captured graph (unless mpx_set_graph_steps(sim, 0)); 0 turns
+ * timing off.  Results are the same bits either way.
  * mpx_kernel_time fills avg_ms[3] (average device time per timed launch,
  * ms) and launches[3] for the last mpx_step call: 0 = the main stencil
- * kernel (fused pass, or the E pass of the two-pass schedule), 1 = the H pass
- * of the two-pass schedule (0 launches when fused), 2 = the film half steps
- * and probes of a step together. */
+ * kernel (fused pass, or the E pass of the two-pass schedule), 1 = the H/M
+ * pass of the two-pass schedule with the film's second half step (0 launches
+ * when fused), 2 = the film's first half step and the probes. */
 mpx_status mpx_set_timing(mpx_sim *sim, int32_t every);
 mpx_status mpx_kernel_time(mpx_sim *sim, double *avg_ms, int64_t *launches);
 

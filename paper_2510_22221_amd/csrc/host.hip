@@ -112,6 +112,12 @@ struct mpx_sim {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     bool graph_valid[2] = {false, false};
+    // with timing on: graphs of the timing_every - 1 untimed steps between
+    // two timed ones, per starting parity, and the parity each ends at
+    hipGraphExec_t tgexec[2] = {nullptr, nullptr};
+    hipGraph_t tgraph[2] = {nullptr, nullptr};
+    bool tgraph_valid[2] = {false, false};
+    int tgraph_end[2] = {0, 0};
     // timing
     int timing_every = 0;
     std::vector<hipEvent_t> ev;
@@ -306,6 +312,11 @@ void drop_graph(mpx_sim *s) {
         s->gexec[q] = nullptr;
         s->graph[q] = nullptr;
         s->graph_valid[q] = false;
+        if (s->tgexec[q]) (void)hipGraphExecDestroy(s->tgexec[q]);
+        if (s->tgraph[q]) (void)hipGraphDestroy(s->tgraph[q]);
+        s->tgexec[q] = nullptr;
+        s->tgraph[q] = nullptr;
+        s->tgraph_valid[q] = false;
     }
 }
 
@@ -537,9 +548,40 @@ mpx_status enqueue_steps(mpx_sim *s, long long nsteps) {
     mpx_status r;
     int par = s->parity;
     if (s->timing_every > 0) {
+        // every timing_every-th step timed with events (direct launches);
+        // the untimed runs between them replayed from a captured graph
+        // unless graphs are off
         s->evi = 0;
-        for (long long n = 0; n < body; n++)
-            if ((r = run_body<T>(s, par, n % s->timing_every == 0)) != MPX_OK) return r;
+        const int U = s->timing_every - 1;
+        long long n = 0;
+        while (n < body) {
+            if ((r = run_body<T>(s, par, true)) != MPX_OK) return r;
+            n++;
+            if (U > 0 && s->graph_steps > 0 && body - n >= U) {
+                if (!s->tgraph_valid[par]) {
+                    CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    int cp = par;
+                    for (int u = 0; u < U; u++) {
+                        r = run_body<T>(s, cp, false);
+                        if (r != MPX_OK) {
+                            hipGraph_t g;
+                            (void)hipStreamEndCapture(st, &g);
+                            return r;
+                        }
+                    }
+                    CK(hipStreamEndCapture(st, &s->tgraph[par]));
+                    CK(hipGraphInstantiate(&s->tgexec[par], s->tgraph[par], nullptr, nullptr, 0));
+                    s->tgraph_valid[par] = true;
+                    s->tgraph_end[par] = cp;
+                }
+                CK(hipGraphLaunch(s->tgexec[par], st));
+                par = s->tgraph_end[par];
+                n += U;
+            } else {
+                for (; n < body && (n % s->timing_every) != 0; n++)
+                    if ((r = run_body<T>(s, par, false)) != MPX_OK) return r;
+            }
+        }
         if ((r = run_last<T>(s, par)) != MPX_OK) return r;
         s->parity = par;
         CK(hipStreamSynchronize(st));
@@ -2695,6 +2737,7 @@ mpx_status mpx_set_graph_steps(mpx_sim *s, int32_t steps) {
 
 mpx_status mpx_set_timing(mpx_sim *s, int32_t every) {
     if (!s || every < 0) return MPX_E_INVALID;
+    if (every != s->timing_every) drop_graph(s); // the untimed runs' graphs have its length
     s->timing_every = every;
     return MPX_OK;
 }

@@ -214,7 +214,8 @@ class Sim:
         self._ck(self._L.mpx_set_graph_steps(self._h, int(n)), "set_graph_steps")
 
     def set_timing(self, every):
-        """0: off; n > 0: event-time every n-th step (direct launches)."""
+        """0: off; n > 0: event-time every n-th step (launched directly; the
+        steps between replay a captured graph)."""
         self._ck(self._L.mpx_set_timing(self._h, int(every)), "set_timing")
 
     # ---- stepping ------------------------------------------------------------

@@ -281,3 +281,29 @@ def test_fused_schedule_bitwise_equals_two_pass(name, make, nsteps):
         a.step(nsteps)
         for f in range(9):
             assert np.array_equal(a.get(f), b.get(f)), ("f32", variant, f)
+
+
+# ------------------------------------------------------------------ timed stepping
+@pytest.mark.parametrize("fused,every", [(0, 10), (0, 4), (0, 1), (2, 7)])
+def test_timed_steps_bitwise_equal_untimed(fused, every):
+    """Stepping with per-kernel timing (every `every`-th step timed with
+    events, the untimed runs between them replayed from captured graphs)
+    gives the same bits as stepping without, and times one step in every
+    `every`."""
+    w = W.c1(90)
+    ref = mpx.from_workload(w, fused=fused)
+    for n in (37, 53):
+        ref.step(n)
+    g = mpx.from_workload(w, fused=fused)
+    g.set_timing(every)
+    for n in (37, 53):
+        g.step(n)
+    kt = g.kernel_time()
+    g.set_timing(0)
+    for f in range(12):
+        assert np.array_equal(g.get(f), ref.get(f)), f
+    for pid, p in enumerate(w.probes):
+        nv = 3 if p.kind == "mean_m" else 1
+        assert np.array_equal(g.read_probe(pid, nv), ref.read_probe(pid, nv)), pid
+    # the body of the last call (53 steps: 52 merged pairs) has ceil(52 / every) timed steps
+    assert kt[0][1] == -(-52 // every), kt
