@@ -246,7 +246,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
-              "across GPUs by design, but this build runs on one GPU only)", file=sys.stderr)
+              "across GPUs by design; only the one-GPU path is implemented)", file=sys.stderr)
         sys.exit(2)
     from synth import workloads as W
     from paper_2510_22221_amd import mpx
