@@ -71,6 +71,7 @@ struct mpx_sim {
     int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
     int kchunk = 16;
     void *d_coef = nullptr;
+    void *d_coefx = nullptr; // extended coefficient table of the mixed-class slots
     // materials
     bool have_mat = false;
     std::vector<mpx_material> mats;
@@ -262,6 +263,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.cls = s->d_cls;
     p.mat = s->d_mat;
     p.coef = (const CoefDev<T> *)s->d_coef;
+    p.coefx = (const CoefDev<T> *)s->d_coefx;
     p.nfilm = (int)s->films.size();
     p.films = s->d_films;
     p.blocktab = s->d_blocktab;
@@ -1957,6 +1959,7 @@ mpx_status mpx_destroy(mpx_sim *s) {
     drop_graph(s);
     for (auto e : s->ev) (void)hipEventDestroy(e);
     (void)hipFree(s->d_coef);
+    (void)hipFree(s->d_coefx);
     for (int c = 0; c < 3; c++) {
         (void)hipFree(s->E[c]);
         (void)hipFree(s->H[c]);
@@ -2216,14 +2219,56 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             for (int C = 0; C < 3; C++) cd[kCoefPerClass * next + C] = o.second->e[C];
             next++;
         }
+        // the triples left without a class get an entry of the extended
+        // table (up to kMaxExt of them; beyond, the cell-id path)
+        constexpr long long kMaxExt = 1 << 20;
+        std::vector<CoefDev<double>> cdx;
+        std::map<const Entry *, int> ext_of;
+        for (auto &o : order) {
+            if (o.second->cls != kMixed || (long long)ext_of.size() >= kMaxExt) continue;
+            ext_of.emplace(o.second, (int)ext_of.size());
+            for (int C = 0; C < 3; C++) cdx.push_back(o.second->e[C]);
+        }
+        // the mixed list, in slot order
+        std::vector<int4> mixed;
         bool changed = false;
         for (auto &sk : slot_key) {
-            const int cl = entry_of[sk.second]->cls;
-            if (cl == kMixed) continue;
-            hc[sk.first] = (uint8_t)cl;
+            const Entry *en = entry_of[sk.second];
+            if (en->cls == kMixed) {
+                const long long q = sk.first;
+                auto it = ext_of.find(en);
+                mixed.push_back(make_int4((int)(q % s->px), (int)((q / s->px) % s->n[1]),
+                                          (int)(q / ((long long)s->px * s->n[1])), it == ext_of.end() ? -1 : it->second));
+                continue;
+            }
+            hc[sk.first] = (uint8_t)en->cls;
             changed = true;
         }
         if (changed) CK(hipMemcpy(s->d_cls, hc.data(), s->nslot, hipMemcpyHostToDevice));
+        (void)hipFree(s->d_mixed);
+        s->d_mixed = nullptr;
+        CK(hipMalloc(&s->d_mixed, std::max<size_t>(1, mixed.size()) * sizeof(int4)));
+        if (!mixed.empty())
+            CK(hipMemcpy(s->d_mixed, mixed.data(), mixed.size() * sizeof(int4), hipMemcpyHostToDevice));
+        s->nmixed = (int)mixed.size();
+        (void)hipFree(s->d_coefx);
+        s->d_coefx = nullptr;
+        const size_t nx3 = std::max<size_t>(1, cdx.size());
+        if (s->prec == MPX_F64) {
+            CK(hipMalloc(&s->d_coefx, nx3 * sizeof(CoefDev<double>)));
+            if (!cdx.empty())
+                CK(hipMemcpy(s->d_coefx, cdx.data(), cdx.size() * sizeof(cdx[0]), hipMemcpyHostToDevice));
+        } else {
+            std::vector<CoefDev<float>> cfx(nx3);
+            memset(cfx.data(), 0, cfx.size() * sizeof(cfx[0]));
+            for (size_t q = 0; q < cdx.size(); q++) {
+                cfx[q].ca = (float)cdx[q].ca;
+                cfx[q].cb = (float)cdx[q].cb;
+                cfx[q].pec = cdx[q].pec;
+            }
+            CK(hipMalloc(&s->d_coefx, nx3 * sizeof(CoefDev<float>)));
+            CK(hipMemcpy(s->d_coefx, cfx.data(), nx3 * sizeof(cfx[0]), hipMemcpyHostToDevice));
+        }
         if (s->prec == MPX_F64) {
             CK(hipMemcpy(s->d_coef, cd.data(), kCoefEntries * sizeof(cd[0]), hipMemcpyHostToDevice));
         } else {
@@ -2236,24 +2281,6 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             }
             CK(hipMemcpy(s->d_coef, cf.data(), kCoefEntries * sizeof(cf[0]), hipMemcpyHostToDevice));
         }
-    }
-    {
-        // the list of mixed slots (count, then fill)
-        int *cnt = nullptr;
-        CK(hipMalloc(&cnt, sizeof(int)));
-        CK(hipMemsetAsync(cnt, 0, sizeof(int), s->stream));
-        CK(launch_list_mixed(s->d_cls, s->n, s->px, cnt, nullptr, s->stream));
-        int nm = 0;
-        CK(hipMemcpyAsync(&nm, cnt, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-        CK(hipStreamSynchronize(s->stream));
-        (void)hipFree(s->d_mixed);
-        s->d_mixed = nullptr;
-        CK(hipMalloc(&s->d_mixed, std::max(1, nm) * sizeof(int4)));
-        CK(hipMemsetAsync(cnt, 0, sizeof(int), s->stream));
-        if (nm > 0) CK(launch_list_mixed(s->d_cls, s->n, s->px, cnt, s->d_mixed, s->stream));
-        CK(hipStreamSynchronize(s->stream));
-        (void)hipFree(cnt);
-        s->nmixed = nm;
     }
     if ((r = update_pass_flags(s)) != MPX_OK) return r;
     std::vector<int4> bt, bte;

@@ -94,6 +94,10 @@ struct KParams {
     T *Hb[3];
     T *psiEb[3][3];
     const CoefDev<T> *coef;
+    // every distinct edge-coefficient triple of the mixed-class slots, three
+    // entries each; a mixed-list entry's w indexes it (-1: none, the
+    // general path from the cell ids)
+    const CoefDev<T> *coefx;
     const uint8_t *id;
     const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
     const uint8_t *pflags; // per separate-pass tile: 1 CPML, 2 source, 4 film within reach
@@ -234,7 +238,6 @@ template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s
 template <typename T>
 hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
                               hipStream_t s);
-hipError_t launch_list_mixed(const uint8_t *cls, const int *n, int px, int *count, int4 *list, hipStream_t s);
 template <typename T>
 hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwork, int nhalf, int inc,
                               hipStream_t s);

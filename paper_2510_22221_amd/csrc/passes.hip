@@ -158,12 +158,11 @@ __device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by,
     epass_tile<T>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 2) != 0);
 }
 
-// the mixed slots, one thread each: the general path (folded loads, edge
-// coefficients from the four cell ids), in place after the E pass
-template <typename T>
-__device__ __forceinline__ void emixed_slot(const KParams<T> &p, int m) {
-    const CoefMem<T> L{p.coef};
-    const int4 s = p.mixed[m];
+// the mixed slots, one thread each: the general path (folded loads; edge
+// coefficients from the slot's entry of the extended table, or else from the
+// four cell ids), in place after the E pass
+template <typename T, bool MIXED>
+__device__ __forceinline__ void emixed_apply(const KParams<T> &p, const CoefMem<T> &L, int4 s, int cls) {
     const int i = s.x, j = s.y, k = s.z;
     const T hx0 = ldz(p, p.H[0], i, j, k), hx_km = ldz(p, p.H[0], i, j, k - 1), hx_ym = ldz(p, p.H[0], i, j - 1, k);
     const T hy0 = ldz(p, p.H[1], i, j, k), hy_km = ldz(p, p.H[1], i, j, k - 1), hy_xm = ldz(p, p.H[1], i - 1, j, k);
@@ -173,15 +172,24 @@ __device__ __forceinline__ void emixed_slot(const KParams<T> &p, int m) {
     const long long step = tsrc ? p.step[0] : 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
     const T e0 = p.E[0][q], e1 = p.E[1][q], e2 = p.E[2][q];
-    const T n0 = e_upd<T, 0, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e0, dif(hz0, hz_ym, dy, iy),
-                                                   dif(hy0, hy_km, dz, iz), tpml, tsrc, step, true);
-    const T n1 = e_upd<T, 1, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e1, dif(hx0, hx_km, dz, iz),
-                                                   dif(hz0, hz_xm, dx, ix), tpml, tsrc, step, true);
-    const T n2 = e_upd<T, 2, true, true, CoefMem<T>>(p, L, i, j, k, kMixed, e2, dif(hy0, hy_xm, dx, ix),
-                                                   dif(hx0, hx_ym, dy, iy), tpml, tsrc, step, true);
+    const T n0 = e_upd<T, 0, true, true, CoefMem<T>, MIXED>(p, L, i, j, k, cls, e0, dif(hz0, hz_ym, dy, iy),
+                                                          dif(hy0, hy_km, dz, iz), tpml, tsrc, step, true);
+    const T n1 = e_upd<T, 1, true, true, CoefMem<T>, MIXED>(p, L, i, j, k, cls, e1, dif(hx0, hx_km, dz, iz),
+                                                          dif(hz0, hz_xm, dx, ix), tpml, tsrc, step, true);
+    const T n2 = e_upd<T, 2, true, true, CoefMem<T>, MIXED>(p, L, i, j, k, cls, e2, dif(hy0, hy_xm, dx, ix),
+                                                          dif(hx0, hx_ym, dy, iy), tpml, tsrc, step, true);
     p.E[0][q] = n0;
     p.E[1][q] = n1;
     p.E[2][q] = n2;
+}
+
+template <typename T>
+__device__ __forceinline__ void emixed_slot(const KParams<T> &p, int m) {
+    const int4 s = p.mixed[m];
+    if (s.w >= 0)
+        emixed_apply<T, false>(p, CoefMem<T>{p.coefx}, s, s.w);
+    else
+        emixed_apply<T, true>(p, CoefMem<T>{p.coef}, s, kMixed);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,22 +369,6 @@ __global__ void __launch_bounds__(PTX *PTY)
     if (inc_step && wk.y == 0 && wk.z == 0 && wk.w == 0 && threadIdx.x == 0 && threadIdx.y == 0)
         p.step[0] = p.step[0] + 1;
     hpass_block<T, NHALF>(p, wk.y, wk.z, wk.w);
-}
-
-// the slots whose class byte says "mixed", in any order (each is updated
-// independently); count only when list is null
-__global__ void __launch_bounds__(256) k_list_mixed(const uint8_t *__restrict__ cls, int nx, int ny, int px,
-                                                     int *count, int4 *list) {
-    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-    if (i >= nx) return;
-    if (cls[(long long)i + (long long)px * ((long long)j + (long long)ny * k)] != kMixed) return;
-    const int m = atomicAdd(count, 1);
-    if (list) list[m] = make_int4(i, j, k, 0);
-}
-
-hipError_t launch_list_mixed(const uint8_t *cls, const int *n, int px, int *count, int4 *list, hipStream_t s) {
-    k_list_mixed<<<dim3((n[0] + 255) / 256, n[1], n[2]), dim3(256), 0, s>>>(cls, n[0], n[1], px, count, list);
-    return hipGetLastError();
 }
 
 int pass_tiles(const int *n) { return ((n[0] + PTX - 1) / PTX) * ((n[1] + PTY - 1) / PTY) * n[2]; }

@@ -228,14 +228,14 @@ __device__ __forceinline__ T e_apply(const KParams<T> &p, const TAB &L, const in
 // the whole E update of one edge (load psi, apply, store psi).
 // PSI_INPLACE: the E-type psi live in one buffer (separate-pass schedule);
 // `own`: this thread owns the edge and writes its psi.
-template <typename T, int C, bool WALL, bool PSI_INPLACE = false, class TAB = CoefLds<T>>
+template <typename T, int C, bool WALL, bool PSI_INPLACE = false, class TAB = CoefLds<T>, bool MIXED = true>
 __device__ __forceinline__ T e_upd(const KParams<T> &p, const TAB &L, int gi, int gj, int gk, int cls,
                                    T eold, T d1, T d2, bool tpml, bool tsrc, long long step, bool own) {
     int idx[3];
     if (!e_site<T, C, WALL>(p, gi, gj, gk, idx)) return T(0);
     Psi2<T> r;
     if (tpml) r = psi_load<T, C, true>(p, idx);
-    const T e = e_apply<T, C>(p, L, idx, cls, eold, d1, d2, r, tsrc, step);
+    const T e = e_apply<T, C, TAB, MIXED>(p, L, idx, cls, eold, d1, d2, r, tsrc, step);
     if (own) psi_store<T, C>(PSI_INPLACE ? p.psiE[C] : p.psiEb[C], r);
     return e;
 }

@@ -8,6 +8,7 @@ import numpy as np
 
 import oracle.oracle as O
 from paper_2510_22221_amd import mpx
+from synth import workloads as W
 
 GROUPS = {"E": (0, 1, 2), "H": (3, 4, 5), "dM": (9, 10, 11)}
 
@@ -59,3 +60,18 @@ def run_pair(w, nsteps, precision=mpx.F64, graph_steps=None, threads=None, chunk
         done += n
     g.sync()
     return g, o
+
+
+def many_materials_case(nsteps):
+    """150 lossy dielectrics and one PEC id on random cells: far more distinct
+    triples of edge coefficients than free class ids, so the most frequent
+    triples get compound classes (the table path) and the remaining mixed
+    slots go through the mixed-slot kernel with their triple's entry of the
+    extended table."""
+    w = W.random_case(8, nx=40, ny=17, nz=13, bc=(W.PML,) * 6, npml=(3,) * 6, film=False, nsteps=nsteps)
+    rng = np.random.default_rng(8)
+    mats = [(float(rng.uniform(1.0, 12.0)), float(rng.uniform(0.0, 5e3)), 0, 0.0, 0.0, 0.0) for _ in range(150)]
+    mats[7] = W.PEC_METAL
+    w.materials = mats
+    w.ids = rng.integers(0, 150, size=(w.nz, w.ny, w.nx)).astype(np.uint8)
+    return w

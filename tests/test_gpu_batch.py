@@ -13,6 +13,7 @@ import pytest
 
 from paper_2510_22221_amd import mpx
 from synth import workloads as W
+from tests.parity import many_materials_case
 
 pytestmark = pytest.mark.gpu
 CALLS = (7, 12, 1, 5)
@@ -106,3 +107,32 @@ def test_batch_rejects_bad_members():
         mpx.Batch([a, a])
     with pytest.raises(mpx.MpxError):
         mpx.Batch([])
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+def test_batch_member_with_mixed_slots(prec):
+    """A member whose mixed slots overflow the class table (150 materials:
+    extended-table and cell-id entries in its mixed list) beside one without
+    any: the batched mixed-slot kernel gives the single-run bits."""
+    nsteps = sum(CALLS) + 2
+    ws = [many_materials_case(nsteps), W.c3_instance(64, 48, 40, 1.0, nsteps)]
+    ref = []
+    for w in ws:
+        s = mpx.from_workload(w, precision=prec, graph_steps=4)
+        for n in CALLS:
+            s.step(n)
+        s.sync()
+        ref.append(state(s, w))
+        s.close()
+    sims = [mpx.from_workload(w, precision=prec) for w in ws]
+    b = mpx.Batch(sims)
+    b.set_graph_steps(4)
+    for n in CALLS:
+        b.step(n)
+    b.sync()
+    for q, (s, w) in enumerate(zip(sims, ws)):
+        for k, (a, r) in enumerate(zip(state(s, w), ref[q])):
+            assert np.array_equal(a, r), (q, k)
+    b.close()
+    for s in sims:
+        s.close()

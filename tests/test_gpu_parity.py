@@ -13,7 +13,7 @@ import pytest
 import oracle.oracle as O
 from paper_2510_22221_amd import mpx
 from synth import workloads as W
-from tests.parity import group_errors, probe_errors, rel, run_pair
+from tests.parity import group_errors, many_materials_case, probe_errors, rel, run_pair
 from tests.spectral import tone_frequency
 
 pytestmark = pytest.mark.gpu
@@ -222,20 +222,6 @@ def test_nonfinite_watchdog():
 
 
 # ------------------------------------------------------------------ schedules
-def many_materials_case(nsteps):
-    """150 lossy dielectrics and one PEC id on random cells: far more distinct
-    triples of edge coefficients than free class ids, so the first triples
-    met get compound classes (the table path) and the remaining mixed slots
-    keep the general path."""
-    w = W.random_case(8, nx=40, ny=17, nz=13, bc=(W.PML,) * 6, npml=(3,) * 6, film=False, nsteps=nsteps)
-    rng = np.random.default_rng(8)
-    mats = [(float(rng.uniform(1.0, 12.0)), float(rng.uniform(0.0, 5e3)), 0, 0.0, 0.0, 0.0) for _ in range(150)]
-    mats[7] = W.PEC_METAL
-    w.materials = mats
-    w.ids = rng.integers(0, 150, size=(w.nz, w.ny, w.nx)).astype(np.uint8)
-    return w
-
-
 @pytest.mark.parametrize("prec,tol", [(mpx.F64, F64_TOL), (mpx.F32, F32_TOL)])
 def test_many_materials_matches_oracle(prec, tol):
     w = many_materials_case(40)
