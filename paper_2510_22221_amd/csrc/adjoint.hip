@@ -1056,35 +1056,58 @@ __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, l
     l2 = le[2];
 }
 
-// the nine face values a slot's half-step pass reads, in a tile near a CPML
-// slab (FILM = 0) or a film's reach (FILM = 1)
+// the six differences of the transposed curl a slot's half-step pass adds to
+// its lambda E, in a tile near a CPML slab (FILM = 0) or a film's reach
+// (FILM = 1): d = {d0a, d0b, d1a, d1b, d2a, d2b}, lambda E_C gaining
+// dCa + dCb.  Each own face's two curl-part adjoints are paired with their
+// neighbours' as soon as those are known, so few values are live at once.
 template <typename T, int FILM>
-__device__ __forceinline__ void hfield_general(const AdjParams<T> &A, const int *t, T *o0, T *o1, T &n1m2, T &n2m1,
-                                               T &n2m0, T &n0m2, T &n0m1, T &n1m0) {
+__device__ __forceinline__ void hfield_general(const AdjParams<T> &A, const int *t, T *d) {
     const KParams<T> &p = A.p;
-    hface<T, 0, FILM>(A, t, true, o0[0], o1[0]);
-    hface<T, 1, FILM>(A, t, true, o0[1], o1[1]);
-    hface<T, 2, FILM>(A, t, true, o0[2], o1[2]);
-    T x0, x1;
+    T a, b, x0, x1, n;
     int u[3];
+    // own face of family 1: with the family-1 faces at k - 1 and i - 1
+    hface<T, 1, FILM>(A, t, true, a, b);
+    n = T(0);
     if (nb<-1>(p.n, p.per, t, 2, u)) {
         hface<T, 1, FILM>(A, u, false, x0, x1);
-        n1m2 = x0;
-        hface<T, 0, FILM>(A, u, false, x0, x1);
-        n0m2 = x1;
+        n = x0;
     }
+    d[0] = dif(n - a, T(0), p.dT[2], p.invd[2]);
+    n = T(0);
+    if (nb<-1>(p.n, p.per, t, 0, u)) {
+        hface<T, 1, FILM>(A, u, false, x0, x1);
+        n = x1;
+    }
+    d[5] = dif(n - b, T(0), p.dT[0], p.invd[0]);
+    // family 2: with the family-2 faces at j - 1 and i - 1
+    hface<T, 2, FILM>(A, t, true, a, b);
+    n = T(0);
     if (nb<-1>(p.n, p.per, t, 1, u)) {
         hface<T, 2, FILM>(A, u, false, x0, x1);
-        n2m1 = x1;
-        hface<T, 0, FILM>(A, u, false, x0, x1);
-        n0m1 = x0;
+        n = x1;
     }
+    d[1] = dif(n - b, T(0), p.dT[1], p.invd[1]);
+    n = T(0);
     if (nb<-1>(p.n, p.per, t, 0, u)) {
         hface<T, 2, FILM>(A, u, false, x0, x1);
-        n2m0 = x0;
-        hface<T, 1, FILM>(A, u, false, x0, x1);
-        n1m0 = x1;
+        n = x0;
     }
+    d[2] = dif(n - a, T(0), p.dT[0], p.invd[0]);
+    // family 0: with the family-0 faces at k - 1 and j - 1
+    hface<T, 0, FILM>(A, t, true, a, b);
+    n = T(0);
+    if (nb<-1>(p.n, p.per, t, 2, u)) {
+        hface<T, 0, FILM>(A, u, false, x0, x1);
+        n = x1;
+    }
+    d[3] = dif(n - b, T(0), p.dT[2], p.invd[2]);
+    n = T(0);
+    if (nb<-1>(p.n, p.per, t, 1, u)) {
+        hface<T, 0, FILM>(A, u, false, x0, x1);
+        n = x0;
+    }
+    d[4] = dif(n - a, T(0), p.dT[1], p.invd[1]);
 }
 
 // the transposed half step on the E side: lambda E_C += the transposed curl
@@ -1097,12 +1120,14 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
     const int t[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
     const uint8_t fl = A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)];
-    // own faces: aD0, aD1 of each family; neighbours, named by family and the
-    // axis of the -1 offset
-    T o0[3], o1[3];
-    T n1m2 = T(0), n2m1 = T(0), n2m0 = T(0), n0m2 = T(0), n0m1 = T(0), n1m0 = T(0);
-    int u[3];
+    // dd: the transposed curl's six differences (see hfield_general)
+    T dd[6];
     if (fl == 0) {
+        // own faces: aD0, aD1 of each family; neighbours, named by family
+        // and the axis of the -1 offset
+        T o0[3], o1[3];
+        T n1m2 = T(0), n2m1 = T(0), n2m0 = T(0), n0m2 = T(0), n0m1 = T(0), n1m0 = T(0);
+        int u[3];
 #pragma unroll
         for (int F = 0; F < 3; F++) {
             const T l = A.lH[F][q];
@@ -1115,10 +1140,16 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
         if (nb<-1>(p.n, p.per, t, 2, u)) n0m2 = p.hc * A.lH[0][p.slot(u[0], u[1], u[2])];
         if (nb<-1>(p.n, p.per, t, 1, u)) n0m1 = -(p.hc * A.lH[0][p.slot(u[0], u[1], u[2])]);
         if (nb<-1>(p.n, p.per, t, 0, u)) n1m0 = p.hc * A.lH[1][p.slot(u[0], u[1], u[2])];
+        dd[0] = dif(n1m2 - o0[1], T(0), p.dT[2], p.invd[2]);
+        dd[1] = dif(n2m1 - o1[2], T(0), p.dT[1], p.invd[1]);
+        dd[2] = dif(n2m0 - o0[2], T(0), p.dT[0], p.invd[0]);
+        dd[3] = dif(n0m2 - o1[0], T(0), p.dT[2], p.invd[2]);
+        dd[4] = dif(n0m1 - o0[0], T(0), p.dT[1], p.invd[1]);
+        dd[5] = dif(n1m0 - o1[1], T(0), p.dT[0], p.invd[0]);
     } else if (fl & 4) {
-        hfield_general<T, 1>(A, t, o0, o1, n1m2, n2m1, n2m0, n0m2, n0m1, n1m0);
+        hfield_general<T, 1>(A, t, dd);
     } else {
-        hfield_general<T, 0>(A, t, o0, o1, n1m2, n2m1, n2m0, n0m2, n0m1, n1m0);
+        hfield_general<T, 0>(A, t, dd);
     }
     T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
     if (SCALE && A.btape) {
@@ -1144,9 +1175,9 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
         l1 = v1 ? ca1 * l1 : T(0);
         l2 = v2 ? ca2 * l2 : T(0);
     }
-    l0 = l0 + (dif(n1m2 - o0[1], T(0), p.dT[2], p.invd[2]) + dif(n2m1 - o1[2], T(0), p.dT[1], p.invd[1]));
-    l1 = l1 + (dif(n2m0 - o0[2], T(0), p.dT[0], p.invd[0]) + dif(n0m2 - o1[0], T(0), p.dT[2], p.invd[2]));
-    l2 = l2 + (dif(n0m1 - o0[0], T(0), p.dT[1], p.invd[1]) + dif(n1m0 - o1[1], T(0), p.dT[0], p.invd[0]));
+    l0 = l0 + (dd[0] + dd[1]);
+    l1 = l1 + (dd[2] + dd[3]);
+    l2 = l2 + (dd[4] + dd[5]);
     if (SCALE && A.ltape && (fl & 4) && A.seg0[0] + A.m > A.loss_from)
         loss_term(A, t, q, l0, l1, l2);
     if (SCALE && A.pw && q == A.pw_slot) {
