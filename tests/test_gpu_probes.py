@@ -56,6 +56,31 @@ def test_em_energy_probe_equals_mpx_energy():
         assert tr[-1] == pytest.approx(g.energy()[0], rel=1e-13)
 
 
+def test_em_energy_probe_periodic_box():
+    """Periodic x and y (the energy sums wrap), PEC z, random media and a
+    film: the probe after each step against the oracle's energy, and
+    mpx_energy at the end."""
+    n = 30
+    w = W.random_case(34, nx=20, ny=16, nz=12, bc=(W.PERIODIC, W.PERIODIC, W.PERIODIC, W.PERIODIC, W.PEC, W.PEC),
+                      nsteps=n)
+    w.probes = []
+    g = mpx.from_workload(w, precision=mpx.F64)
+    pid = g.add_probe(mpx.PROBE_EM_ENERGY, cap=n, every=2)
+    g.step(n)
+    tr = g.read_probe(pid, 1).ravel()
+    o = O.from_workload(w)
+    ref = []
+    for _ in range(n // 2):
+        o.step(2)
+        ref.append(o.energy()[0])
+    ref = np.array(ref)
+    assert tr.shape == ref.shape
+    err = np.max(np.abs(tr - ref)) / np.max(np.abs(ref))
+    say(f"periodic box: max |probe - oracle| / max W = {err:.2e}")
+    assert err <= 1e-12
+    assert g.energy()[0] == pytest.approx(o.energy()[0], rel=1e-12)
+
+
 def stride_case(nsteps):
     w = W.random_case(31, nx=24, ny=18, nz=16, bc=(W.PEC,) * 6, npml=(0,) * 6, nsteps=nsteps)
     w.H0 = (3e6, 0.0, 5e6)
