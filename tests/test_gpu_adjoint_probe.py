@@ -88,6 +88,45 @@ def test_trace_adjoint_matches_oracle_finite_differences(pml, field):
         assert close(a, b, sc), (a, b)
 
 
+def test_trace_adjoint_periodic_box():
+    """Periodic x, PEC y, CPML z, a film: the weighted E_z trace at an edge
+    one cell from the periodic seam; dL/dH0 and dL/deps_r of cells that
+    straddle the seam against the oracle's differences."""
+    w = W.random_case(6, nx=29, ny=17, nz=23, bc=(W.PERIODIC, W.PERIODIC, W.PEC, W.PEC, W.PML, W.PML),
+                      npml=(0, 0, 0, 0, 4, 4), nsteps=40)
+    w.H0 = (2e6, 1e6, 4e6)
+    n, K = 40, 6
+    kf, jf, i_f, kz0 = film_geometry(w)
+    ijk = (1, jf, kz0 - 1)
+    wt = np.random.default_rng(13).standard_normal(n)
+    eb = (27, jf - 1, kz0 - 3, 2, 2, 2)  # x cells 27, 28: the seam is at 0
+    g = mpx.from_workload(w, precision=mpx.F64)
+    res = g.adjoint_probe(n, 2, ijk, wt, checkpoint_every=K, eps_box=eb)
+    g.close()
+
+    def lossf(w2):
+        return fd.trace_loss(w2, n, 2, ijk, wt)
+
+    assert res["loss"] == pytest.approx(lossf(w), rel=1e-11)
+    gh = [fd.grad_H0_of(lossf, w, c) for c in range(3)]
+    say(f"periodic: dL/dH0 adjoint {res['dH0']} fd {gh}")
+    sc = max(abs(v) for v in gh)
+    assert sc > 0
+    for c in range(3):
+        assert close(res["dH0"][c], gh[c], sc), (c, res["dH0"][c], gh[c])
+    ge = []
+    for (di, dj, dk) in ((1, 0, 0), (0, 1, 1), (1, 1, 0)):
+        cell = (eb[0] + di, eb[1] + dj, eb[2] + dk)
+        if w.materials[int(w.ids[cell[2], cell[1], cell[0]])][2]:
+            continue
+        ge.append((res["deps"][dk, dj, di], fd.grad_eps_of(lossf, w, cell)))
+    say(f"periodic: dL/deps (adjoint, fd) {ge}")
+    sc = max(abs(b) for _, b in ge)
+    assert sc > 0
+    for a, b in ge:
+        assert close(a, b, sc), (a, b)
+
+
 def test_trace_adjoint_without_films():
     """No magnetic cell: the bias enters nothing, so dL/dH0 is exactly zero,
     and dL/deps_r still matches the oracle's differences."""
