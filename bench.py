@@ -3,16 +3,17 @@
 
 One bench "step" is one full time step of the hot path over the workload
 (H/M half step, E step with CPML and source, H/M half step, probes), so a
-run of K steps advances the simulation K time steps.  The workload is the
-single on-chip resonator: 512 x 256 x 128 cells, silicon substrate, PEC CPW
-strips, a 400 x 60 x 4-cell film, PML 10 on every face (synthetic, seeded).
+run of K steps advances the simulation K time steps.  The headline workload
+is the large single-GPU layout: 1536 x 768 x 384 cells (453 M), eight PEC
+strips each carrying a 200 x 40 x 4-cell film, random eps_r blocks, PML 16 on
+every face (synthetic, seeded), in float32.
 
-Prints one JSON line: Gcell-updates/s in float32 (float64 in "secondary"),
-the roofline of the dominant kernel measured with HIP events on the
-library's stream over the timed region, the batched bias sweep against
-sequential runs, the adjoint's cost against the forward run on the
-128 x 64 x 64 resonator, and the float64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line: Gcell-updates/s of the headline workload, the roofline
+of its dominant kernel (per-launch durations from HIP events on the
+library's stream), the 512 x 256 x 128 single resonator in float32 and
+float64 ("secondary"), the batched bias sweep against sequential runs, the
+adjoint's cost against the forward run on the 128 x 64 x 64 resonator, and
+the float64 CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -61,15 +62,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, dtype):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
-    were taken on the current kernel source; else None."""
+def traffic_from_profiles(kernel, dtype, wkey):
+    """HBM bytes per launch of a kernel on workload `wkey` (c2, c5) from the
+    committed rocprofv3 PMC summaries, if they were taken on the current
+    kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         data = json.load(open(p))
-        ent = data.get(f"{kernel}:{dtype}")
+        ent = data.get(f"{wkey}:{kernel}:{dtype}")
         if ent and ent.get("source_hash") == kernel_source_hash():
             return ent["bytes_per_launch"]
     except Exception:
@@ -77,33 +79,44 @@ def traffic_from_profiles(kernel, dtype):
     return None
 
 
-def run_gpu(w, precision, steps, warmup, every, schedule=0):
+def run_gpu(w, precision, steps, warmup, timing_steps=12, schedule=0):
+    """Steps `w` on the GPU: `warmup` untimed steps, one untimed call that
+    captures the HIP graph of the step batch the timed call replays, then
+    `steps` steps timed by the host clock between two device synchronisations
+    (graph replays, no per-step events), then a separate short pass of
+    `timing_steps` steps with every kernel group bracketed by HIP events on
+    the library's stream (direct launches) for the per-launch durations."""
     import torch
     from paper_2510_22221_amd import mpx
 
     stream = torch.cuda.current_stream()
     t0 = time.time()
     sim = mpx.from_workload(w, precision=precision, stream=stream, fused=schedule)
+    # an even batch the timed call replays at least once
+    G = max(2, min(64, (steps - 1) // 2 * 2))
+    sim.set_graph_steps(G)
     sim.step(1)
     sim.sync()
-    log(f"  setup {time.time() - t0:.1f} s")
+    log(f"  setup {time.time() - t0:.1f} s, graph batch {G} steps")
     if warmup > 1:
         sim.step(warmup - 1)
+    sim.step(G + 1)  # captures the graph for the parity the timed call starts at
     sim.sync()
-    torch.cuda.synchronize()
-    sim.set_timing(every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     sim.sync()
     wall = time.perf_counter() - t0
+    sim.set_timing(1)
+    sim.step(timing_steps)
+    sim.sync()
     kt = sim.kernel_time()
     sim.set_timing(0)
     return sim, wall, kt
 
 
-def roofline_for(w, esz, kt, dtype_name, schedule=0):
+def roofline_for(w, esz, kt, dtype_name, schedule=0, wkey="c5"):
     fused = schedule != 0
     ab = algorithmic_bytes(w, esz)
     if fused:
@@ -115,7 +128,7 @@ def roofline_for(w, esz, kt, dtype_name, schedule=0):
     achieved = ab[name] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-           "traffic": traffic_from_profiles(name, dtype_name),
+           "traffic": traffic_from_profiles(name, dtype_name, wkey),
            "algorithmic_bytes_per_launch": ab[name], "avg_launch_ms": round(ms, 5), "launches_timed": nl,
            "film_half1_and_probe_ms_per_step": round(kt[2][0], 5)}
     if not fused:
@@ -126,17 +139,18 @@ def roofline_for(w, esz, kt, dtype_name, schedule=0):
     return out
 
 
-def batched_sweep(steps, n_inst, variant=None, kchunk=None):
+def batched_sweep(steps, n_inst, tune_steps=20):
     """The bias sweep: n_inst resonator + film instances of uneven size,
-    float32, stepped one after another (each with its own captured graphs)
-    and then as one batch (one launch per pass over all instances).
-    Both runs start from the same state and the batch's results are bitwise
-    those of the single runs (checked in the GPU tests); returns the
-    throughput of both."""
-    from paper_2510_22221_amd import mpx
+    float32, stepped one after another (each with its own captured graphs),
+    then as one batch (one launch per pass over all instances) with the
+    default schedule, and as one batch with the schedule the autotuner picks
+    for it (every candidate timed on scratch copies of the same instances).
+    All runs give the single runs' bits (checked in the GPU tests); returns
+    the throughput of each."""
+    from paper_2510_22221_amd import mpx, tune
     from synth import workloads as W
 
-    ws = W.c3(nsteps=2 * steps + 40, n=n_inst)
+    ws = W.c3(nsteps=3 * steps + 60, n=n_inst)
     cells = sum(w.ncells for w in ws)
     t0 = time.time()
     sims = [mpx.from_workload(w, precision=mpx.F32) for w in ws]
@@ -150,23 +164,35 @@ def batched_sweep(steps, n_inst, variant=None, kchunk=None):
         s.step(steps)
         s.sync()
     seq = time.perf_counter() - t0
-    b = mpx.Batch(sims)
-    if variant:
-        b.set_schedule(variant, kchunk or 0)
-    b.step(4)
-    b.sync()
-    t0 = time.perf_counter()
-    b.step(steps)
-    b.sync()
-    bat = time.perf_counter() - t0
-    b.close()
+
+    def timed_batch(variant, kchunk):
+        b = mpx.Batch(sims)
+        b.set_schedule(variant, kchunk)
+        b.step(4)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        el = time.perf_counter() - t0
+        b.close()
+        return el
+
+    bat = timed_batch(0, 0)
+    t0 = time.time()
+    v, kc, _ = tune.tune_batch(ws, precision=mpx.F32, steps=tune_steps, cache=None)
+    log(f"  autotuner: variant {v}, z-chunk {kc} ({time.time() - t0:.1f} s)")
+    tuned = timed_batch(v, kc)
     for s in sims:
         s.close()
+    rate = lambda el: round(cells * steps / el / 1e9, 3)
     return {"instances": n_inst, "cells": cells, "steps": steps, "dtype": "f32",
-            "sequential_Gcell_s": round(cells * steps / seq / 1e9, 3),
-            "batched_Gcell_s": round(cells * steps / bat / 1e9, 3),
+            "sequential_Gcell_s": rate(seq),
+            "batched_Gcell_s": rate(bat),
             "batched_over_sequential": round(seq / bat, 3),
-            "schedule": ("separate E and H/M passes" if not variant else f"fused pass, variant {variant}")}
+            "schedule": "separate E and H/M passes (64 x 4 tiles)",
+            "tuned": {"variant": v, "kchunk": kc,
+                      "schedule": ("separate E and H/M passes" if v == 0 else f"fused pass, variant {v}"),
+                      "batched_Gcell_s": rate(tuned), "batched_over_sequential": round(seq / tuned, 3)}}
 
 
 def adjoint_cost(steps, window, graphs=True):
@@ -205,36 +231,75 @@ def adjoint_cost(steps, window, graphs=True):
     return out
 
 
-def cpu_baseline(w, nsteps):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(O, w, seconds):
+    """Steps the oracle one step at a time until `seconds` have passed;
+    returns (steps, elapsed), setup excluded."""
+    s = O.from_workload(w)
+    s.step(1)  # first touch of every array
+    n, t0 = 0, time.perf_counter()
+    while True:
+        s.step(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return n, dt
+
+
+def cpu_baseline(w_full, seconds=10.0):
+    """The float64 CPU oracle on a bounded sample of the headline workload:
+    a 384 x 384 x 192 crop of the 1536 x 768 x 384 layout around its first
+    resonator (its film, strip, source, PML 16 and random eps_r blocks), timed
+    with all the host threads it may use and with one thread."""
     import oracle.oracle as O
+    from synth import workloads as W
+
     O.build()
+    w = W.crop(w_full, (0, 0, 96), (384, 384, 192))
     O.set_threads(min(os.cpu_count() or 1, 64))
     threads = O.get_threads()
-    t0 = time.time()
-    s = O.from_workload(w)
-    log(f"  oracle setup {time.time() - t0:.1f} s, {threads} threads")
-    t0 = time.perf_counter()
-    s.step(nsteps)
-    dt = time.perf_counter() - t0
-    return {"value": round(w.ncells * nsteps / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{w.nx}x{w.ny}x{w.nz} resonator, {nsteps} of its time steps, float64, setup excluded, "
-                      f"{dt:.1f} s"}
+    n, dt = _time_oracle(O, w, seconds)
+    log(f"  oracle {threads} threads: {n} steps in {dt:.1f} s")
+    O.set_threads(1)
+    n1, dt1 = _time_oracle(O, w, seconds)
+    log(f"  oracle 1 thread: {n1} steps in {dt1:.1f} s")
+    O.set_threads(threads)
+    sample = (f"{w.nx}x{w.ny}x{w.nz} crop (origin 0,0,96) of the {w_full.nx}x{w_full.ny}x{w_full.nz} layout, "
+              f"float64, setup excluded")
+    return {"value": round(w.ncells * n / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": threads,
+            "kind": "oracle", "sample": f"{sample}: {n} steps in {dt:.1f} s",
+            "single_core": {"value": round(w.ncells * n1 / dt1 / 1e9, 5), "cores": 1,
+                            "sample": f"{sample}: {n1} steps in {dt1:.1f} s"},
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
+
+
+def stencil_line(w, precision, dtype_name, esz, steps, warmup, sched, wkey):
+    from paper_2510_22221_amd import mpx
+    sim, wall, kt = run_gpu(w, precision, steps, warmup, schedule=sched)
+    sim.close()
+    return {"dtype": dtype_name, "value": round(w.ncells * steps / wall / 1e9, 3), "unit": "Gcell-updates/s",
+            "steps": steps, "ms_per_step": round(wall / steps * 1e3, 5),
+            "roofline": roofline_for(w, esz, kt, dtype_name, sched, wkey)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--f64-steps", type=int, default=4000)
-    ap.add_argument("--cpu-steps", type=int, default=12)
-    ap.add_argument("--timing-every", type=int, default=0, help="event-time every n-th step (0: auto)")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--c2-steps", type=int, default=4000, help="steps of the 512x256x128 lines (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
-    ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--nz", type=int, default=128)
     ap.add_argument("--schedule", type=int, default=0,
                     help="0: separate E and H/M passes (default); 1-5: fused pass variants")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
@@ -245,20 +310,20 @@ def main():
                     help="launch the adjoint's kernels directly (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by z-slabs "
-              "across GPUs by design; only the one-GPU path is implemented)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would shard by "
+              "z-slabs across GPUs; only the one-GPU path is built)", file=sys.stderr)
         sys.exit(2)
     from synth import workloads as W
     from paper_2510_22221_amd import mpx
 
-    w = W.c2(max(args.steps, args.f64_steps) + args.warmup + 2, nx=args.nx, ny=args.ny, nz=args.nz)
-    every = args.timing_every or max(1, args.steps // 2000)
-    log(f"workload {w.name}: {w.ncells} cells, FP32 {args.steps} steps (+{args.warmup} warmup)")
     sched = args.schedule
-    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, every, sched)
+    w = W.c5(args.steps + args.warmup + 160)
+    log(f"workload {w.name}: {w.ncells} cells, FP32 {args.steps} steps (+{args.warmup} warmup)")
+    sim, wall, kt = run_gpu(w, mpx.F32, args.steps, args.warmup, schedule=sched)
+    sim.close()
     del sim
     value = w.ncells * args.steps / wall / 1e9
-    roof = roofline_for(w, 4, kt, "f32", sched)
+    roof = roofline_for(w, 4, kt, "f32", sched, "c5")
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -272,21 +337,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"single on-chip CPW resonator + film, {w.nx}x{w.ny}x{w.nz} cells, "
-                               f"d=(45,2,2) um, PML 10, source + probes, one time step per bench step",
+        "config": {"workload": f"large single-GPU multi-resonator layout, {w.nx}x{w.ny}x{w.nz} cells, "
+                               f"d=2 um, 8 PEC strips each with a 200x40x4 film, random eps_r in [1,12] per "
+                               f"32^3 block, PML 16, source + 8 mean-M probes, one time step per bench step",
                    "cells": w.ncells, "precision": "f32 fields, f64 magnetisation",
                    "schedule": ("separate E and H/M passes" if sched == 0 else f"fused pass, variant {sched}"),
+                   "timing": "host clock around graph replays; kernel durations from a separate "
+                             "event-timed pass of 12 steps",
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
-    if not args.no_f64:
-        log(f"FP64 {args.f64_steps} steps")
-        sim, wall64, kt64 = run_gpu(w, mpx.F64, args.f64_steps, args.warmup, max(1, args.f64_steps // 2000), sched)
-        del sim
-        out["secondary"] = [{"dtype": "f64", "value": round(w.ncells * args.f64_steps / wall64 / 1e9, 3),
-                             "unit": "Gcell-updates/s", "steps": args.f64_steps,
-                             "ms_per_step": round(wall64 / args.f64_steps * 1e3, 5),
-                             "roofline": roofline_for(w, 8, kt64, "f64", sched)}]
+    sec = []
+    if args.c2_steps > 0:
+        w2 = W.c2(args.c2_steps + args.warmup + 160)
+        log(f"workload {w2.name}: FP32 {args.c2_steps} steps")
+        ent = stencil_line(w2, mpx.F32, "f32", 4, args.c2_steps, args.warmup, sched, "c2")
+        ent["workload"] = f"single CPW resonator + film, {w2.nx}x{w2.ny}x{w2.nz} cells, PML 10"
+        sec.append(ent)
+        if not args.no_f64:
+            log(f"workload {w2.name}: FP64 {args.c2_steps} steps")
+            ent = stencil_line(w2, mpx.F64, "f64", 8, args.c2_steps, args.warmup, sched, "c2")
+            ent["workload"] = f"single CPW resonator + film, {w2.nx}x{w2.ny}x{w2.nz} cells, PML 10"
+            sec.append(ent)
+    if sec:
+        out["secondary"] = sec
     if args.sweep_steps > 0:
         log(f"batched bias sweep: {args.sweep_instances} instances, {args.sweep_steps} steps")
         out["batched_sweep"] = batched_sweep(args.sweep_steps, args.sweep_instances)
@@ -295,8 +369,8 @@ def main():
         out["adjoint"] = adjoint_cost(args.adjoint_steps, min(args.adjoint_window, args.adjoint_steps),
                                       graphs=not args.adjoint_no_graphs)
     if not args.no_cpu:
-        log(f"CPU oracle baseline: {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        log(f"CPU oracle baseline: about {args.cpu_seconds} s per thread setting")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

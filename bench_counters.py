@@ -5,16 +5,17 @@ Two steps (the counters need rocprofv3 as the outer process):
 
   1. run, once per counter (one counter block per run):
        rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_fetch> -o pmc -- \
-           python3 bench_counters.py --run [--dtype f32|f64] [--steps N]
+           python3 bench_counters.py --run [--workload c2|c5] [--dtype f32|f64] [--steps N]
        rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_write> -o pmc -- \
-           python3 bench_counters.py --run [--dtype f32|f64] [--steps N]
-     The program runs N time steps of the resonator workload (schedule
+           python3 bench_counters.py --run [--workload c2|c5] [--dtype f32|f64] [--steps N]
+     The program runs N time steps of the workload (c2: the 512 x 256 x 128
+     resonator, c5: the 1536 x 768 x 384 multi-resonator layout; schedule
      --fused, default 0: the separate E and H/M passes) and, after them, a
      plain elementwise kernel (b = a * 2 over 1 GiB of
      float32: reads 1 GiB, writes 1 GiB) whose true traffic is known.
 
   2. parse:
-       python3 bench_counters.py --parse <dir_fetch> <dir_write> [--dtype f32]
+       python3 bench_counters.py --parse <dir_fetch> <dir_write> [--workload c2|c5] [--dtype f32]
      FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  Each is scaled by
      (known bytes / what the same counter reads for the calibration kernel), and
      the per-launch HBM bytes of each stencil kernel found are written to
@@ -37,12 +38,16 @@ sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 30
 
 
-def run(dtype: str, steps: int, nx: int, ny: int, nz: int, fused: int = 0):
+def workload(name: str, nsteps: int):
+    from synth import workloads as W
+    return W.c5(nsteps) if name == "c5" else W.c2(nsteps)
+
+
+def run(dtype: str, steps: int, wname: str, fused: int = 0):
     import torch
     from paper_2510_22221_amd import mpx
-    from synth import workloads as W
 
-    w = W.c2(steps + 4, nx=nx, ny=ny, nz=nz)
+    w = workload(wname, steps + 4)
     prec = mpx.F32 if dtype == "f32" else mpx.F64
     stream = torch.cuda.current_stream()
     sim = mpx.from_workload(w, precision=prec, stream=stream, graph_steps=0, fused=fused)
@@ -89,10 +94,8 @@ KERNELS = {"e_pass": lambda k: "k_epass<" in k and "batch" not in k,
            "fused": lambda k: ("k_sweep<" in k or "k_fused<" in k) and "batch" not in k}
 
 
-def parse(dfetch, dwrite, dtype):
+def parse(dfetch, dwrite, dtype, wname):
     import bench
-
-    from synth import workloads as W
 
     cf, cw = read_counters(dfetch), read_counters(dwrite)
     # calibration: b = a * 2 over 1 GiB reads 1 GiB and writes 1 GiB
@@ -101,7 +104,7 @@ def parse(dfetch, dwrite, dtype):
         kib, n = pick(c, lambda k: "elementwise" in k and "Mul" in k)
         cal[label] = {"calibration_kib_per_dispatch": kib, "calibration_dispatches": n,
                       "scale": (COPY_BYTES / 1024.0) / kib}
-    w = W.c2(10)
+    w = workload(wname, 10)
     esz = 4 if dtype == "f32" else 8
     alg = bench.algorithmic_bytes(w, esz)
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -115,11 +118,11 @@ def parse(dfetch, dwrite, dtype):
             res[label] = {"kib_per_dispatch": kib, "dispatches": n, "scale": cal[label]["scale"],
                           "bytes_per_launch": kib * 1024.0 * cal[label]["scale"]}
         total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
-        data[f"{name}:{dtype}"] = {"source_hash": bench.kernel_source_hash(), "bytes_per_launch": round(total),
+        data[f"{wname}:{name}:{dtype}"] = {"workload": w.name, "source_hash": bench.kernel_source_hash(), "bytes_per_launch": round(total),
                                    "algorithmic_bytes_per_launch": alg[name],
                                    "ratio_to_algorithmic": round(total / alg[name], 4),
                                    "counters": res, "calibration": cal}
-        print(name, json.dumps(data[f"{name}:{dtype}"], indent=1))
+        print(name, json.dumps(data[f"{wname}:{name}:{dtype}"], indent=1))
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
 
@@ -130,15 +133,13 @@ def main():
     ap.add_argument("--parse", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
     ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--nz", type=int, default=128)
+    ap.add_argument("--workload", default="c5", choices=("c2", "c5"))
     ap.add_argument("--fused", type=int, default=0, help="0: separate E and H/M passes; 1-5: fused variants")
     args = ap.parse_args()
     if args.run:
-        run(args.dtype, args.steps, args.nx, args.ny, args.nz, args.fused)
+        run(args.dtype, args.steps, args.workload, args.fused)
     elif args.parse:
-        parse(args.parse[0], args.parse[1], args.dtype)
+        parse(args.parse[0], args.parse[1], args.dtype, args.workload)
     else:
         ap.error("--run or --parse")
 

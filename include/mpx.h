@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MPX_ABI_VERSION 2u
+#define MPX_ABI_VERSION 3u
 
 typedef struct mpx_sim mpx_sim;
 
@@ -139,8 +139,10 @@ uint32_t mpx_abi_version(void);
  * case the library creates and owns a non-blocking stream at default
  * priority.  All device work of the handle is ordered on that stream.
  * Errors: MPX_E_INVALID for non-positive sizes or spacings, courant outside
- * (0, 1] when dt <= 0, a one-sided periodic axis, PML slabs that leave no
- * interior cell on an axis; MPX_E_DEVICE / MPX_E_NOMEM from HIP. */
+ * (0, 1] when dt <= 0, an explicit dt > 0 above the 3-D Yee stability limit
+ * 1 / (c sqrt(dx^-2 + dy^-2 + dz^-2)) (or not finite), a one-sided periodic
+ * axis, PML slabs that leave no interior cell on an axis (all checked before
+ * any device call); MPX_E_DEVICE / MPX_E_NOMEM from HIP. */
 mpx_status mpx_create(const mpx_grid_desc *grid, mpx_precision precision, int32_t hip_device,
                       void *hip_stream, mpx_sim **out);
 
@@ -157,7 +159,9 @@ mpx_status mpx_query_field(const mpx_sim *sim, int32_t field, int64_t dims[4], i
  * magnetic cells, boxes closer than two cells merged) and resets M to zero.
  * Errors: MPX_E_INVALID for an id >= n, a magnetic cell inside or next to a
  * PML slab, or > 64 films; MPX_E_UNSUPPORTED for a film that touches a
- * non-periodic domain face or wraps partially around a periodic one. */
+ * non-periodic domain face or wraps partially around a periodic one;
+ * MPX_E_STATE once a MEAN_M or FILM_ENERGY probe exists (it names a film of
+ * the previous map: set the materials first). */
 mpx_status mpx_set_materials(mpx_sim *sim, const mpx_material *table, int32_t n, const uint8_t *cell_ids);
 
 /* Uniform static bias field H0 (A/m), part of H_eff (Methods: H_eff collects
@@ -190,8 +194,11 @@ mpx_status mpx_step(mpx_sim *sim, int64_t nsteps);
 mpx_status mpx_synchronize(mpx_sim *sim);
 
 /* Copy a field out (natural dims) to host (dst_is_device = 0) or device
- * memory.  Synchronises.  MPX_E_RANGE if dst_bytes is below mpx_query_field's
- * size. */
+ * memory.  E and H into device memory: strided device-to-device copies on the
+ * handle's stream, no host staging; M fields (film sites only) are gathered
+ * on the host.  The device copies run on the handle's stream: work of other
+ * streams on dst must be complete before the call.  Synchronises.
+ * MPX_E_RANGE if dst_bytes is below mpx_query_field's size. */
 mpx_status mpx_read_field(mpx_sim *sim, int32_t field, void *dst, int64_t dst_bytes, int32_t dst_is_device);
 
 /* Copy the sub-box box = (i0,j0,k0,ni,nj,nk) of a field (natural index
@@ -205,7 +212,9 @@ mpx_status mpx_read_field_region(mpx_sim *sim, int32_t field, const int32_t box[
 /* Overwrite a field (natural dims, the element type of mpx_query_field).
  * E values on PEC edges and on the faces of non-periodic walls are held at
  * zero; H values on the upper wall faces are not stored; M values are kept
- * only at magnetic sites.  MPX_DM_* fields are read-only. */
+ * only at magnetic sites.  MPX_DM_* fields are read-only.  The values pass
+ * through host memory (the PEC edges are masked there), also from a device
+ * source; mpx_field_storage gives copy-free device access. */
 mpx_status mpx_write_field(mpx_sim *sim, int32_t field, const void *src, int64_t src_bytes, int32_t src_is_device);
 
 /* Copy the recorded samples of probe `id`, oldest first, into dst (float64;
@@ -218,6 +227,22 @@ mpx_status mpx_read_probe(mpx_sim *sim, int32_t id, double *dst, int64_t capacit
  * and the Zeeman term -mu0 dV sum_c sum_{family-c sites} H0_c M_c.  Computed
  * on the device in float64.  MPX_E_UNSUPPORTED with PML faces. */
 mpx_status mpx_energy(mpx_sim *sim, double *W_em, double *W_zeeman);
+
+/* Zero-copy access to the library's own storage of an E or H component
+ * (field 0..5), for callers that keep fields in device tensors without
+ * copies (in place of binding caller-owned buffers: the stored lattice is
+ * padded, which the library owns).  Returns the device pointer of site
+ * (0, 0, 0) and the element strides along x, y, z: stored site (i, j, k),
+ * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, is element i + strides[1] j +
+ * strides[2] k (float32 or float64 as the precision; x fastest, strides[1]
+ * >= nx).  Sites of the natural dims beyond nx, ny or nz (wall edges and
+ * faces) are not stored; they are zero.  `bytes` (may be NULL) is the
+ * allocation's size.  The pointer stays valid until mpx_destroy; reads and
+ * writes through it must be ordered with the handle's stream (a write must
+ * keep PEC edges at zero).  Errors: MPX_E_INVALID (field, null pointers),
+ * MPX_E_STATE under a fused schedule (mpx_set_schedule > 0: the fields move
+ * between two buffers there). */
+mpx_status mpx_field_storage(mpx_sim *sim, int32_t field, void **device_ptr, int64_t strides[3], int64_t *bytes);
 
 /* Step count, time = step dt, dt and number of films. */
 mpx_status mpx_info(const mpx_sim *sim, int64_t *step, double *time, double *dt, int32_t *n_films);

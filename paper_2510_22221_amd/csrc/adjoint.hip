@@ -764,6 +764,72 @@ __global__ void __launch_bounds__(256) k_adj_loss_tape(AdjParams<T> A, int film,
     }
 }
 
+// The loss's own dependence on eps_r: the film energy holds
+// 1/2 eps0 eps_r dV times the mean over its four edges of E_C^2 (summed over
+// C) for each film cell, so dL/d eps_r of a film cell collects that sum of
+// every state in the loss window, x scale.  acc is [film cell box] (x
+// fastest).  From a film-region tape slot (seg0 null: always; else only when
+// seg0 + m is past loss_from) ...
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_loss_eps_tape(KParams<T> p, int film, double scale, const double *tape,
+                                                           const long long *seg0, int m, long long loss_from,
+                                                           double *acc) {
+    if (seg0 && seg0[0] + m <= loss_from) return;
+    const FilmDev &F = p.films[film];
+    const int b0[3] = {F.cb[0], F.cb[1], F.cb[2]}, r[3] = {F.cb[3] + 1, F.cb[4] + 1, F.cb[5] + 1};
+    const long long tb = (long long)r[0] * r[1] * r[2];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)F.cb[3] * F.cb[4] * F.cb[5]) return;
+    const int cell[3] = {F.cb[0] + (int)(t % F.cb[3]), F.cb[1] + (int)((t / F.cb[3]) % F.cb[4]),
+                         F.cb[2] + (int)(t / ((long long)F.cb[3] * F.cb[4]))};
+    double eps;
+    if (!film_cell(p, F, cell[0], cell[1], cell[2], eps)) return;
+    double we = 0.0;
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        double e2 = 0.0;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int e[3] = {cell[0], cell[1], cell[2]};
+                e[C1] += u;
+                e[C2] += v;
+                const long long ri = region_index(p.n, p.per, b0, r, e);
+                if (ri < 0) continue; // a wall edge: E = 0
+                const double x = tape[C * tb + ri];
+                e2 += x * x;
+            }
+        we += e2 / 4.0;
+    }
+    acc[t] += scale * 0.5 * p.eps0 * p.dV * we;
+}
+
+// ... or from the current state (the plain schedule)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_loss_eps_state(KParams<T> p, int film, double scale, double *acc) {
+    const FilmDev &F = p.films[film];
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)F.cb[3] * F.cb[4] * F.cb[5]) return;
+    const int cell[3] = {F.cb[0] + (int)(t % F.cb[3]), F.cb[1] + (int)((t / F.cb[3]) % F.cb[4]),
+                         F.cb[2] + (int)(t / ((long long)F.cb[3] * F.cb[4]))};
+    double eps;
+    if (!film_cell(p, F, cell[0], cell[1], cell[2], eps)) return;
+    double we = 0.0;
+    for (int C = 0; C < 3; C++) {
+        const int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
+        double e2 = 0.0;
+        for (int u = 0; u < 2; u++)
+            for (int v = 0; v < 2; v++) {
+                int q[3] = {cell[0], cell[1], cell[2]};
+                q[C1] += u;
+                q[C2] += v;
+                const double x = (double)ldz(p, p.E[C], q[0], q[1], q[2]);
+                e2 += x * x;
+            }
+        we += e2 / 4.0;
+    }
+    acc[t] += scale * 0.5 * p.eps0 * p.dV * we;
+}
+
 // E^n and x^n = (d1 + psi1') - (d2 + psi2') - J^n (the E update's input, H at
 // n + 1/2) over the edges of a cell box: [6][region] (E0..2, x0..2); taken
 // just before the E pass
@@ -1381,6 +1447,24 @@ hipError_t launch_adj_loss_tape(const AdjParams<T> &A, int film, double scale, c
 }
 
 template <typename T>
+hipError_t launch_adj_loss_eps_tape(const KParams<T> &p, int film, double scale, const double *tape,
+                                    const long long *seg0, int m, long long loss_from, double *acc, hipStream_t s,
+                                    const int *cb) {
+    const long long nc = (long long)cb[3] * cb[4] * cb[5];
+    k_adj_loss_eps_tape<T><<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s>>>(p, film, scale, tape, seg0, m,
+                                                                                    loss_from, acc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_loss_eps_state(const KParams<T> &p, int film, double scale, double *acc, hipStream_t s,
+                                     const int *cb) {
+    const long long nc = (long long)cb[3] * cb[4] * cb[5];
+    k_adj_loss_eps_state<T><<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s>>>(p, film, scale, acc);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_tape_box(const KParams<T> &p, const int *box, double *dst, hipStream_t s) {
     const long long tb = box_tape_size(box) / 6;
     k_tape_box<T><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(
@@ -1449,6 +1533,11 @@ hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t
     template hipError_t launch_adj_loss_tape<T>(const AdjParams<T> &, int, double, const double *,              \
                                                 const long long *, int, long long, hipStream_t, const int *);   \
     template hipError_t launch_tape_box<T>(const KParams<T> &, const int *, double *, hipStream_t);             \
+    template hipError_t launch_adj_loss_eps_tape<T>(const KParams<T> &, int, double, const double *,             \
+                                                    const long long *, int, long long, double *, hipStream_t,    \
+                                                    const int *);                                                \
+    template hipError_t launch_adj_loss_eps_state<T>(const KParams<T> &, int, double, double *, hipStream_t,     \
+                                                     const int *);                                               \
     template hipError_t launch_adj_eps_box<T>(const KParams<T> &, const int *, const double *, const double *,   \
                                               double *, hipStream_t);
 MPX_ADJ(float)

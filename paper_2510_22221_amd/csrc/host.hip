@@ -71,7 +71,7 @@ struct mpx_sim {
     int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
     int kchunk = 16;
     void *d_coef = nullptr;
-    void *d_coefx = nullptr; // extended coefficient table of the mixed-class slots
+    long long n_coef_ext = 0; // extended triples after the class entries of d_coef
     // materials
     bool have_mat = false;
     std::vector<mpx_material> mats;
@@ -103,8 +103,9 @@ struct mpx_sim {
     SrcDev *d_srcs = nullptr; // device copy of the source descriptors
     uint8_t *d_pflags = nullptr; // per separate-pass tile: CPML / source / film bits
     uint8_t *d_pflags_w = nullptr; // the same for the wide tiles (when nx >= kWideMinNx)
-    int4 *d_mixed = nullptr;     // slots of the mixed class (the general path)
+    int4 *d_mixed = nullptr;     // mixed-class slots without an extended triple (the general path)
     int nmixed = 0;
+    uint16_t *d_cls16 = nullptr; // per slot: the class with extended triples (256 + index), 0xffff: mixed list
     long long *d_step = nullptr;
     int *d_flag = nullptr;
     long long step = 0;
@@ -263,7 +264,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.cls = s->d_cls;
     p.mat = s->d_mat;
     p.coef = (const CoefDev<T> *)s->d_coef;
-    p.coefx = (const CoefDev<T> *)s->d_coefx;
+    p.coefx = p.coef + kCoefEntries;
     p.nfilm = (int)s->films.size();
     p.films = s->d_films;
     p.blocktab = s->d_blocktab;
@@ -278,6 +279,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.wide = s->d_pflags_w != nullptr;
     p.mixed = s->d_mixed;
     p.nmixed = s->nmixed;
+    p.cls16 = s->d_cls16;
     p.probes = s->d_probes;
     p.step = s->d_step;
     p.flag = s->d_flag;
@@ -722,6 +724,7 @@ struct mpx_batch {
     int nwork2 = 0;
     int2 *d_wmixed = nullptr; // mixed-slot blocks: (instance, first entry)
     int nwmixed = 0;
+    bool any_xcls = false; // a member has extended-table slots
     int2 *d_wfilm = nullptr, *d_wext = nullptr, *d_wprobe = nullptr;
     int nwfilm = 0, nwext = 0, nwprobe = 0;
     int probe_maxpart = 0;
@@ -760,6 +763,7 @@ void batch_drop_graph(mpx_batch *b) {
 
 template <typename T>
 mpx_status batch_tables(mpx_batch *b) {
+    b->any_xcls = false;
     // tiles instance by instance, in the single-instance order
     std::vector<int4> work, work2;
     std::vector<int2> wmixed, wfilm, wext, wprobe;
@@ -772,6 +776,7 @@ mpx_status batch_tables(mpx_batch *b) {
                 for (int by = 0; by < nyt; by++)
                     for (int bx = 0; bx < nxt; bx++) work2.push_back(make_int4(q, bx, by, k));
             for (int m = 0; m < s->nmixed; m += 256) wmixed.push_back(make_int2(q, m));
+            if (s->d_cls16) b->any_xcls = true;
         } else {
             // tiles of 64 x 4 columns (register sweep) or 64 x 8 (LDS-staged)
             const int nxt = (s->n[0] + 63) / 64, nyt = b->variant == 1 ? (s->n[1] + 3) / 4 : (s->n[1] + 7) / 8;
@@ -857,7 +862,7 @@ mpx_status batch_body(mpx_batch *b, int f) {
     if (b->variant == 0) {
         // E pass, film half steps and probes, then the bulk H pass (which
         // moves every instance's step counter)
-        BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, b->d_wmixed, b->nwmixed, st));
+        BCK(launch_epass_batch<T>(pa, b->d_work2, b->nwork2, b->d_wmixed, b->nwmixed, b->any_xcls, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 1, 0, st));
         BCK(launch_probes_batch<T>(pa, b->d_wprobe, b->nwprobe, b->probe_maxpart, st));
         BCK(launch_film_batch<T>(pa, b->d_wext, b->nwext, b->d_wfilm, b->nwfilm, 2, 0, st));
@@ -1202,6 +1207,34 @@ mpx_status film_grads(mpx_sim *s, const AdjHost &h, double S, const int *ms_box,
     return MPX_OK;
 }
 
+// whether two cell boxes (x0, y0, z0, nx, ny, nz) share a cell
+bool boxes_meet(const int *a, const int *b) {
+    for (int i = 0; i < 3; i++)
+        if (a[i] + a[3 + i] <= b[i] || b[i] + b[3 + i] <= a[i]) return false;
+    return a[3] * a[4] * a[5] > 0 && b[3] * b[4] * b[5] > 0;
+}
+
+// adds the film-energy loss's own eps_r term (accumulated per cell of the
+// film's cell box cb, scaled like the adjoint seed) to the eps-box gradient
+mpx_status add_loss_eps(mpx_sim *s, const double *d_acc, const int *cb, const int *eps_box, double *geps) {
+    const long long nc = (long long)cb[3] * cb[4] * cb[5];
+    std::vector<double> acc(nc);
+    CK(hipMemcpy(acc.data(), d_acc, nc * sizeof(double), hipMemcpyDeviceToHost));
+    const long long neps = (long long)eps_box[3] * eps_box[4] * eps_box[5];
+    for (long long t = 0; t < neps; t++) {
+        const int c[3] = {eps_box[0] + (int)(t % eps_box[3]), eps_box[1] + (int)((t / eps_box[3]) % eps_box[4]),
+                          eps_box[2] + (int)(t / ((long long)eps_box[3] * eps_box[4]))};
+        int l[3];
+        bool in = true;
+        for (int a = 0; a < 3; a++) {
+            l[a] = c[a] - cb[a];
+            if (l[a] < 0 || l[a] >= cb[3 + a]) in = false;
+        }
+        if (in) geps[t] += acc[l[0] + (long long)cb[3] * (l[1] + (long long)cb[4] * l[2])];
+    }
+    return MPX_OK;
+}
+
 template <typename T>
 mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, int K, const int *eps_box,
                        const int *ms_box, double *loss, double *gH0, double *geps, double *gms) {
@@ -1215,9 +1248,16 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
     AdjHost h;
     const long long neps = (long long)eps_box[3] * eps_box[4] * eps_box[5];
     mpx_status r = MPX_OK;
+    double *d_lacc = nullptr; // the loss's own eps_r term per film cell
+    const int *fcb = s->films[film].cb;
     auto body = [&]() -> mpx_status {
         mpx_status q;
         if ((q = adj_alloc(s, h, neps)) != MPX_OK) return q;
+        if (boxes_meet(eps_box, fcb)) {
+            const size_t nb = (size_t)fcb[3] * fcb[4] * fcb[5] * sizeof(double);
+            CK(hipMalloc(&d_lacc, nb));
+            CK(hipMemsetAsync(d_lacc, 0, nb, st));
+        }
         for (auto &z : cp)
             if ((q = snap_alloc(s, z)) != MPX_OK) return q;
         for (int m = 1; m < K; m++)
@@ -1262,6 +1302,11 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
                     if ((q = snap_copy(s, Sp, false)) != MPX_OK) return q;
                     adj_params<T>(s, h, A);
                     CK(launch_adj_loss<T>(A, film, dt * S, st));
+                    if (d_lacc) {
+                        KParams<T> p;
+                        fill_params<T>(s, p, MODE_INPLACE, s->parity);
+                        CK(launch_adj_loss_eps_state<T>(p, film, dt * S, d_lacc, st, fcb));
+                    }
                 }
                 // the step's intermediate states
                 if ((q = snap_copy(s, Sn, false)) != MPX_OK) return q;
@@ -1297,6 +1342,7 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
             if (neps > 0) CK(hipMemcpyAsync(geps, h.d_out, neps * sizeof(double), hipMemcpyDeviceToHost, st));
         }
         CK(hipStreamSynchronize(st));
+        if (d_lacc && (q = add_loss_eps(s, d_lacc, fcb, eps_box, geps)) != MPX_OK) return q;
         for (long long t = 0; t < neps; t++) geps[t] /= S;
         if ((q = film_grads(s, h, S, ms_box, gH0, gms)) != MPX_OK) return q;
         // leave the handle at the end of the forward run
@@ -1306,6 +1352,10 @@ mpx_status run_adjoint(mpx_sim *s, long long N, long long loss_from, int film, i
     };
     r = body();
     s->fused = saved_fused;
+    if (d_lacc) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(d_lacc);
+    }
     adj_free(h);
     for (auto &z : cp) snap_free(z);
     for (auto &z : seg) snap_free(z);
@@ -1543,9 +1593,15 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool probe_added = false;
+    double *d_lacc = nullptr; // the film-energy loss's own eps_r term per film cell
     auto body = [&]() -> mpx_status {
         mpx_status q;
         if ((q = adj_alloc(s, h, neps, false)) != MPX_OK) return q;
+        if (floss && boxes_meet(eps_box, LF.cb)) {
+            const size_t nb = (size_t)LF.cb[3] * LF.cb[4] * LF.cb[5] * sizeof(double);
+            CK(hipMalloc(&d_lacc, nb));
+            CK(hipMemsetAsync(d_lacc, 0, nb, st));
+        }
         for (int c = 0; c < 3; c++) {
             CK(hipMalloc(&h.mu[c], s->nslot * s->esz));
             CK(hipMemsetAsync(h.mu[c], 0, s->nslot * s->esz, st));
@@ -1712,6 +1768,12 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             adj_params<T>(s, h, A);
             CK(launch_tape_loss<T>(A.p, film, 0, tp.lossp(0), st, LF.cb));
             CK(launch_adj_loss_tape<T>(A, film, dt * S, tp.lossp(0), nullptr, 0, loss_from, st, LF.cb));
+            if (d_lacc) {
+                KParams<T> pe;
+                fill_params<T>(s, pe, MODE_INPLACE, s->parity);
+                CK(launch_adj_loss_eps_tape<T>(pe, film, dt * S, tp.lossp(0), nullptr, 0, loss_from, d_lacc, st,
+                                               LF.cb));
+            }
         } else {
             pw_slot = (long long)ls.ijk[0] + (long long)s->px * ((long long)ls.ijk[1] + (long long)s->n[1] * ls.ijk[2]);
             CK(hipMalloc(&d_w, N * sizeof(double)));
@@ -1747,6 +1809,13 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
                 }
             }
             for (int m = len - 1; m >= 0; m--) {
+                if (d_lacc) {
+                    // the loss's eps_r term of the step's input state
+                    KParams<T> pe;
+                    fill_params<T>(s, pe, MODE_INPLACE, s->parity);
+                    CK(launch_adj_loss_eps_tape<T>(pe, film, dt * S, tp.lossp(m), h.d_seg0, m, loss_from, d_lacc,
+                                                   st, LF.cb));
+                }
                 AdjParams<T> A;
                 adj_params<T>(s, h, A);
                 A.aflags = h.d_aflags;
@@ -1828,6 +1897,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             CK(hipMemcpyAsync(geps, h.d_out, neps * sizeof(double), hipMemcpyDeviceToHost, st));
         }
         CK(hipStreamSynchronize(st));
+        if (d_lacc && (q = add_loss_eps(s, d_lacc, LF.cb, eps_box, geps)) != MPX_OK) return q;
         for (long long t = 0; t < neps; t++) geps[t] /= S;
         if ((q = film_grads(s, h, S, ms_box, gH0, gms)) != MPX_OK) return q;
         // leave the handle at the end of the forward run
@@ -1848,6 +1918,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     }
     if (r != MPX_OK) (void)hipStreamSynchronize(st);
     (void)hipFree(d_w);
+    (void)hipFree(d_lacc);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     s->fused = saved_fused;
@@ -1883,11 +1954,14 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
         if (plo < 0 || phi < 0 || (lo == MPX_BC_PML && plo < 1) || (hi == MPX_BC_PML && phi < 1)) return MPX_E_INVALID;
         if (plo + phi >= nn[a]) return MPX_E_INVALID;
     }
+    // the stability limit of the 3-D Yee scheme
+    const double dt_max = 1.0 / (C0 * std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz)));
     double dt = g->dt;
     if (!(dt > 0)) {
         if (!(g->courant > 0) || g->courant > 1.0) return MPX_E_INVALID;
-        // Courant-limited step of the 3-D Yee scheme
-        dt = g->courant / (C0 * std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz)));
+        dt = g->courant * dt_max;
+    } else if (!(dt <= dt_max) || !std::isfinite(dt)) {
+        return MPX_E_INVALID; // an explicit step above the limit would grow without bound
     }
     mpx_sim *s = new mpx_sim();
     s->g = *g;
@@ -1959,7 +2033,6 @@ mpx_status mpx_destroy(mpx_sim *s) {
     drop_graph(s);
     for (auto e : s->ev) (void)hipEventDestroy(e);
     (void)hipFree(s->d_coef);
-    (void)hipFree(s->d_coefx);
     for (int c = 0; c < 3; c++) {
         (void)hipFree(s->E[c]);
         (void)hipFree(s->H[c]);
@@ -1986,6 +2059,7 @@ mpx_status mpx_destroy(mpx_sim *s) {
     (void)hipFree(s->d_pflags);
     (void)hipFree(s->d_pflags_w);
     (void)hipFree(s->d_mixed);
+    (void)hipFree(s->d_cls16);
     (void)hipFree(s->d_id);
     (void)hipFree(s->d_cls);
     (void)hipFree(s->d_mat);
@@ -2010,6 +2084,11 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
     mpx_status r = check_live(s);
     if (r != MPX_OK) return r;
     if (!table || !cell_ids || n < 1 || n > 256) return fail(s, MPX_E_INVALID, "bad material table");
+    // a film probe names a film of the current material map (its index and
+    // partial-sum layout were checked against that map's films)
+    for (auto &ph : s->probes)
+        if (ph.dev.kind == MPX_PROBE_MEAN_M || ph.dev.kind == MPX_PROBE_FILM_ENERGY)
+            return fail(s, MPX_E_STATE, "film probes exist: set the materials before adding film probes");
     const long long ncell = (long long)s->n[0] * s->n[1] * s->n[2];
     for (long long q = 0; q < ncell; q++)
         if (cell_ids[q] >= n) return fail(s, MPX_E_INVALID, "cell id outside the material table");
@@ -2229,57 +2308,75 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             ext_of.emplace(o.second, (int)ext_of.size());
             for (int C = 0; C < 3; C++) cdx.push_back(o.second->e[C]);
         }
-        // the mixed list, in slot order
+        // when the extended table has entries: a 16-bit class per slot for
+        // the E pass, the class byte's value where it is below 255 and
+        // otherwise 256 + the triple's index in the extended table (the
+        // table's rows after the 256 classes'), for the 65279 most frequent
+        // extended triples; the slots of the rarer ones (and of triples
+        // beyond the extended table) take 0xffff and go on the mixed list,
+        // in slot order, with their extended index (or -1: the cell-id path)
+        constexpr int kMaxCls16 = 0xffff - 256;
         std::vector<int4> mixed;
+        std::vector<uint16_t> c16;
+        if (!ext_of.empty()) {
+            c16.resize(s->nslot);
+            for (long long q = 0; q < s->nslot; q++) c16[q] = hc[q];
+        }
         bool changed = false;
         for (auto &sk : slot_key) {
             const Entry *en = entry_of[sk.second];
+            const long long q = sk.first;
             if (en->cls == kMixed) {
-                const long long q = sk.first;
                 auto it = ext_of.find(en);
-                mixed.push_back(make_int4((int)(q % s->px), (int)((q / s->px) % s->n[1]),
-                                          (int)(q / ((long long)s->px * s->n[1])), it == ext_of.end() ? -1 : it->second));
+                const int e = it == ext_of.end() ? -1 : it->second;
+                if (e >= 0 && e < kMaxCls16) {
+                    c16[q] = (uint16_t)(256 + e);
+                } else {
+                    if (!c16.empty()) c16[q] = 0xffff;
+                    mixed.push_back(make_int4((int)(q % s->px), (int)((q / s->px) % s->n[1]),
+                                              (int)(q / ((long long)s->px * s->n[1])), e));
+                }
                 continue;
             }
-            hc[sk.first] = (uint8_t)en->cls;
+            hc[q] = (uint8_t)en->cls;
+            if (!c16.empty()) c16[q] = (uint16_t)en->cls;
             changed = true;
         }
         if (changed) CK(hipMemcpy(s->d_cls, hc.data(), s->nslot, hipMemcpyHostToDevice));
+        (void)hipFree(s->d_cls16);
+        s->d_cls16 = nullptr;
+        if (!c16.empty()) {
+            CK(hipMalloc(&s->d_cls16, c16.size() * sizeof(uint16_t)));
+            CK(hipMemcpy(s->d_cls16, c16.data(), c16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        }
         (void)hipFree(s->d_mixed);
         s->d_mixed = nullptr;
         CK(hipMalloc(&s->d_mixed, std::max<size_t>(1, mixed.size()) * sizeof(int4)));
         if (!mixed.empty())
             CK(hipMemcpy(s->d_mixed, mixed.data(), mixed.size() * sizeof(int4), hipMemcpyHostToDevice));
         s->nmixed = (int)mixed.size();
-        (void)hipFree(s->d_coefx);
-        s->d_coefx = nullptr;
-        const size_t nx3 = std::max<size_t>(1, cdx.size());
+        // one table: the classes' entries, then the extended entries (the E
+        // pass indexes an extended triple as class 256 + its index)
+        const size_t ntot = (size_t)kCoefEntries + cdx.size();
+        (void)hipFree(s->d_coef);
+        s->d_coef = nullptr;
+        s->n_coef_ext = (long long)cdx.size() / kCoefPerClass;
         if (s->prec == MPX_F64) {
-            CK(hipMalloc(&s->d_coefx, nx3 * sizeof(CoefDev<double>)));
-            if (!cdx.empty())
-                CK(hipMemcpy(s->d_coefx, cdx.data(), cdx.size() * sizeof(cdx[0]), hipMemcpyHostToDevice));
+            std::vector<CoefDev<double>> all(cd);
+            all.insert(all.end(), cdx.begin(), cdx.end());
+            CK(hipMalloc(&s->d_coef, ntot * sizeof(CoefDev<double>)));
+            CK(hipMemcpy(s->d_coef, all.data(), ntot * sizeof(all[0]), hipMemcpyHostToDevice));
         } else {
-            std::vector<CoefDev<float>> cfx(nx3);
-            memset(cfx.data(), 0, cfx.size() * sizeof(cfx[0]));
-            for (size_t q = 0; q < cdx.size(); q++) {
-                cfx[q].ca = (float)cdx[q].ca;
-                cfx[q].cb = (float)cdx[q].cb;
-                cfx[q].pec = cdx[q].pec;
-            }
-            CK(hipMalloc(&s->d_coefx, nx3 * sizeof(CoefDev<float>)));
-            CK(hipMemcpy(s->d_coefx, cfx.data(), nx3 * sizeof(cfx[0]), hipMemcpyHostToDevice));
-        }
-        if (s->prec == MPX_F64) {
-            CK(hipMemcpy(s->d_coef, cd.data(), kCoefEntries * sizeof(cd[0]), hipMemcpyHostToDevice));
-        } else {
-            std::vector<CoefDev<float>> cf(kCoefEntries);
+            std::vector<CoefDev<float>> cf(ntot);
             memset(cf.data(), 0, cf.size() * sizeof(cf[0]));
-            for (int q = 0; q < kCoefEntries; q++) {
-                cf[q].ca = (float)cd[q].ca;
-                cf[q].cb = (float)cd[q].cb;
-                cf[q].pec = cd[q].pec;
+            for (size_t q = 0; q < ntot; q++) {
+                const CoefDev<double> &c = q < (size_t)kCoefEntries ? cd[q] : cdx[q - kCoefEntries];
+                cf[q].ca = (float)c.ca;
+                cf[q].cb = (float)c.cb;
+                cf[q].pec = c.pec;
             }
-            CK(hipMemcpy(s->d_coef, cf.data(), kCoefEntries * sizeof(cf[0]), hipMemcpyHostToDevice));
+            CK(hipMalloc(&s->d_coef, ntot * sizeof(CoefDev<float>)));
+            CK(hipMemcpy(s->d_coef, cf.data(), ntot * sizeof(cf[0]), hipMemcpyHostToDevice));
         }
     }
     if ((r = update_pass_flags(s)) != MPX_OK) return r;
@@ -2517,6 +2614,31 @@ mpx_status mpx_synchronize(mpx_sim *s) {
     return MPX_OK;
 }
 
+// the stored values of a box (x0, y0, z0, nx, ny, nz) of an E or H slot
+// array, clipped to the stored lattice, into a dense destination of that box
+// (x fastest; zero where nothing is stored): one strided copy per plane on
+// the handle's stream, device to device or device to host; synchronous
+static mpx_status copy_box_out(mpx_sim *s, const void *src, const int64_t b[6], void *dst, bool dst_dev) {
+    const size_t esz = s->esz;
+    const size_t need = (size_t)(b[3] * b[4] * b[5]) * esz;
+    if (dst_dev)
+        CK(hipMemsetAsync(dst, 0, need, s->stream));
+    else
+        memset(dst, 0, need);
+    const int64_t ci = std::min<int64_t>(b[3], s->n[0] - b[0]), cj = std::min<int64_t>(b[4], s->n[1] - b[1]);
+    if (ci > 0 && cj > 0)
+        for (int64_t k = 0; k < b[5]; k++) {
+            const int64_t gk = b[2] + k;
+            if (gk >= s->n[2]) break;
+            const char *from = (const char *)src + (size_t)(b[0] + (int64_t)s->px * (b[1] + (int64_t)s->n[1] * gk)) * esz;
+            char *to = (char *)dst + (size_t)(b[3] * b[4] * k) * esz;
+            CK(hipMemcpy2DAsync(to, (size_t)b[3] * esz, from, (size_t)s->px * esz, (size_t)ci * esz, (size_t)cj,
+                                dst_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+        }
+    CK(hipStreamSynchronize(s->stream));
+    return MPX_OK;
+}
+
 mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_bytes, int32_t dst_is_device) {
     mpx_status r = check_live(s);
     if (r != MPX_OK) return r;
@@ -2525,6 +2647,10 @@ mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_byte
     mpx_query_field(s, field, dims, &bytes);
     if (dst_bytes < bytes) return fail(s, MPX_E_RANGE, "destination too small");
     CK(hipStreamSynchronize(s->stream));
+    if (field < 6 && dst_is_device) {
+        const int64_t b[6] = {0, 0, 0, dims[0], dims[1], dims[2]};
+        return copy_box_out(s, field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3], b, dst, true);
+    }
     std::vector<char> host(bytes, 0);
     if (field < 6) {
         std::vector<char> slots(s->nslot * s->esz);
@@ -2567,6 +2693,19 @@ mpx_status mpx_read_field(mpx_sim *s, int32_t field, void *dst, int64_t dst_byte
     return MPX_OK;
 }
 
+mpx_status mpx_field_storage(mpx_sim *s, int32_t field, void **device_ptr, int64_t strides[3], int64_t *bytes) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (field < 0 || field > 5 || !device_ptr || !strides) return fail(s, MPX_E_INVALID, "bad field");
+    if (s->fused) return fail(s, MPX_E_STATE, "the fused schedules move the fields between two buffers");
+    *device_ptr = field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3];
+    strides[0] = 1;
+    strides[1] = s->px;
+    strides[2] = (int64_t)s->px * s->n[1];
+    if (bytes) *bytes = s->nslot * (int64_t)s->esz;
+    return MPX_OK;
+}
+
 mpx_status mpx_read_field_region(mpx_sim *s, int32_t field, const int32_t box[6], void *dst, int64_t dst_bytes,
                                  int32_t dst_is_device) {
     mpx_status r = check_live(s);
@@ -2581,24 +2720,14 @@ mpx_status mpx_read_field_region(mpx_sim *s, int32_t field, const int32_t box[6]
     const int64_t need = nr * dims[3] * (int64_t)esz;
     if (dst_bytes < need) return fail(s, MPX_E_RANGE, "destination too small");
     CK(hipStreamSynchronize(s->stream));
-    std::vector<char> host(need, 0);
     if (field < 6) {
-        void *src = field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3];
-        const int ni = box[3];
-        std::vector<char> row((size_t)ni * esz);
-        for (int k = 0; k < box[5]; k++)
-            for (int j = 0; j < box[4]; j++) {
-                const int gj = box[1] + j, gk = box[2] + k;
-                if (gj >= s->n[1] || gk >= s->n[2] || ni == 0) continue;
-                // contiguous run of the row inside the stored lattice
-                const int gi0 = box[0];
-                const int cnt = std::max(0, std::min(ni, s->n[0] - gi0));
-                if (cnt == 0) continue;
-                const size_t off = ((size_t)gi0 + (size_t)s->px * ((size_t)gj + (size_t)s->n[1] * gk)) * esz;
-                CK(hipMemcpy(&host[((size_t)j + (size_t)box[4] * k) * ni * esz], (const char *)src + off,
-                             (size_t)cnt * esz, hipMemcpyDeviceToHost));
-            }
-    } else {
+        if (nr == 0) return MPX_OK;
+        const int64_t b[6] = {box[0], box[1], box[2], box[3], box[4], box[5]};
+        return copy_box_out(s, field < 3 ? Eset(s, s->parity)[field] : Hset(s, s->parity)[field - 3], b, dst,
+                            dst_is_device != 0);
+    }
+    std::vector<char> host(need, 0);
+    {
         const int c = (field - 6) % 3;
         const bool delta = field >= 9;
         double *h = (double *)host.data();

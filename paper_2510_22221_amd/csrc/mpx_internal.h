@@ -94,9 +94,9 @@ struct KParams {
     T *Hb[3];
     T *psiEb[3][3];
     const CoefDev<T> *coef;
-    // every distinct edge-coefficient triple of the mixed-class slots, three
-    // entries each; a mixed-list entry's w indexes it (-1: none, the
-    // general path from the cell ids)
+    // every distinct edge-coefficient triple of the mixed-class slots (up to
+    // 2^20 of them), three entries each: the same allocation as coef, after
+    // its kCoefEntries class entries
     const CoefDev<T> *coefx;
     const uint8_t *id;
     const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
@@ -105,8 +105,15 @@ struct KParams {
     // two tiles), with their flags in pflags_w; batches keep the 64 x 4 tiles
     const uint8_t *pflags_w;
     int wide;
-    const int4 *mixed;     // slots of the mixed class, kMixed (i, j, k, -)
+    // slots of the mixed class left out of the 16-bit classes: (i, j, k,
+    // their extended-table index, or -1 for the general path from the cell
+    // ids)
+    const int4 *mixed;
     int nmixed;
+    // per slot, when the extended table has entries (else null): the class
+    // byte's value below 255, or 256 + the extended triple's index (rows of
+    // coef after the 256 classes'), or 0xffff for a slot on the mixed list
+    const uint16_t *cls16;
     const MatDev *mat;
     int nlo[3], nhi[3];
     const T *bE[3];
@@ -217,6 +224,15 @@ hipError_t launch_adj_eps_box(const KParams<T> &p, const int *box, const double 
                               hipStream_t s);
 hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t s);
 template <typename T> hipError_t launch_add_one(T *a, long long q, double v, hipStream_t s);
+// the film-energy loss's own eps_r term of the film cells, accumulated per
+// cell of the film's cell box from a tape slot or from the current state
+template <typename T>
+hipError_t launch_adj_loss_eps_tape(const KParams<T> &p, int film, double scale, const double *tape,
+                                    const long long *seg0, int m, long long loss_from, double *acc, hipStream_t s,
+                                    const int *cb);
+template <typename T>
+hipError_t launch_adj_loss_eps_state(const KParams<T> &p, int film, double scale, double *acc, hipStream_t s,
+                                     const int *cb);
 long long film_tape_size(const int *cb);
 long long box_tape_size(const int *box);
 // fused schedule: the half-step adjoint (scale = 1: first apply the E step's
@@ -237,7 +253,7 @@ template <typename T> hipError_t launch_hbulk(const KParams<T> &p, int nhalf, in
 template <typename T> hipError_t launch_epass(const KParams<T> &p, hipStream_t s);
 template <typename T>
 hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
-                              hipStream_t s);
+                              bool xcls, hipStream_t s);
 template <typename T>
 hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwork, int nhalf, int inc,
                               hipStream_t s);

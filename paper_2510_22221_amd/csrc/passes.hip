@@ -43,13 +43,14 @@ constexpr int kOOB = 0x7ffffff0; // a byte offset past every resource: the load 
 // any in-range value (only edges held at zero would read it); lanes past the
 // domain (partial tiles) compute nothing that is stored.  Each edge takes its
 // coefficients from the table entry of its slot's class and component (a
-// material, or a compound class of a slot whose eight cells differ); slots of
-// the mixed class (255: the table had no room) are skipped, and the
-// mixed-slot kernel updates them afterwards from the same old values.
+// material, or a compound class of a slot whose eight cells differ); on a
+// grid with more distinct triples than the class byte holds (XC) the slot's
+// 16-bit class also reaches the extended table's rows.  A slot on the mixed
+// list (class byte 255, or 16-bit class 0xffff) is skipped and updated
+// afterwards by the mixed-slot kernel from the same old values.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool XC>
 __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tsrc) {
-    const CoefMem<T> L{p.coef};
     const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
     const bool inside = i < p.n[0] && j < p.n[1];
     const int ic = min(i, p.n[0] - 1), jc = min(j, p.n[1] - 1);
@@ -66,7 +67,20 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
     const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
     const T hz0 = bld<T>(rz, vo, 0), hz_xm = bld<T>(rz, vxm, 0), hz_ym = bld<T>(rz, vym, 0);
-    const int c0 = (p.cls + k * sz)[o];
+    // the coefficient triple's row: the class byte (255: the slot is on the
+    // mixed list), or with extended triples (XC) the 16-bit class (0xffff:
+    // on the mixed list), whose rows past 255 are the extended table's
+    // (a batch member without 16-bit classes takes the byte: the test is
+    // uniform over the launch's lanes of one member)
+    bool c16 = false;
+    if constexpr (XC) c16 = p.cls16 != nullptr;
+    int c0;
+    if (c16)
+        c0 = (p.cls16 + k * sz)[o];
+    else
+        c0 = (p.cls + k * sz)[o];
+    const CoefMem<T> L{p.coef};
+    const int kSkip = c16 ? 0xffff : kMixed;
     T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
     const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
     const long long step = tsrc ? p.step[0] : 0;
@@ -78,7 +92,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
         // float64: the CPML state of one edge at a time (each thread alone
         // reads and writes its edges' psi and E), which keeps the kernel's
         // registers, and with them its occupancy, near the bulk path's
-        if (!inside || c0 == kMixed) return;
+        if (!inside || c0 == kSkip) return;
         T n0 = T(0), n1 = T(0), n2 = T(0);
         {
             Psi2<T> r;
@@ -117,7 +131,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
         if (v1) r1 = psi_load<T, 1, true>(p, q1);
         if (v2) r2 = psi_load<T, 2, true>(p, q2);
     }
-    if (!inside || c0 == kMixed) return;
+    if (!inside || c0 == kSkip) return;
     const T n0 = v0 ? e_apply<T, 0, CoefMem<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy),
                                                        dif(hy0, hy_km, dz, iz), r0, tsrc, step)
                     : T(0);
@@ -151,11 +165,11 @@ __device__ __forceinline__ bool wave_pml(const KParams<T> &p, int bx, int f) {
 
 // a block: the TX x TY slots (bx, by) of plane k, flags from the table of
 // that tile shape
-template <typename T, int TX = PTX, int TY = PTY>
+template <typename T, bool XC, int TX = PTX, int TY = PTY>
 __device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + TX - 1) / TX, nyt = (p.n[1] + TY - 1) / TY;
     const int f = (TX == PTX ? p.pflags : p.pflags_w)[bx + nxt * (by + nyt * k)];
-    epass_tile<T>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 2) != 0);
+    epass_tile<T, XC>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 2) != 0);
 }
 
 // the mixed slots, one thread each: the general path (folded loads; edge
@@ -298,11 +312,12 @@ __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by,
 // then reads and writes 256 consecutive slots of every array: measured 5 %
 // (float32) and 9 % (float64) faster per step on a 512-wide grid, slower on
 // narrow ones).  In float32 the E pass is held to 64 VGPRs (8 waves per
-// SIMD; it fits without spilling).
-template <typename T, int TX, int TY>
+// SIMD; it fits without spilling).  XC: the variant for grids with
+// extended-table slots (16-bit classes).
+template <typename T, int TX, int TY, bool XC>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
 k_epass(KParams<T> p) {
-    epass_block<T, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+    epass_block<T, XC, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int NHALF, int TX, int TY>
@@ -337,13 +352,13 @@ __global__ void __launch_bounds__(256) k_emixed(KParams<T> p) {
 }
 
 // batched: work[w] = (instance, x tile, y tile, plane)
-template <typename T>
+template <typename T, bool XC>
 __global__ void __launch_bounds__(PTX *PTY)
     k_epass_batch(const KParams<T> *__restrict__ plist, const int4 *__restrict__ work, int nwork) {
     const int w = blockIdx.x;
     if (w >= nwork) return;
     const int4 wk = work[w];
-    epass_block<T>(plist[wk.x], wk.y, wk.z, wk.w);
+    epass_block<T, XC>(plist[wk.x], wk.y, wk.z, wk.w);
 }
 
 // work[w] = (instance, first list entry of a 256-entry block)
@@ -381,10 +396,15 @@ static dim3 pass_grid(const int *n) {
 // the E pass and then its mixed slots
 template <typename T>
 hipError_t launch_epass(const KParams<T> &p, hipStream_t s) {
-    if (p.wide)
-        k_epass<T, kWideTX, kWideTY><<<pass_grid<kWideTX, kWideTY>(p.n), dim3(kWideTX, kWideTY), 0, s>>>(p);
+    const dim3 gw = pass_grid<kWideTX, kWideTY>(p.n), gn = pass_grid<PTX, PTY>(p.n);
+    if (p.wide && p.cls16)
+        k_epass<T, kWideTX, kWideTY, true><<<gw, dim3(kWideTX, kWideTY), 0, s>>>(p);
+    else if (p.wide)
+        k_epass<T, kWideTX, kWideTY, false><<<gw, dim3(kWideTX, kWideTY), 0, s>>>(p);
+    else if (p.cls16)
+        k_epass<T, PTX, PTY, true><<<gn, dim3(PTX, PTY), 0, s>>>(p);
     else
-        k_epass<T, PTX, PTY><<<pass_grid<PTX, PTY>(p.n), dim3(PTX, PTY), 0, s>>>(p);
+        k_epass<T, PTX, PTY, false><<<gn, dim3(PTX, PTY), 0, s>>>(p);
     if (p.nmixed > 0) k_emixed<T><<<dim3((p.nmixed + 255) / 256), dim3(256), 0, s>>>(p);
     return hipGetLastError();
 }
@@ -427,9 +447,12 @@ hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t
 
 template <typename T>
 hipError_t launch_epass_batch(const KParams<T> *plist, const int4 *work, int nwork, const int2 *mwork, int nmwork,
-                              hipStream_t s) {
+                              bool xcls, hipStream_t s) {
     if (nwork == 0) return hipSuccess;
-    k_epass_batch<T><<<dim3(nwork), dim3(PTX, PTY), 0, s>>>(plist, work, nwork);
+    if (xcls)
+        k_epass_batch<T, true><<<dim3(nwork), dim3(PTX, PTY), 0, s>>>(plist, work, nwork);
+    else
+        k_epass_batch<T, false><<<dim3(nwork), dim3(PTX, PTY), 0, s>>>(plist, work, nwork);
     if (nmwork > 0) k_emixed_batch<T><<<dim3(nmwork), dim3(256), 0, s>>>(plist, mwork, nmwork);
     return hipGetLastError();
 }
@@ -451,7 +474,7 @@ hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwo
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);                       \
     template hipError_t launch_hbulk_film<T>(const KParams<T> &, int, int, hipStream_t);                  \
     template hipError_t launch_epass_batch<T>(const KParams<T> *, const int4 *, int, const int2 *, int,   \
-                                              hipStream_t);                                               \
+                                              bool, hipStream_t);                                         \
     template hipError_t launch_hbulk_batch<T>(const KParams<T> *, const int4 *, int, int, int, hipStream_t);
 MPX_PASSES(float)
 MPX_PASSES(double)

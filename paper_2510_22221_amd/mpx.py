@@ -25,7 +25,7 @@ F64, F32 = 0, 1
 PEC, PML, PERIODIC = 0, 1, 2
 EX, EY, EZ, HX, HY, HZ, MXF, MYF, MZF, DMXF, DMYF, DMZF = range(12)
 PROBE_FIELD, PROBE_MEAN_M, PROBE_FILM_ENERGY, PROBE_EM_ENERGY = 0, 1, 2, 3
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4: "MPX_E_DEVICE",
           5: "MPX_E_UNSUPPORTED", 6: "MPX_E_RANGE", 7: "MPX_E_NONFINITE"}
@@ -33,7 +33,7 @@ STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "mpx_set_materials",
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
-           "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_read_probe", "mpx_energy", "mpx_info",
+           "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_field_storage", "mpx_read_probe", "mpx_energy", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
            "mpx_last_error", "mpx_adjoint", "mpx_adjoint_probe", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
            "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "mpx_read_field": (I32, [P, I32, P, I64, I32]),
         "mpx_read_field_region": (I32, [P, I32, C.POINTER(I32), P, I64, I32]),
         "mpx_write_field": (I32, [P, I32, P, I64, I32]),
+        "mpx_field_storage": (I32, [P, I32, C.POINTER(P), C.POINTER(I64), C.POINTER(I64)]),
         "mpx_read_probe": (I32, [P, I32, P, I64, C.POINTER(I64)]),
         "mpx_energy": (I32, [P, C.POINTER(D), C.POINTER(D)]),
         "mpx_info": (I32, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]),
@@ -160,6 +161,7 @@ class Sim:
         self._h = h
         self.precision = precision
         self.shape = (int(nz), int(ny), int(nx))
+        self.device = int(device)
         self.dtype = np.float64 if precision == F64 else np.float32
 
     def close(self):
@@ -257,6 +259,25 @@ class Sim:
         arr = np.empty((nc, nz, ny, nx), dtype=dt)
         self._ck(self._L.mpx_read_field(self._h, int(field), arr.ctypes.data, nb, 0), "read_field")
         return arr[0] if nc == 1 else arr
+
+    def storage(self, field):
+        """A torch tensor [nz, ny, nx] viewing the library's own storage of
+        E or H component `field` (0..5), without a copy: writes through it
+        change the simulation (order them with the handle's stream and keep
+        PEC edges at zero)."""
+        import torch
+        ptr = C.c_void_p()
+        st = (C.c_int64 * 3)()
+        nb = C.c_int64()
+        self._ck(self._L.mpx_field_storage(self._h, int(field), C.byref(ptr), st, C.byref(nb)), "field_storage")
+        esz = np.dtype(self.dtype).itemsize
+        shape = self.shape
+        typestr = "<f8" if esz == 8 else "<f4"
+
+        class _View:
+            __cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (ptr.value, False),
+                                        "strides": (st[2] * esz, st[1] * esz, esz), "version": 3}
+        return torch.as_tensor(_View(), device=f"cuda:{self.device}")
 
     def get_region(self, field, box):
         """Sub-box (i0, j0, k0, ni, nj, nk) of a field, numpy [k, j, i] (or

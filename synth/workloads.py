@@ -366,3 +366,21 @@ def c4_instance(nx: int = 128, ny: int = 64, nz: int = 64, nsteps: int = 20000, 
 
 def c4(nsteps: int = 20000) -> Workload:
     return c4_instance(128, 64, 64, nsteps)
+
+
+def crop(w: Workload, lo: Tuple[int, int, int], size: Tuple[int, int, int], name: str = "") -> Workload:
+    """A sub-box of a workload's grid (x, y, z origin `lo`, cell counts
+    `size`) with the same materials, boundaries and PML depth; sources that
+    lie wholly inside move with it, probes are dropped.  A bounded sample of a
+    large configuration for timing the oracle on the host."""
+    (i0, j0, k0), (nx, ny, nz) = lo, size
+    ids = None if w.ids is None else w.ids[k0:k0 + nz, j0:j0 + ny, i0:i0 + nx].copy()
+    srcs = []
+    for s in w.sources:
+        a, b, c, ni, nj, nk = s.box
+        if a >= i0 and b >= j0 and c >= k0 and a + ni <= i0 + nx and b + nj <= j0 + ny and c + nk <= k0 + nz:
+            srcs.append(Source(s.comp, (a - i0, b - j0, c - k0, ni, nj, nk), s.table))
+    return Workload(name or f"{w.name} [crop {nx}x{ny}x{nz} at {lo}]", nx, ny, nz, w.d, w.dt, w.courant,
+                    bc=w.bc, npml=w.npml, pml_order=w.pml_order, pml_factor=w.pml_factor,
+                    materials=list(w.materials), ids=ids, H0=w.H0, m_dir=w.m_dir, sources=srcs, probes=[],
+                    nsteps=w.nsteps)

@@ -75,3 +75,16 @@ def many_materials_case(nsteps):
     w.materials = mats
     w.ids = rng.integers(0, 150, size=(w.nz, w.ny, w.nx)).astype(np.uint8)
     return w
+
+
+def drive_film(w, nsteps, amp=2e11):
+    """Adds two point currents just above the centre of the workload's
+    topmost film layer (cells of material 3), so that the film's
+    magnetisation moves within a short run; returns w."""
+    k_top = int(np.nonzero((w.ids == 3).any(axis=(1, 2)))[0].max())
+    ys, xs = np.nonzero(w.ids[k_top] == 3)
+    ctr = (int(xs.mean()), int(ys.mean()), k_top + 1)
+    tab = amp * np.sin(0.7 * np.arange(nsteps) + 0.2)
+    w.sources.append(W.Source(0, (ctr[0], ctr[1], ctr[2], 1, 1, 1), tab))
+    w.sources.append(W.Source(1, (ctr[0] + 3, ctr[1] - 2, ctr[2], 1, 1, 1), -0.6 * tab))
+    return w

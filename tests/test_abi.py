@@ -57,3 +57,35 @@ def test_missing_library_fails_loudly(tmp_path):
             mpx.load(str(tmp_path / "absent.so"))
     finally:
         mpx._lib = saved
+
+
+def _grid(dt, courant=0.9, d=(1e-6, 2e-6, 1.5e-6)):
+    g = mpx.GridDesc()
+    g.nx, g.ny, g.nz = 8, 8, 8
+    g.dx, g.dy, g.dz = d
+    g.courant = courant
+    g.dt = dt
+    for a in range(6):
+        g.bc[a] = 0
+    return g
+
+
+@pytest.mark.parametrize("factor", [1.0 + 1e-9, 1.5, float("inf")])
+def test_create_rejects_dt_above_the_courant_limit_without_touching_the_device(factor):
+    """An explicit dt above the 3-D Yee limit is refused before any device
+    call (the library's own limit, compared with the oracle's formula)."""
+    from oracle import oracle as O
+    d = (1e-6, 2e-6, 1.5e-6)
+    lim = O.courant_dt(1.0, *d)
+    h = ctypes.c_void_p()
+    g = _grid(lim * factor, d=d)
+    assert mpx.load().mpx_create(ctypes.byref(g), 0, 0, None, ctypes.byref(h)) == 1
+    assert not h.value
+
+
+@pytest.mark.parametrize("courant", [0.0, -0.5, 1.01])
+def test_create_rejects_courant_outside_the_unit_interval(courant):
+    h = ctypes.c_void_p()
+    g = _grid(0.0, courant=courant)
+    assert mpx.load().mpx_create(ctypes.byref(g), 0, 0, None, ctypes.byref(h)) == 1
+    assert not h.value

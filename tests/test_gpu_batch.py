@@ -6,14 +6,17 @@ single-instance bodies on a work list, so not one rounding may differ.  The
 members differ in grid size, bias and boundary conditions, one has no film
 (its step counter advances by the tick kernel), and the batch is stepped in
 several calls (odd and even step counts, through captured graphs and direct
-launches).  The single runs are checked against the oracle elsewhere.
+launches).  The members of one batch are also compared with the FP64
+oracle directly (two resonator instances of the sweep with their films
+driven, and a member with overflowing coefficient classes).
 """
 import numpy as np
 import pytest
 
+import oracle.oracle as O
 from paper_2510_22221_amd import mpx
 from synth import workloads as W
-from tests.parity import many_materials_case
+from tests.parity import drive_film, group_errors, many_materials_case, probe_errors
 
 pytestmark = pytest.mark.gpu
 CALLS = (7, 12, 1, 5)
@@ -112,8 +115,8 @@ def test_batch_rejects_bad_members():
 @pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
 def test_batch_member_with_mixed_slots(prec):
     """A member whose mixed slots overflow the class table (150 materials:
-    extended-table and cell-id entries in its mixed list) beside one without
-    any: the batched mixed-slot kernel gives the single-run bits."""
+    its slots take the extended table inside the E pass) beside one without
+    any: the batch gives the single-run bits."""
     nsteps = sum(CALLS) + 2
     ws = [many_materials_case(nsteps), W.c3_instance(64, 48, 40, 1.0, nsteps)]
     ref = []
@@ -136,3 +139,71 @@ def test_batch_member_with_mixed_slots(prec):
     b.close()
     for s in sims:
         s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(mpx.F64, 1e-11), (mpx.F32, 1e-4)])
+def test_batch_members_match_oracle(prec, tol):
+    """Two instances of the bias sweep (uneven sizes, biases 0.9 and 1.15 of
+    the anti-crossing field, films driven by a point current so that M moves)
+    and the 150-material member, stepped as one batch in several calls: each
+    member against the FP64 oracle, element by element (E, H, M - M0 and
+    the probes)."""
+    nsteps = sum(CALLS) + 8
+    ws = [drive_film(W.c3_instance(80, 64, 48, 0.9, nsteps), nsteps),
+          drive_film(W.c3_instance(64, 80, 40, 1.15, nsteps), nsteps),
+          many_materials_case(nsteps)]
+    say(f"batch of {len(ws)} against the oracle, prec={prec}")
+    sims = [mpx.from_workload(w, precision=prec) for w in ws]
+    b = mpx.Batch(sims)
+    b.set_graph_steps(4)
+    done = 0
+    for n in CALLS + (8,):
+        b.step(n)
+        done += n
+    b.sync()
+    for q, (s, w) in enumerate(zip(sims, ws)):
+        o = O.from_workload(w, threads=16)
+        o.step(done)
+        if q < 2:
+            dm = np.concatenate([o.get(f).ravel() for f in (9, 10, 11)])
+            assert np.abs(dm).max() > 1e-3, q
+        errs = group_errors(s, o)
+        perr = probe_errors(s, o, w, f64=tol < 1e-9)
+        say(f"  member {q}: {errs} probes max {max(perr) if perr else 0:.2e}")
+        for k, v in errs.items():
+            assert v <= tol, (q, k, v)
+        for v in perr:
+            assert v <= tol, q
+    b.close()
+    for s in sims:
+        s.close()
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+def test_every_tuning_candidate_gives_the_same_bits(prec):
+    """The autotuner may pick any of its candidates (the separate passes or
+    a fused variant with a z-chunk): each gives the batch the same bits, so
+    the choice changes speed only."""
+    from paper_2510_22221_amd import tune
+    nsteps = 2 * 11 + 2
+    ws = members(nsteps)[:3]
+    ref = None
+    for v, kc in tune.candidates(max(w.nz for w in ws)):
+        say(f"tuning candidate variant {v} z-chunk {kc}, prec={prec}")
+        sims = [mpx.from_workload(w, precision=prec) for w in ws]
+        b = mpx.Batch(sims)
+        b.set_schedule(v, kc)
+        b.set_graph_steps(4)
+        b.step(11)
+        b.step(11)
+        b.sync()
+        got = [state(s, w) for s, w in zip(sims, ws)]
+        b.close()
+        for s in sims:
+            s.close()
+        if ref is None:
+            ref = got
+            continue
+        for q in range(len(ws)):
+            for k, (a, r) in enumerate(zip(got[q], ref[q])):
+                assert np.array_equal(a, r), (v, kc, q, k)
