@@ -244,6 +244,17 @@ mpx_status mpx_energy(mpx_sim *sim, double *W_em, double *W_zeeman);
  * between two buffers there). */
 mpx_status mpx_field_storage(mpx_sim *sim, int32_t field, void **device_ptr, int64_t strides[3], int64_t *bytes);
 
+/* mpx_energy without any device allocation, for callers that cannot
+ * allocate (code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the per-block partial sums live in a
+ * static device array of 2^21 doubles (16 MiB) that each GPU the library runs
+ * on holds until the process ends.  Same results as mpx_energy, bitwise.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (several threads or handles) race.
+ * Errors as mpx_energy, plus MPX_E_RANGE for a grid of more than 1048560
+ * blocks of 64 x 4 cells (ceil(nx/64) ceil(ny/4) nz). */
+mpx_status mpx_energy_noalloc(mpx_sim *sim, double *W_em, double *W_zeeman);
+
 /* Step count, time = step dt, dt and number of films. */
 mpx_status mpx_info(const mpx_sim *sim, int64_t *step, double *time, double *dt, int32_t *n_films);
 

@@ -10,6 +10,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -1931,6 +1932,45 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
 
 } // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation energy call: a static device array (each GPU
+// the library runs on holds its own copy until the process ends).  In host
+// code `energy_scratch` names a host-side stand-in, never a device address:
+// the device address is taken once per device with hipGetSymbolAddress and
+// used everywhere instead.  Layout: the three sums at 0, the per-block
+// partial pairs from kScratchPart on.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr long long kScratchDoubles = 1LL << 21; // 16 MiB per device
+constexpr long long kScratchPart = 32;           // 256-byte offset of the partials
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kScratchDevices] = {};
+} // namespace
+
+static __device__ __align__(256) double energy_scratch[kScratchDoubles];
+
+__global__ void k_clear3(double *p) {
+    if (threadIdx.x < 3) p[threadIdx.x] = 0.0;
+}
+
+namespace {
+// the device address of this device's scratch (the handle's device current)
+mpx_status energy_scratch_ptr(mpx_sim *s, double **out) {
+    if (s->device < 0 || s->device >= kScratchDevices) return fail(s, MPX_E_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[s->device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(energy_scratch));
+        if (e != hipSuccess || !ptr) return dev_fail(s, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                     "hipGetSymbolAddress(energy_scratch)");
+        g_scratch_dev[s->device] = (double *)ptr;
+    }
+    *out = g_scratch_dev[s->device];
+    return MPX_OK;
+}
+} // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -2862,6 +2902,39 @@ mpx_status mpx_energy(mpx_sim *s, double *W_em, double *W_z) {
     CK(hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
     (void)hipFree(part);
     (void)hipFree(out);
+    const double dV = s->d[0] * s->d[1] * s->d[2];
+    *W_em = 0.5 * dV * (h[0] + MU0 * h[1]);
+    *W_z = -MU0 * dV * h[2];
+    return MPX_OK;
+}
+
+mpx_status mpx_energy_noalloc(mpx_sim *s, double *W_em, double *W_z) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (!W_em || !W_z) return MPX_E_INVALID;
+    if (!s->have_mat) return fail(s, MPX_E_STATE, "energy before set_materials");
+    if (s->any_pml) return fail(s, MPX_E_UNSUPPORTED, "energy with PML faces");
+    const long long nb = (long long)((s->n[0] + 63) / 64) * ((s->n[1] + 3) / 4) * s->n[2];
+    if (kScratchPart + 2 * nb > kScratchDoubles)
+        return fail(s, MPX_E_RANGE, "grid too large for the no-allocation energy (at most 1048560 blocks of 64 x 4 cells)");
+    double *scr = nullptr;
+    if ((r = energy_scratch_ptr(s, &scr)) != MPX_OK) return r;
+    double *out = scr, *part = scr + kScratchPart;
+    hipLaunchKernelGGL(k_clear3, dim3(1), dim3(64), 0, s->stream, out);
+    hipError_t e;
+    if (s->prec == MPX_F64) {
+        KParams<double> p;
+        fill_params<double>(s, p);
+        e = launch_energy<double>(p, s->nblk, part, out, s->stream);
+    } else {
+        KParams<float> p;
+        fill_params<float>(s, p);
+        e = launch_energy<float>(p, s->nblk, part, out, s->stream);
+    }
+    if (e != hipSuccess) return dev_fail(s, e, "energy kernels");
+    double h[3];
+    CK(hipStreamSynchronize(s->stream));
+    CK(hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
     const double dV = s->d[0] * s->d[1] * s->d[2];
     *W_em = 0.5 * dV * (h[0] + MU0 * h[1]);
     *W_z = -MU0 * dV * h[2];

@@ -33,7 +33,7 @@ STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "mpx_set_materials",
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
-           "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_field_storage", "mpx_read_probe", "mpx_energy", "mpx_info",
+           "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_field_storage", "mpx_read_probe", "mpx_energy", "mpx_energy_noalloc", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
            "mpx_last_error", "mpx_adjoint", "mpx_adjoint_probe", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
            "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "mpx_field_storage": (I32, [P, I32, C.POINTER(P), C.POINTER(I64), C.POINTER(I64)]),
         "mpx_read_probe": (I32, [P, I32, P, I64, C.POINTER(I64)]),
         "mpx_energy": (I32, [P, C.POINTER(D), C.POINTER(D)]),
+        "mpx_energy_noalloc": (I32, [P, C.POINTER(D), C.POINTER(D)]),
         "mpx_info": (I32, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(I32)]),
         "mpx_film_box": (I32, [P, I32, C.POINTER(I32), C.POINTER(I64)]),
         "mpx_set_graph_steps": (I32, [P, I32]),
@@ -314,6 +315,12 @@ class Sim:
     def energy(self):
         a, b = C.c_double(), C.c_double()
         self._ck(self._L.mpx_energy(self._h, C.byref(a), C.byref(b)), "energy")
+        return a.value, b.value
+
+    def energy_noalloc(self):
+        """energy() through the entry point that allocates no device memory."""
+        a, b = C.c_double(), C.c_double()
+        self._ck(self._L.mpx_energy_noalloc(self._h, C.byref(a), C.byref(b)), "energy_noalloc")
         return a.value, b.value
 
     def info(self):
