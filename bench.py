@@ -12,8 +12,9 @@ Prints one JSON line: Gcell-updates/s of the headline workload, the roofline
 of its dominant kernel (per-launch durations from HIP events on the
 library's stream), the 512 x 256 x 128 single resonator in float32 and
 float64 ("secondary"), the batched bias sweep against sequential runs, the
-adjoint's cost against the forward run on the 128 x 64 x 64 resonator, and
-the float64 CPU oracle timed on a bounded sample of the headline workload.
+anti-crossing analysed from a sweep's own traces, the adjoint's cost against
+the forward run on the 128 x 64 x 64 resonator, and the float64 CPU oracle
+timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -195,6 +196,69 @@ def batched_sweep(steps, n_inst, tune_steps=20):
                       "batched_Gcell_s": rate(tuned), "batched_over_sequential": round(seq / tuned, 3)}}
 
 
+def anticrossing(steps, n_inst, drive_factor=3000.0):
+    """The bias sweep's own traces through the spectral analysis: n_inst
+    copies of one 96 x 64 x 64 resonator + film whose bias runs over
+    0.7-1.3 of the field that tunes the film to the resonator, stepped as
+    one float32 batch; per instance the two strongest modes of the film's
+    mean M_x (ESPRIT on the trace after the drive pulse), then a fit of the
+    hybrid-mode law (eq. omega_pm) with the magnon branch proportional to
+    mu0 |gamma| H0 / 2 pi: the photon frequency, the coupling g and the
+    minimum splitting (the magnon branch fitted with a slope and an offset on
+    that law).  The drive-power variant: the instance nearest the
+    crossing with its source `drive_factor` times stronger."""
+    import numpy as np
+    from paper_2510_22221_amd import mpx, spectral as S
+    from synth import workloads as W
+
+    hs = np.linspace(0.7, 1.3, n_inst)
+    ws = [W.c3_instance(96, 64, 64, float(h), steps) for h in hs]
+    for w in ws:
+        w.probes = [W.Probe("mean_m", film=0)]
+    dt = ws[0].dt
+    sims = [mpx.from_workload(w, precision=mpx.F32) for w in ws]
+    b = mpx.Batch(sims)
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    run_s = time.perf_counter() - t0
+    b.close()
+    skip = steps // 5
+
+    def two_modes(sim):
+        mx = sim.read_probe(0, 3)[skip:, 0]
+        return S.sweep_branches([mx], dt, 2, stride=8, fmin=1e9, min_separation=0.02, max_rows=512)[0]
+
+    br = np.array([two_modes(s) for s in sims])
+    for s in sims:
+        s.close()
+    H0 = np.array([w.H0[2] for w in ws])
+    lo, hi = br[:, 0], br[:, 1]
+    fit = S.fit_anticrossing(H0, lo, hi, lambda h: S.kittel_perpendicular(h, 0.0), fp0=float(np.median(hi[:2])),
+                             g0=0.25 * float(np.min(hi - lo)), fit_scale=True, fit_offset=True)
+    split, q = S.mode_splitting(lo, hi)
+    out = {"instances": n_inst, "grid": "96x64x64", "steps": steps, "dtype": "f32", "batched_run_s": round(run_s, 2),
+           "H0_over_tuned": [round(float(h), 4) for h in hs],
+           "lower_GHz": [round(float(v) / 1e9, 4) for v in lo], "upper_GHz": [round(float(v) / 1e9, 4) for v in hi],
+           "fit": {"f_photon_GHz": round(fit.fp / 1e9, 4), "g_GHz": round(fit.g / 1e9, 4),
+                   "magnon_branch": f"{fit.scale:.5f} x mu0|gamma|H0/2pi + {fit.offset / 1e9:.4f} GHz",
+                   "residual_rms_GHz": round(fit.residual_rms / 1e9, 4)},
+           "min_splitting_GHz": round(split / 1e9, 4), "min_at_H0_over_tuned": round(float(hs[q]), 4)}
+    # the drive-power variant at the instance nearest the crossing
+    qc = int(np.argmin(np.abs(hs - 1.0)))
+    drv = {}
+    for name, w in (("x1", ws[qc]), (f"x{drive_factor:g}", W.scaled_drive(ws[qc], drive_factor))):
+        s = mpx.from_workload(w, precision=mpx.F32)
+        s.step(steps)
+        s.sync()
+        f = two_modes(s)
+        drv[name] = {"lower_GHz": round(float(f[0]) / 1e9, 4), "upper_GHz": round(float(f[1]) / 1e9, 4),
+                     "max_abs_dMx_over_Ms": round(float(np.abs(s.read_probe(0, 3)[:, 0]).max()) / 1.4e5, 6)}
+        s.close()
+    out["drive_power"] = {"H0_over_tuned": round(float(hs[qc]), 4), **drv}
+    return out
+
+
 def adjoint_cost(steps, window, graphs=True):
     """The adjoint of the 128 x 64 x 64 resonator + film + eps_r patch
     workload: loss = film EM energy summed over the last `window` of `steps`
@@ -304,6 +368,8 @@ def main():
                     help="0: separate E and H/M passes (default); 1-5: fused pass variants")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
     ap.add_argument("--sweep-instances", type=int, default=64)
+    ap.add_argument("--anticrossing-steps", type=int, default=100000,
+                    help="steps of the sweep analysed for the anti-crossing (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=20000, help="steps of the adjoint cost run (0: skip)")
     ap.add_argument("--adjoint-window", type=int, default=5000)
     ap.add_argument("--adjoint-no-graphs", action="store_true",
@@ -364,6 +430,9 @@ def main():
     if args.sweep_steps > 0:
         log(f"batched bias sweep: {args.sweep_instances} instances, {args.sweep_steps} steps")
         out["batched_sweep"] = batched_sweep(args.sweep_steps, args.sweep_instances)
+    if args.anticrossing_steps > 0:
+        log(f"anti-crossing: 12 instances, {args.anticrossing_steps} steps")
+        out["anticrossing"] = anticrossing(args.anticrossing_steps, 12)
     if args.adjoint_steps > 0:
         log(f"adjoint: {args.adjoint_steps} steps, loss over the last {args.adjoint_window}")
         out["adjoint"] = adjoint_cost(args.adjoint_steps, min(args.adjoint_window, args.adjoint_steps),

@@ -149,13 +149,16 @@ class AntiCrossingFit:
     g: float            # coupling of eq. omega_pm (minimum splitting 2 g)
     scale: float        # multiplier of the magnon branch fm(H0)
     residual_rms: float
+    offset: float = 0.0  # added to the magnon branch (fit_offset)
 
 
-def fit_anticrossing(H0, f_lower, f_upper, fm_of_H0, fp0: float, g0: float, fit_scale: bool = False):
+def fit_anticrossing(H0, f_lower, f_upper, fm_of_H0, fp0: float, g0: float, fit_scale: bool = False,
+                     fit_offset: bool = False):
     """Least-squares fit of eq. omega_pm to the two branches measured over a
-    bias sweep, with the detuning delta(H0) = s fm(H0) - fp taken from a
+    bias sweep, with the detuning delta(H0) = s fm(H0) + c - fp taken from a
     magnon law fm (for example kittel_inplane); fits fp, g (and s when
-    fit_scale)."""
+    fit_scale, c when fit_offset: a magnon branch linear in the law, for
+    static demagnetising and surface shifts the law leaves out)."""
     from scipy.optimize import least_squares
 
     H0 = np.asarray(H0, dtype=np.float64)
@@ -164,31 +167,49 @@ def fit_anticrossing(H0, f_lower, f_upper, fm_of_H0, fp0: float, g0: float, fit_
     fm = np.asarray(fm_of_H0(H0), dtype=np.float64)
     unit = float(max(abs(fp0), 1.0))
 
+    def unpack(v):
+        q = 2
+        s = 1.0
+        if fit_scale:
+            s = v[q]
+            q += 1
+        c = v[q] * unit if fit_offset else 0.0
+        return v[0] * unit, v[1] * unit, s, c
+
     def resid(v):
-        fp, g = v[0] * unit, v[1] * unit
-        s = v[2] if fit_scale else 1.0
-        a, b = omega_pm(fp, s * fm - fp, g)
+        fp, g, s, c = unpack(v)
+        a, b = omega_pm(fp, s * fm + c - fp, g)
         return np.concatenate([a - lo, b - hi]) / unit
 
-    v0 = [fp0 / unit, g0 / unit] + ([1.0] if fit_scale else [])
+    v0 = [fp0 / unit, g0 / unit] + ([1.0] if fit_scale else []) + ([0.0] if fit_offset else [])
     r = least_squares(resid, v0, xtol=1e-15, ftol=1e-15, gtol=1e-15)
-    fp, g = r.x[0] * unit, abs(r.x[1]) * unit
-    s = float(r.x[2]) if fit_scale else 1.0
-    return AntiCrossingFit(fp=float(fp), g=float(g), scale=s,
-                           residual_rms=float(np.sqrt(np.mean(r.fun ** 2)) * unit))
+    fp, g, s, c = unpack(r.x)
+    return AntiCrossingFit(fp=float(fp), g=float(abs(g)), scale=float(s),
+                           residual_rms=float(np.sqrt(np.mean(r.fun ** 2)) * unit), offset=float(c))
 
 
 def sweep_branches(traces: Sequence[np.ndarray], dt: float, n_modes: int = 2, stride: int = 1,
-                   fmin: float = 0.0, fmax: Optional[float] = None) -> np.ndarray:
+                   fmin: float = 0.0, fmax: Optional[float] = None, min_separation: float = 0.0,
+                   max_rows: int = 2048) -> np.ndarray:
     """ESPRIT frequencies (n_traces x n_modes, ascending per trace) of a bias
-    sweep's probe traces, restricted to [fmin, fmax]; missing modes are NaN."""
+    sweep's probe traces, restricted to [fmin, fmax]: per trace the strongest
+    modes taken in order of amplitude, skipping any closer than
+    `min_separation` (relative) to one already taken (a mode the fit splits
+    into a close pair counts once); missing modes are NaN."""
     out = np.full((len(traces), n_modes), np.nan)
     for q, x in enumerate(traces):
-        m = esprit(x, dt, n_modes + 2, stride=stride)
+        x = np.asarray(x, dtype=np.float64)
+        m = esprit(x - x.mean(), dt, n_modes + 2, stride=stride, max_rows=max_rows)
         sel = (m.f >= fmin) & (m.f <= (fmax if fmax is not None else np.inf))
         f = m.f[sel]
         a = m.amp[sel]
-        top = np.sort(f[np.argsort(-a)[:n_modes]])
+        top = []
+        for k in np.argsort(-a):
+            if all(abs(f[k] - t) > min_separation * t for t in top):
+                top.append(f[k])
+            if len(top) == n_modes:
+                break
+        top = np.sort(top)
         out[q, :top.size] = top
     return out
 
