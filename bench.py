@@ -117,8 +117,16 @@ def run_gpu(w, precision, steps, warmup, timing_steps=12, schedule=0):
     return sim, wall, kt
 
 
+def schedule_name(sched):
+    if sched == 0:
+        return "separate E and H/M passes (256 x 1 tiles on grids at least 512 wide)"
+    if sched == 6:
+        return "separate E and H/M passes on 64 x 4 tiles"
+    return f"fused pass, variant {sched}"
+
+
 def roofline_for(w, esz, kt, dtype_name, schedule=0, wkey="c5"):
-    fused = schedule != 0
+    fused = 1 <= schedule <= 5
     ab = algorithmic_bytes(w, esz)
     if fused:
         name, ms, nl = "fused", kt[0][0], kt[0][1]
@@ -365,7 +373,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--schedule", type=int, default=0,
-                    help="0: separate E and H/M passes (default); 1-5: fused pass variants")
+                    help="0: separate E and H/M passes (default); 1-5: fused pass variants; 6: separate passes on "
+                         "64 x 4 tiles")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="steps of the batched bias sweep (0: skip)")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--anticrossing-steps", type=int, default=100000,
@@ -407,7 +416,7 @@ def main():
                                f"d=2 um, 8 PEC strips each with a 200x40x4 film, random eps_r in [1,12] per "
                                f"32^3 block, PML 16, source + 8 mean-M probes, one time step per bench step",
                    "cells": w.ncells, "precision": "f32 fields, f64 magnetisation",
-                   "schedule": ("separate E and H/M passes" if sched == 0 else f"fused pass, variant {sched}"),
+                   "schedule": schedule_name(sched),
                    "timing": "host clock around graph replays; kernel durations from a separate "
                              "event-timed pass of 12 steps",
                    "parallelism": "single GPU"},

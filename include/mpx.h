@@ -273,7 +273,10 @@ mpx_status mpx_set_graph_steps(mpx_sim *sim, int32_t steps);
  * columns per block, each thread recomputes the neighbour edges it needs);
  * 2..5 = LDS-staged sweep over 64 x 8 tiles (2: two rows per thread, >= 2
  * waves per SIMD; 3: two rows, >= 4 waves; 4: one row, >= 2 waves; 5: one
- * row, >= 4 waves).  All give bitwise identical results. */
+ * row, >= 4 waves).  fused = 6: the separate passes on 64 x 4 tiles also
+ * on grids at least 512 cells wide (which schedule 0 runs on 256 x 1 tiles).
+ * All give bitwise identical results.  Errors: MPX_E_INVALID for fused
+ * outside 0..6 or kchunk < 0. */
 mpx_status mpx_set_schedule(mpx_sim *sim, int32_t fused, int32_t kchunk);
 
 /* Kernel timing with HIP events on the handle's stream.  With every > 0,

@@ -71,6 +71,7 @@ struct mpx_sim {
     int fused = 0; // separate passes (the fastest schedule measured on gfx950)
     int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
     int kchunk = 16;
+    bool narrow = false; // separate passes on 64 x 4 tiles whatever the width (schedule 6)
     void *d_coef = nullptr;
     long long n_coef_ext = 0; // extended triples after the class entries of d_coef
     // materials
@@ -277,7 +278,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.srcs = s->d_srcs;
     p.pflags = s->d_pflags;
     p.pflags_w = s->d_pflags_w;
-    p.wide = s->d_pflags_w != nullptr;
+    p.wide = s->d_pflags_w != nullptr && !s->narrow;
     p.mixed = s->d_mixed;
     p.nmixed = s->nmixed;
     p.cls16 = s->d_cls16;
@@ -2982,9 +2983,10 @@ mpx_status mpx_kernel_time(mpx_sim *s, double *avg_ms, int64_t *launches) {
 
 mpx_status mpx_set_schedule(mpx_sim *s, int32_t fused, int32_t kchunk) {
     if (!s || kchunk < 0) return MPX_E_INVALID;
+    if (fused < 0 || fused > 6) return MPX_E_INVALID;
     drop_graph(s);
-    if (fused < 0 || fused > 5) return MPX_E_INVALID;
-    s->fused = fused;
+    s->narrow = fused == 6;
+    s->fused = fused == 6 ? 0 : fused;
     if (kchunk > 0) s->kchunk = kchunk;
     return MPX_OK;
 }

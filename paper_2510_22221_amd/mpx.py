@@ -230,7 +230,8 @@ class Sim:
 
     def set_schedule(self, fused=True, kchunk=0):
         """fused: False/0 = separate E and H passes (the default); True/1 =
-        register-blocked fused sweep; 2..5 = LDS-staged fused tile variants."""
+        register-blocked fused sweep; 2..5 = LDS-staged fused tile variants;
+        6 = the separate passes on 64 x 4 tiles on wide grids too."""
         v = int(fused) if not isinstance(fused, bool) else (1 if fused else 0)
         self._ck(self._L.mpx_set_schedule(self._h, v, int(kchunk)), "set_schedule")
 

@@ -1,7 +1,8 @@
 """Schedule autotuner for the fused step pass.
 
-A step runs as two separate passes (schedule 0) or as one fused pass in one
-of five tile variants with a z-chunk length; which is fastest depends on
+A step runs as two separate passes (schedule 0, or 6 for 64 x 4 tiles on
+grids that schedule 0 runs on 256 x 1 tiles) or as one fused pass in one of
+five tile variants with a z-chunk length; which is fastest depends on
 the grid shape, the share of CPML and film tiles, and the precision.  ``tune`` builds scratch
 simulations of the caller's workload (the caller's own handles are never
 stepped), times every candidate with captured graphs, and caches the winner
@@ -24,8 +25,13 @@ KCHUNKS = (8, 16, 32)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
-def candidates(nz: int) -> List[Tuple[int, int]]:
+def candidates(nz: int, single: bool = False) -> List[Tuple[int, int]]:
+    """(schedule, z-chunk) pairs: the separate passes (schedule 0; for a
+    single handle also on 64 x 4 tiles on wide grids, schedule 6), and the
+    fused variants 1-5 at each z-chunk."""
     out = [(0, 16)]  # the separate passes have no z-chunk
+    if single:
+        out.append((6, 16))
     for v in VARIANTS[1:]:
         for kc in KCHUNKS:
             if kc <= max(8, nz):
@@ -84,7 +90,7 @@ def tune(w, precision=mpx.F32, steps: int = 40, repeats: int = 2, cache: Optiona
     s = mpx.from_workload(w, precision=precision, device=device, graph_steps=16)
     timings = {}
     try:
-        for v, kc in (cands or candidates(w.nz)):
+        for v, kc in (cands or candidates(w.nz, single=True)):
             s.set_schedule(v, kc)
             timings[(v, kc)] = _time_sims(s.step, s.sync, steps, repeats)
     finally:

@@ -99,3 +99,23 @@ def test_wide_member_of_a_batch_bitwise(prec):
     b.close()
     for s in sims:
         s.close()
+
+
+def test_narrow_tile_schedule_bitwise_equal_wide_tiles():
+    """Schedule 6 (the separate passes on 64 x 4 tiles, the film's second
+    half step as its own launch) gives the 520-wide box the bits of the
+    256 x 1 tiles in both precisions."""
+    w = wide_case(26)
+    for prec in (mpx.F64, mpx.F32):
+        say(f"64 x 4 tiles on the 520-wide box, prec={prec}")
+        ref = mpx.from_workload(w, precision=prec)
+        ref.step(13)
+        ref.step(13)
+        g = mpx.from_workload(w, precision=prec, fused=6)
+        g.step(13)
+        g.step(13)
+        for f in range(12):
+            assert np.array_equal(g.get(f), ref.get(f)), (prec, f)
+        for pid, p in enumerate(w.probes):
+            nv = 3 if p.kind == "mean_m" else 1
+            assert np.array_equal(g.read_probe(pid, nv), ref.read_probe(pid, nv)), (prec, pid)
