@@ -279,7 +279,7 @@ def adjoint_cost(steps, window, graphs=True):
     w = W.c4(steps + 10)
     out = {"workload": f"resonator + film + eps_r patch, {w.nx}x{w.ny}x{w.nz} cells, d=(40,2,2) um, PML 8",
            "steps": steps, "loss_window": window, "eps_cells": int(w.patch_box[3] * w.patch_box[4] * w.patch_box[5]),
-           "schedule": "tape, fused field passes"}
+           "schedule": "tape (segments keep their forward tapes as memory allows), fused field passes"}
     gs = None if graphs else 0
     for name, prec in (("f32", mpx.F32), ("f64", mpx.F64)):
         s = mpx.from_workload(w, precision=prec, graph_steps=gs)
@@ -292,14 +292,25 @@ def adjoint_cost(steps, window, graphs=True):
         s.sync()
         fwd = time.perf_counter() - t0
         s.close()
-        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
-        t0 = time.perf_counter()
-        r = s.adjoint(steps, steps - window, eps_box=w.patch_box, ms_box=w.film_top)
-        adj = time.perf_counter() - t0
-        s.close()
+        t_adj = {}
+        for mem in (-1, 0):
+            # -1: tapes kept as memory allows (the default); 0: every segment
+            # recomputed from its checkpoint
+            s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+            s.set_adjoint_memory(mem)
+            t0 = time.perf_counter()
+            r = s.adjoint(steps, steps - window, eps_box=w.patch_box, ms_box=w.film_top)
+            t_adj[mem] = time.perf_counter() - t0
+            s.close()
+            if mem == -1:
+                res = r
+        adj = t_adj[-1]
         out[name] = {"forward_s": round(fwd, 4), "adjoint_s": round(adj, 4), "adjoint_over_forward": round(adj / fwd, 3),
-                     "loss": r["loss"], "dL_dH0z": float(r["dH0"][2])}
-        log(f"  adjoint {name}: forward {fwd:.3f} s, adjoint {adj:.3f} s, ratio {adj / fwd:.2f}")
+                     "loss": res["loss"], "dL_dH0z": float(res["dH0"][2]),
+                     "recompute_every_segment": {"adjoint_s": round(t_adj[0], 4),
+                                                 "adjoint_over_forward": round(t_adj[0] / fwd, 3)}}
+        log(f"  adjoint {name}: forward {fwd:.3f} s, adjoint {adj:.3f} s, ratio {adj / fwd:.2f} "
+            f"(every segment recomputed: {t_adj[0]:.3f} s, {t_adj[0] / fwd:.2f})")
     return out
 
 

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MPX_ABI_VERSION 3u
+#define MPX_ABI_VERSION 4u
 
 typedef struct mpx_sim mpx_sim;
 
@@ -313,12 +313,16 @@ const char *mpx_last_error(const mpx_sim *sim);
  *              the face values Ms_s (mean over the face's cells) in the LLG
  *              solve and, when the run starts at step 0, through the initial
  *              magnetisation M0 = Ms_s u.
- * The forward states are recomputed from checkpoints taken every
- * `checkpoint_every` steps (0: ceil(sqrt(nsteps))): memory is about
- * nsteps / checkpoint_every + 12 field states, plus, per step of a segment,
- * a tape of film-region and eps-box values (schedule 0).  On return the
- * handle holds the state after nsteps (step counter advanced, probes
- * recorded as by mpx_step).
+ * The run is cut into segments of `checkpoint_every` steps (0:
+ * ceil(sqrt(nsteps))).  Under schedule 0 the reverse sweep reads, per step,
+ * a tape of film-region and eps-box values: the last segments keep the tape
+ * their forward run writes, as far as mpx_set_adjoint_memory allows, and
+ * every other segment takes a checkpoint (a full field state) and is run
+ * again from it, writing the tape, before its reverse steps.  Memory is
+ * about (segments without a kept tape) + 12 field states, plus one
+ * segment's tape, plus the kept tapes.  On return the handle holds the
+ * state after nsteps (step counter advanced, probes recorded as by
+ * mpx_step).
  * Host output buffers; boxes must lie inside the grid.  Synchronous.
  * Errors: MPX_E_INVALID (arguments), MPX_E_STATE (materials / magnetisation
  * not set), MPX_E_NOMEM / MPX_E_DEVICE. */
@@ -358,6 +362,16 @@ mpx_status mpx_adjoint_probe(mpx_sim *sim, int64_t nsteps, int32_t field, const 
  *     half steps (the reference the tape schedule is tested against).
  * Errors: MPX_E_INVALID for another value. */
 mpx_status mpx_set_adjoint_schedule(mpx_sim *sim, int32_t schedule);
+
+/* Device memory the tape schedule may spend on keeping the tapes of the
+ * forward run, so that those segments are not run a second time (the
+ * gradients are the same bits either way):
+ *   -1 (default) as much as fits, with the checkpoints of the other
+ *      segments, in three quarters of the device memory free at the call;
+ *    0 none: every segment is recomputed from its checkpoint;
+ *   >0 at most that many bytes (whole segments' tapes).
+ * Errors: MPX_E_INVALID for a value below -1. */
+mpx_status mpx_set_adjoint_memory(mpx_sim *sim, int64_t max_bytes);
 
 /* ---- Batched stepping (many simulations per launch) --------------------
  *

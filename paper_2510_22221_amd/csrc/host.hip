@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <array>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -70,6 +71,10 @@ struct mpx_sim {
     int parity = 0;
     int fused = 0; // separate passes (the fastest schedule measured on gfx950)
     int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
+    // tape schedule: the most device memory the tapes kept from the forward
+    // run may take (-1: three quarters of the free memory, with the
+    // checkpoints of the other segments; 0: none, every segment recomputed)
+    long long adj_resident = -1;
     int kchunk = 16;
     bool narrow = false; // separate passes on 64 x 4 tiles whatever the width (schedule 6)
     void *d_coef = nullptr;
@@ -1421,6 +1426,7 @@ SnapLayout snap_layout(const mpx_sim *s) {
 struct Tape {
     int K = 0, nf = 0;
     char *buf = nullptr;
+    size_t bytes = 0;
     std::vector<double *> Mf, Mh, B1s, B1n, B2s, B2n; // [f][slot]
     double *loss = nullptr, *box = nullptr;
     long long loss_sz = 0, box_sz = 0;
@@ -1464,6 +1470,7 @@ mpx_status tape_alloc(mpx_sim *s, Tape &t, int K, const int *film_cb, const int 
     put((size_t)std::max<long long>(1, K * t.box_sz) * sizeof(double));
     CK(hipMalloc(&t.buf, off));
     CK(hipMemsetAsync(t.buf, 0, off, s->stream));
+    t.bytes = off;
     size_t q = 0;
     t.Mf.assign((size_t)nf * (K + 1), nullptr);
     t.Mh.assign((size_t)nf * K, nullptr);
@@ -1592,8 +1599,11 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     Snap2 fin;
     AdjHost h;
     Tape tp;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // captured segments: 0 the forward run with the tape and the probes, 1 a
+    // recompute with the tape, 2 the reverse steps
+    hipGraph_t graph[3] = {};
+    hipGraphExec_t gexec[3] = {};
+    char *pages = nullptr; // the tapes kept from the forward run
     bool probe_added = false;
     double *d_lacc = nullptr; // the film-energy loss's own eps_r term per film cell
     auto body = [&]() -> mpx_status {
@@ -1686,17 +1696,93 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
         CK(hipMalloc(&h.d_seg0, sizeof(long long)));
         if ((q = tape_alloc(s, tp, K, LF.cb, eps_box)) != MPX_OK) return q;
         const SnapLayout L = snap_layout(s);
-        std::vector<Snap2 *> all;
-        for (auto &z : cp) {
-            CK(hipMalloc(&z.buf, L.total));
-            all.push_back(&z);
+        // the last npage segments keep the tape their forward run writes (a
+        // page each: no checkpoint and no recompute); the others take a
+        // checkpoint and are recomputed in the reverse sweep
+        int npage = 0;
+        if (s->adj_resident != 0) {
+            const double page = (double)tp.bytes, snap = (double)L.total;
+            if (s->adj_resident > 0) {
+                npage = (int)std::min<double>(ncp, std::floor((double)s->adj_resident / page));
+            } else {
+                size_t fr = 0, tot = 0;
+                CK(hipMemGetInfo(&fr, &tot));
+                const double cap = 0.75 * (double)fr - snap; // less the final state's copy
+                npage = ncp;
+                while (npage > 0 && npage * page + (ncp - npage) * snap > cap) npage--;
+            }
+        }
+        const int g0 = ncp - npage;
+        std::vector<Snap2 *> all; // the checkpoints of segments 0 .. g0 - 1, then the final state
+        for (int g = 0; g < g0; g++) {
+            CK(hipMalloc(&cp[g].buf, L.total));
+            all.push_back(&cp[g]);
         }
         CK(hipMalloc(&fin.buf, L.total));
         all.push_back(&fin);
+        if (npage) CK(hipMalloc(&pages, (size_t)npage * tp.bytes));
         if ((q = snap_tables(s, tp, L, all)) != MPX_OK) return q;
         const int ns = tp.nseg;
         auto tab = [&](int z, int kind) { return tp.d_tab + ((size_t)z * 3 + kind) * ns; };
         const double dt = s->dt;
+        const int nf = (int)s->films.size();
+        auto mslot = [&](int f, int m) { return (void *)tp.Mf[(size_t)f * (K + 1) + m]; };
+        auto mbytes = [&](int f) { return 9 * (size_t)s->films[f].ns * sizeof(double); };
+
+        // a segment of len steps from an integer time with the tape (the
+        // magnetisation in the tape's slots), with the probes in the forward
+        // run; and the adjoint steps of a segment from its tape
+        auto fwd = [&](int len, bool probes) -> mpx_status {
+            KParams<T> p;
+            fill_params<T>(s, p, MODE_INPLACE, s->parity);
+            const int np = (int)s->probes.size();
+            p.films = tvar(tp, 0, V_R1);
+            if (floss) CK(launch_tape_loss<T>(p, film, 0, tp.lossp(0), st, LF.cb));
+            p.films = tvar(tp, 0, V_BR);
+            CK(launch_film<T>(p, nblk, 1, 0, st));
+            p.films = tvar(tp, 0, V_BRC);
+            CK(launch_commit<T>(p, nblk, st));
+            CK(launch_hbulk<T>(p, 1, 0, st));
+            for (int m = 0; m < len; m++) {
+                if (neps > 0) CK(launch_tape_box<T>(p, eps_box, tp.boxp(m), st));
+                CK(launch_epass<T>(p, st));
+                p.films = tvar(tp, m, V_P1);
+                CK(launch_film<T>(p, nblk, 1, 0, st));
+                if (probes) CK(launch_probes<T>(p, np, s->probe_maxpart, st));
+                if (m + 1 < len) {
+                    if (floss) CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
+                    p.films = tvar(tp, m, V_P2);
+                    CK(launch_film<T>(p, nblk, 2, 0, st));
+                    CK(launch_hbulk<T>(p, 2, 1, st));
+                } else {
+                    p.films = tvar(tp, m, V_C);
+                    CK(launch_commit<T>(p, nblk, st));
+                    CK(launch_hbulk<T>(p, 1, 1, st));
+                }
+            }
+            return MPX_OK;
+        };
+        std::function<mpx_status(int)> rev;
+        // one captured graph per kind serves every full-length segment
+        auto run = [&](int kind, int len) -> mpx_status {
+            auto direct = [&]() { return kind == 2 ? rev(len) : fwd(len, kind == 0); };
+            if (len != K || ncp < 2 || s->graph_steps <= 0) return direct();
+            if (!gexec[kind]) {
+                CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                const mpx_status e1 = direct();
+                hipGraph_t gg = nullptr;
+                const hipError_t e2 = hipStreamEndCapture(st, &gg);
+                if (e1 != MPX_OK) {
+                    if (gg) (void)hipGraphDestroy(gg);
+                    return e1;
+                }
+                CK(e2);
+                graph[kind] = gg;
+                CK(hipGraphInstantiate(&gexec[kind], gg, nullptr, nullptr, 0));
+            }
+            CK(hipGraphLaunch(gexec[kind], st));
+            return MPX_OK;
+        };
 
         // forward: the loss through a temporary probe (film energy, or the
         // weighted E component)
@@ -1723,14 +1809,32 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             drop_graph(s);
             if ((q = upload_probes(s)) != MPX_OK) return q;
         }
+        std::vector<long long> pstep(ncp, 0);
         for (int g = 0; g < ncp; g++) {
             const long long c0 = (long long)g * K, len = std::min<long long>(K, N - c0);
-            CK(launch_copy_segs(tab(g, 0), ns, L.nblk, st));
-            cp[g].step = s->step;
-            if ((q = enqueue_steps<T>(s, len)) != MPX_OK) return q;
+            if (g < g0) {
+                CK(launch_copy_segs(tab(g, 0), ns, L.nblk, st));
+                cp[g].step = s->step;
+                if ((q = enqueue_steps<T>(s, len)) != MPX_OK) return q;
+                s->step += len;
+                continue;
+            }
+            // a segment that keeps its tape: its magnetisation starts in the
+            // tape's first slot and ends in slot len, from where it goes back
+            // to the handle and to the next segment's first slot
+            if (g == g0)
+                for (int f = 0; f < nf; f++)
+                    CK(hipMemcpyAsync(mslot(f, 0), s->films[f].M, mbytes(f), hipMemcpyDeviceToDevice, st));
+            pstep[g] = s->step;
+            if ((q = run(0, (int)len)) != MPX_OK) return q;
             s->step += len;
+            CK(hipMemcpyAsync(pages + (size_t)(g - g0) * tp.bytes, tp.buf, tp.bytes, hipMemcpyDeviceToDevice, st));
+            for (int f = 0; f < nf; f++) {
+                CK(hipMemcpyAsync(s->films[f].M, mslot(f, (int)len), mbytes(f), hipMemcpyDeviceToDevice, st));
+                CK(hipMemcpyAsync(mslot(f, 0), mslot(f, (int)len), mbytes(f), hipMemcpyDeviceToDevice, st));
+            }
         }
-        CK(launch_copy_segs(tab(ncp, 0), ns, L.nblk, st));
+        CK(launch_copy_segs(tab(g0, 0), ns, L.nblk, st));
         fin.step = s->step;
         std::vector<double> tr(N);
         CK(hipMemcpyAsync(tr.data(), s->probes.back().dev.data, N * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1783,33 +1887,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             CK(launch_add_one<T>((T *)h.lE[ls.field], pw_slot, S * ls.w[N - 1], st));
         }
 
-        // recompute a segment of len steps with the tape, then its adjoint
-        auto segment = [&](int len) -> mpx_status {
-            KParams<T> p;
-            fill_params<T>(s, p, MODE_INPLACE, s->parity);
-            p.films = tvar(tp, 0, V_R1);
-            if (floss) CK(launch_tape_loss<T>(p, film, 0, tp.lossp(0), st, LF.cb));
-            p.films = tvar(tp, 0, V_BR);
-            CK(launch_film<T>(p, nblk, 1, 0, st));
-            p.films = tvar(tp, 0, V_BRC);
-            CK(launch_commit<T>(p, nblk, st));
-            CK(launch_hbulk<T>(p, 1, 0, st));
-            for (int m = 0; m < len; m++) {
-                if (neps > 0) CK(launch_tape_box<T>(p, eps_box, tp.boxp(m), st));
-                CK(launch_epass<T>(p, st));
-                p.films = tvar(tp, m, V_P1);
-                CK(launch_film<T>(p, nblk, 1, 0, st));
-                if (m + 1 < len) {
-                    if (floss) CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
-                    p.films = tvar(tp, m, V_P2);
-                    CK(launch_film<T>(p, nblk, 2, 0, st));
-                    CK(launch_hbulk<T>(p, 2, 1, st));
-                } else {
-                    p.films = tvar(tp, m, V_C);
-                    CK(launch_commit<T>(p, nblk, st));
-                    CK(launch_hbulk<T>(p, 1, 1, st));
-                }
-            }
+        rev = [&](int len) -> mpx_status {
             for (int m = len - 1; m >= 0; m--) {
                 if (d_lacc) {
                     // the loss's eps_r term of the step's input state
@@ -1867,28 +1945,18 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
         for (int g = ncp - 1; g >= 0; g--) {
             const long long c0 = (long long)g * K;
             const int len = (int)std::min<long long>(K, N - c0);
-            CK(launch_copy_segs(tab(g, 2), ns, L.nblk, st));
-            s->step = cp[g].step;
-            CK(launch_set_step(s->d_step, cp[g].step, st));
-            CK(launch_set_step(h.d_seg0, c0, st));
-            if (len == K && ncp > 1 && s->graph_steps > 0) {
-                if (!gexec) {
-                    CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                    q = segment(len);
-                    hipGraph_t gg = nullptr;
-                    const hipError_t e = hipStreamEndCapture(st, &gg);
-                    if (q != MPX_OK) {
-                        if (gg) (void)hipGraphDestroy(gg);
-                        return q;
-                    }
-                    CK(e);
-                    graph = gg;
-                    CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-                }
-                CK(hipGraphLaunch(gexec, st));
-            } else if ((q = segment(len)) != MPX_OK) {
-                return q;
+            if (g >= g0) {
+                CK(hipMemcpyAsync(tp.buf, pages + (size_t)(g - g0) * tp.bytes, tp.bytes, hipMemcpyDeviceToDevice,
+                                  st));
+                s->step = pstep[g];
+            } else {
+                CK(launch_copy_segs(tab(g, 2), ns, L.nblk, st));
+                s->step = cp[g].step;
             }
+            CK(launch_set_step(s->d_step, s->step, st));
+            CK(launch_set_step(h.d_seg0, c0, st));
+            if (g < g0 && (q = run(1, len)) != MPX_OK) return q;
+            if ((q = run(2, len)) != MPX_OK) return q;
         }
         // the initial magnetisation M0 = Ms u
         if (step0 == 0 && s->have_u) CK(launch_adj_init_ms(s->d_blocktab, nblk, s->d_films, h.d_af, s->u, st));
@@ -1903,7 +1971,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
         for (long long t = 0; t < neps; t++) geps[t] /= S;
         if ((q = film_grads(s, h, S, ms_box, gH0, gms)) != MPX_OK) return q;
         // leave the handle at the end of the forward run
-        CK(launch_copy_segs(tab(ncp, 1), ns, L.nblk, st));
+        CK(launch_copy_segs(tab(g0, 1), ns, L.nblk, st));
         s->step = fin.step;
         CK(launch_set_step(s->d_step, fin.step, st));
         CK(hipStreamSynchronize(st));
@@ -1921,8 +1989,11 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     if (r != MPX_OK) (void)hipStreamSynchronize(st);
     (void)hipFree(d_w);
     (void)hipFree(d_lacc);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int k = 0; k < 3; k++) {
+        if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+        if (graph[k]) (void)hipGraphDestroy(graph[k]);
+    }
+    (void)hipFree(pages);
     s->fused = saved_fused;
     adj_free(h);
     tape_free(tp);
@@ -3066,6 +3137,14 @@ mpx_status mpx_set_adjoint_schedule(mpx_sim *s, int32_t schedule) {
     if (r != MPX_OK) return r;
     if (schedule < 0 || schedule > 1) return fail(s, MPX_E_INVALID, "adjoint schedule");
     s->adj_schedule = schedule;
+    return MPX_OK;
+}
+
+mpx_status mpx_set_adjoint_memory(mpx_sim *s, int64_t max_bytes) {
+    mpx_status r = check_live(s);
+    if (r != MPX_OK) return r;
+    if (max_bytes < -1) return fail(s, MPX_E_INVALID, "adjoint memory");
+    s->adj_resident = max_bytes;
     return MPX_OK;
 }
 

@@ -25,7 +25,7 @@ F64, F32 = 0, 1
 PEC, PML, PERIODIC = 0, 1, 2
 EX, EY, EZ, HX, HY, HZ, MXF, MYF, MZF, DMXF, DMYF, DMZF = range(12)
 PROBE_FIELD, PROBE_MEAN_M, PROBE_FILM_ENERGY, PROBE_EM_ENERGY = 0, 1, 2, 3
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 STATUS = {0: "MPX_OK", 1: "MPX_E_INVALID", 2: "MPX_E_STATE", 3: "MPX_E_NOMEM", 4: "MPX_E_DEVICE",
           5: "MPX_E_UNSUPPORTED", 6: "MPX_E_RANGE", 7: "MPX_E_NONFINITE"}
@@ -35,7 +35,7 @@ EXPORTS = ["mpx_abi_version", "mpx_create", "mpx_destroy", "mpx_query_field", "m
            "mpx_set_bias", "mpx_init_magnetization", "mpx_add_source", "mpx_add_probe", "mpx_step",
            "mpx_synchronize", "mpx_read_field", "mpx_read_field_region", "mpx_write_field", "mpx_field_storage", "mpx_read_probe", "mpx_energy", "mpx_energy_noalloc", "mpx_info",
            "mpx_film_box", "mpx_set_graph_steps", "mpx_set_schedule", "mpx_set_timing", "mpx_kernel_time",
-           "mpx_last_error", "mpx_adjoint", "mpx_adjoint_probe", "mpx_set_adjoint_schedule", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
+           "mpx_last_error", "mpx_adjoint", "mpx_adjoint_probe", "mpx_set_adjoint_schedule", "mpx_set_adjoint_memory", "mpx_batch_create", "mpx_batch_destroy", "mpx_batch_set_schedule",
            "mpx_batch_set_graph_steps", "mpx_batch_step", "mpx_batch_synchronize", "mpx_batch_last_error"]
 
 
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
         "mpx_adjoint_probe": (I32, [P, I64, I32, C.POINTER(I32), P, I32, C.POINTER(I32), C.POINTER(I32),
                                     C.POINTER(D), C.POINTER(D), P, P]),
         "mpx_set_adjoint_schedule": (I32, [P, I32]),
+        "mpx_set_adjoint_memory": (I32, [P, C.c_int64]),
         "mpx_batch_create": (I32, [C.POINTER(P), I32, C.POINTER(P)]),
         "mpx_batch_destroy": (I32, [P]),
         "mpx_batch_set_schedule": (I32, [P, I32, I32]),
@@ -368,6 +369,12 @@ class Sim:
     def set_adjoint_schedule(self, schedule: int):
         """0: tape schedule (default); 1: plain recompute-per-step schedule."""
         self._ck(self._L.mpx_set_adjoint_schedule(self._h, int(schedule)), "set_adjoint_schedule")
+
+    def set_adjoint_memory(self, max_bytes: int):
+        """Device memory the tape schedule may keep forward tapes in: -1 (default)
+        three quarters of the free memory, 0 none (every segment recomputed),
+        > 0 a cap in bytes."""
+        self._ck(self._L.mpx_set_adjoint_memory(self._h, int(max_bytes)), "set_adjoint_memory")
 
     def films(self):
         out = []

@@ -343,3 +343,50 @@ def test_tape_schedule_from_a_later_step():
         sc = float(np.abs(b[key]).max())
         assert sc > 0, key
         assert float(np.abs(a[key] - b[key]).max()) <= 1e-10 * sc, key
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+def test_kept_tapes_match_recompute(prec):
+    """Segments that keep the tape of their forward run (no checkpoint, no
+    second run) give the gradients of recomputing every segment from its
+    checkpoint: caps from none to all of the twelve segments' tapes, so that
+    some runs keep only the last few."""
+    w = small_case(True)
+    n, n0, K = 60, 20, 5
+    fc = np.argwhere(w.ids == 3)
+    lo, hi = fc.min(axis=0), fc.max(axis=0)  # (k, j, i)
+    eps_box = (max(0, lo[2] - 2), max(0, lo[1] - 1), max(0, lo[0] - 3), 6, 4, 3)
+    ms_box = (lo[2], lo[1], lo[0], hi[2] - lo[2] + 1, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1)
+
+    def run(cap):
+        g = mpx.from_workload(w, precision=prec)
+        g.set_adjoint_memory(cap)
+        r = g.adjoint(n, n0, film=0, checkpoint_every=K, eps_box=eps_box, ms_box=ms_box)
+        r["fields"] = [g.get(f) for f in range(9)]
+        r["step"] = g.info()["step"]
+        g.close()
+        return r
+
+    ref = run(0)
+    for cap in [-1] + [2 ** e for e in range(14, 32, 2)]:
+        say(f"kept tapes: precision {prec} cap {cap}")
+        r = run(cap)
+        assert r["step"] == ref["step"] == n
+        for f in range(9):
+            a, b = r["fields"][f], ref["fields"][f]
+            if prec == mpx.F64:
+                assert np.array_equal(a, b), (cap, f)
+            else:
+                assert float(np.abs(a - b).max()) <= 1e-6 * max(float(np.abs(b).max()), 1e-300), (cap, f)
+        if prec == mpx.F64:
+            assert r["loss"] == ref["loss"], cap
+            for key in ("dH0", "deps", "dMs"):
+                assert np.array_equal(r[key], ref[key]), (cap, key)
+        else:
+            assert r["loss"] == pytest.approx(ref["loss"], rel=1e-6), cap
+            for key in ("dH0", "deps", "dMs"):
+                sc = float(np.abs(ref[key]).max())
+                assert sc > 0, key
+                err = float(np.abs(r[key] - ref[key]).max()) / sc
+                say(f"  {key}: max |kept - recomputed| / max = {err:.2e}")
+                assert err <= 1e-6, (cap, key)
