@@ -964,22 +964,44 @@ __device__ __noinline__ EdgeCoef<T> edge_coef_mixed(const uint8_t *id, const Mat
     return r;
 }
 
-template <typename T, int C>
-__device__ __forceinline__ bool edge_coef(const KParams<T> &p, const int *idx, long long q, T &ca, T &cb) {
-    for (int a = 0; a < 3; a++)
-        if (a != C && !p.per[a] && idx[a] == 0) return false;
-    const uint8_t cl = p.cls[q];
+// the E-step coefficients of the three edges of slot idx (q its slot): one
+// class read, then the three table entries together
+template <typename T>
+__device__ __forceinline__ void edge_coefs(const KParams<T> &p, const int *idx, long long q, T *ca, T *cb, bool *ok) {
+    const int cl = p.cls[q];
+    ca[0] = ca[1] = ca[2] = cb[0] = cb[1] = cb[2] = T(0);
+    ok[0] = ok[1] = ok[2] = false;
     if (cl != kMixed) {
-        const CoefDev<T> cd = p.coef[kCoefPerClass * cl + C];
-        ca = cd.ca;
-        cb = cd.cb;
-        return !cd.pec;
+        const CoefDev<T> c0 = p.coef[kCoefPerClass * cl], c1 = p.coef[kCoefPerClass * cl + 1],
+                         c2 = p.coef[kCoefPerClass * cl + 2];
+        ca[0] = c0.ca;
+        cb[0] = c0.cb;
+        ok[0] = !c0.pec;
+        ca[1] = c1.ca;
+        cb[1] = c1.cb;
+        ok[1] = !c1.pec;
+        ca[2] = c2.ca;
+        cb[2] = c2.cb;
+        ok[2] = !c2.pec;
     }
-    const EdgeCoef<T> r = edge_coef_mixed<T>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.per[0], p.per[1], p.per[2], p.px,
-                                             p.eps0, p.dt, C, idx[0], idx[1], idx[2]);
-    ca = r.ca;
-    cb = r.cb;
-    return r.ok;
+    // an edge on a lower wall (a non-periodic axis other than its own) is held
+    // at zero; a mixed slot's edges read the four cells around them, which
+    // exist off the walls only
+    for (int C = 0; C < 3; C++) {
+        bool wall = false;
+        for (int a = 0; a < 3; a++)
+            if (a != C && !p.per[a] && idx[a] == 0) wall = true;
+        if (wall) {
+            ca[C] = cb[C] = T(0);
+            ok[C] = false;
+        } else if (cl == kMixed) {
+            const EdgeCoef<T> r = edge_coef_mixed<T>(p.id, p.mat, p.n[0], p.n[1], p.n[2], p.per[0], p.per[1],
+                                                     p.per[2], p.px, p.eps0, p.dt, C, idx[0], idx[1], idx[2]);
+            ca[C] = r.ca;
+            cb[C] = r.cb;
+            ok[C] = r.ok;
+        }
+    }
 }
 
 // the first film whose reach holds the face slot idx, its region index lr
@@ -1047,9 +1069,19 @@ __device__ __forceinline__ long long region_index_folded(const int *n, const int
     return li;
 }
 
+// a new lambda psi value held for a store after the thread's last load
+// (q1 / q2 < 0: none)
+template <typename T>
+struct PsiOut {
+    long long q1 = -1, q2 = -1;
+    T v1 = T(0), v2 = T(0);
+};
+
 // curl-part adjoints (aD0, aD1) of the face of family F at slot f (in the
 // domain), general case: from the film region's table, or from lambda H with
-// the CPML recursions (own: also store lambda psiH after the map)
+// the CPML recursions (own: also store lambda psiH after the map; holding it
+// for a store after the thread's last load measured slower in float64, where
+// the extra registers cost a wave per SIMD)
 template <typename T, int F, int FILM>
 __device__ __forceinline__ void hface(const AdjParams<T> &A, const int *f, bool own, T &aD0, T &aD1) {
     constexpr int F1 = (F + 1) % 3, F2 = (F + 2) % 3;
@@ -1186,6 +1218,13 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
     const int t[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
     const uint8_t fl = A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)];
+    // lambda E and the edge coefficients (one class read) before the faces
+    T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
+    T ca[3], cb[3];
+    bool ok[3];
+    edge_coefs<T>(p, t, q, ca, cb, ok);
+    const T ca0 = ca[0], cb0 = cb[0], ca1 = ca[1], cb1 = cb[1], ca2 = ca[2], cb2 = cb[2];
+    const bool v0 = ok[0], v1 = ok[1], v2 = ok[2];
     // dd: the transposed curl's six differences (see hfield_general)
     T dd[6];
     if (fl == 0) {
@@ -1217,7 +1256,6 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
     } else {
         hfield_general<T, 0>(A, t, dd);
     }
-    T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
     if (SCALE && A.btape) {
         // dL/dca += lambda E' E^n, dL/dcb += lambda E' x^n over the eps box
         const int r[3] = {A.bs[0] + 1, A.bs[1] + 1, A.bs[2] + 1};
@@ -1232,10 +1270,6 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
             }
         }
     }
-    T ca0, cb0, ca1, cb1, ca2, cb2;
-    const bool v0 = edge_coef<T, 0>(p, t, q, ca0, cb0);
-    const bool v1 = edge_coef<T, 1>(p, t, q, ca1, cb1);
-    const bool v2 = edge_coef<T, 2>(p, t, q, ca2, cb2);
     if (SCALE) {
         l0 = v0 ? ca0 * l0 : T(0);
         l1 = v1 ? ca1 * l1 : T(0);
@@ -1275,8 +1309,8 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
 // and X+2 (in2 -> out2); own: store lambda psiE after the map.  (On a wall or
 // PEC edge mu is zero, and so stays its lambda psiE.)
 template <typename T, int X, int PML>
-__device__ __forceinline__ void eedge(const AdjParams<T> &A, const int *e, bool own, const T *in1, const T *in2,
-                                      T *out1, T *out2, T &eD0, T &eD1) {
+__device__ __forceinline__ void eedge(const AdjParams<T> &A, const int *e, const T *in1, const T *in2, PsiOut<T> *own,
+                                      T &eD0, T &eD1) {
     constexpr int X1 = (X + 1) % 3, X2 = (X + 2) % 3;
     const KParams<T> &p = A.p;
     const T lx = A.mu[X][p.slot(e[0], e[1], e[2])];
@@ -1287,13 +1321,19 @@ __device__ __forceinline__ void eedge(const AdjParams<T> &A, const int *e, bool 
         if (p.psiE[X][X1] && (a1 < p.nlo[X1] || a1 >= p.n[X1] - p.nhi[X1])) {
             const long long q1 = p.psi_index(X1, e);
             const T aps = in1[q1] + lx;
-            if (own) out1[q1] = p.bE[X1][a1] * aps;
+            if (own) {
+                own->q1 = q1;
+                own->v1 = p.bE[X1][a1] * aps;
+            }
             eD0 = lx + p.cE[X1][a1] * aps;
         }
         if (p.psiE[X][X2] && (a2 < p.nlo[X2] || a2 >= p.n[X2] - p.nhi[X2])) {
             const long long q2 = p.psi_index(X2, e);
             const T aps = in2[q2] - lx;
-            if (own) out2[q2] = p.bE[X2][a2] * aps;
+            if (own) {
+                own->q2 = q2;
+                own->v2 = p.bE[X2][a2] * aps;
+            }
             eD1 = -lx + p.cE[X2][a2] * aps;
         }
     }
@@ -1312,36 +1352,49 @@ __device__ __forceinline__ void efield_body(const AdjParams<T> &A, const int *t,
     const T *i0a = par ? A.lpsiE2[0][1] : A.lpsiE[0][1], *i0b = par ? A.lpsiE2[0][2] : A.lpsiE[0][2];
     const T *i1a = par ? A.lpsiE2[1][2] : A.lpsiE[1][2], *i1b = par ? A.lpsiE2[1][0] : A.lpsiE[1][0];
     const T *i2a = par ? A.lpsiE2[2][0] : A.lpsiE[2][0], *i2b = par ? A.lpsiE2[2][1] : A.lpsiE[2][1];
-    T *o0a = par ? A.lpsiE[0][1] : A.lpsiE2[0][1], *o0b = par ? A.lpsiE[0][2] : A.lpsiE2[0][2];
-    T *o1a = par ? A.lpsiE[1][2] : A.lpsiE2[1][2], *o1b = par ? A.lpsiE[1][0] : A.lpsiE2[1][0];
-    T *o2a = par ? A.lpsiE[2][0] : A.lpsiE2[2][0], *o2b = par ? A.lpsiE[2][1] : A.lpsiE2[2][1];
+    // every load of the thread before any store: lambda H of the slot, then
+    // the edges (own edges' new lambda psiE held until the end; the sets read
+    // and written are different arrays)
+    const T lh0 = A.lH[0][q], lh1 = A.lH[1][q], lh2 = A.lH[2][q];
+    PsiOut<T> w0, w1, w2;
     T o0[3], o1[3], x0, x1;
-    eedge<T, 0, PML>(A, t, true, i0a, i0b, o0a, o0b, o0[0], o1[0]);
-    eedge<T, 1, PML>(A, t, true, i1a, i1b, o1a, o1b, o0[1], o1[1]);
-    eedge<T, 2, PML>(A, t, true, i2a, i2b, o2a, o2b, o0[2], o1[2]);
+    eedge<T, 0, PML>(A, t, i0a, i0b, PML ? &w0 : nullptr, o0[0], o1[0]);
+    eedge<T, 1, PML>(A, t, i1a, i1b, PML ? &w1 : nullptr, o0[1], o1[1]);
+    eedge<T, 2, PML>(A, t, i2a, i2b, PML ? &w2 : nullptr, o0[2], o1[2]);
     T n1p2 = T(0), n2p1 = T(0), n2p0 = T(0), n0p2 = T(0), n0p1 = T(0), n1p0 = T(0);
     int u[3];
     if (nb<1>(p.n, p.per, t, 2, u)) {
-        eedge<T, 1, PML>(A, u, false, i1a, i1b, o1a, o1b, x0, x1);
+        eedge<T, 1, PML>(A, u, i1a, i1b, nullptr, x0, x1);
         n1p2 = x0;
-        eedge<T, 0, PML>(A, u, false, i0a, i0b, o0a, o0b, x0, x1);
+        eedge<T, 0, PML>(A, u, i0a, i0b, nullptr, x0, x1);
         n0p2 = x1;
     }
     if (nb<1>(p.n, p.per, t, 1, u)) {
-        eedge<T, 2, PML>(A, u, false, i2a, i2b, o2a, o2b, x0, x1);
+        eedge<T, 2, PML>(A, u, i2a, i2b, nullptr, x0, x1);
         n2p1 = x1;
-        eedge<T, 0, PML>(A, u, false, i0a, i0b, o0a, o0b, x0, x1);
+        eedge<T, 0, PML>(A, u, i0a, i0b, nullptr, x0, x1);
         n0p1 = x0;
     }
     if (nb<1>(p.n, p.per, t, 0, u)) {
-        eedge<T, 2, PML>(A, u, false, i2a, i2b, o2a, o2b, x0, x1);
+        eedge<T, 2, PML>(A, u, i2a, i2b, nullptr, x0, x1);
         n2p0 = x0;
-        eedge<T, 1, PML>(A, u, false, i1a, i1b, o1a, o1b, x0, x1);
+        eedge<T, 1, PML>(A, u, i1a, i1b, nullptr, x0, x1);
         n1p0 = x1;
     }
-    A.lH[0][q] = A.lH[0][q] + (dif(o0[1] - n1p2, T(0), p.dT[2], p.invd[2]) + dif(o1[2] - n2p1, T(0), p.dT[1], p.invd[1]));
-    A.lH[1][q] = A.lH[1][q] + (dif(o0[2] - n2p0, T(0), p.dT[0], p.invd[0]) + dif(o1[0] - n0p2, T(0), p.dT[2], p.invd[2]));
-    A.lH[2][q] = A.lH[2][q] + (dif(o0[0] - n0p1, T(0), p.dT[1], p.invd[1]) + dif(o1[1] - n1p0, T(0), p.dT[0], p.invd[0]));
+    if (PML) {
+        T *o0a = par ? A.lpsiE[0][1] : A.lpsiE2[0][1], *o0b = par ? A.lpsiE[0][2] : A.lpsiE2[0][2];
+        T *o1a = par ? A.lpsiE[1][2] : A.lpsiE2[1][2], *o1b = par ? A.lpsiE[1][0] : A.lpsiE2[1][0];
+        T *o2a = par ? A.lpsiE[2][0] : A.lpsiE2[2][0], *o2b = par ? A.lpsiE[2][1] : A.lpsiE2[2][1];
+        if (w0.q1 >= 0) o0a[w0.q1] = w0.v1;
+        if (w0.q2 >= 0) o0b[w0.q2] = w0.v2;
+        if (w1.q1 >= 0) o1a[w1.q1] = w1.v1;
+        if (w1.q2 >= 0) o1b[w1.q2] = w1.v2;
+        if (w2.q1 >= 0) o2a[w2.q1] = w2.v1;
+        if (w2.q2 >= 0) o2b[w2.q2] = w2.v2;
+    }
+    A.lH[0][q] = lh0 + (dif(o0[1] - n1p2, T(0), p.dT[2], p.invd[2]) + dif(o1[2] - n2p1, T(0), p.dT[1], p.invd[1]));
+    A.lH[1][q] = lh1 + (dif(o0[2] - n2p0, T(0), p.dT[0], p.invd[0]) + dif(o1[0] - n0p2, T(0), p.dT[2], p.invd[2]));
+    A.lH[2][q] = lh2 + (dif(o0[0] - n0p1, T(0), p.dT[1], p.invd[1]) + dif(o1[1] - n1p0, T(0), p.dT[0], p.invd[0]));
 }
 
 template <typename T>
