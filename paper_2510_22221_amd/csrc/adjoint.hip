@@ -1029,6 +1029,15 @@ __device__ __forceinline__ bool nb(const int *n, const int *per, const int *t, i
     return q[a] >= 0;
 }
 
+// the neighbour t + D e_a as nb, or t itself where nb finds none (false):
+// the caller evaluates there and drops the value
+template <int D>
+__device__ __forceinline__ bool nb_or_self(const int *n, const int *per, const int *t, int a, int *q) {
+    const bool ok = nb<D>(n, per, t, a, q);
+    if (!ok) q[a] = t[a];
+    return ok;
+}
+
 // the film region's faces: the general face adjoint (magnetic faces, faces
 // the solves read), lambda H and lambda M updated in place, the curl-part
 // adjoints stored for the field pass
@@ -1079,9 +1088,10 @@ struct PsiOut {
 
 // curl-part adjoints (aD0, aD1) of the face of family F at slot f (in the
 // domain), general case: from the film region's table, or from lambda H with
-// the CPML recursions (own: also store lambda psiH after the map; holding it
-// for a store after the thread's last load measured slower in float64, where
-// the extra registers cost a wave per SIMD)
+// the CPML recursions (own: also store lambda psiH after the map).  In
+// float32 every load is unconditional (a lane outside a slab reads its
+// lambda H again in place of the slab state and drops it), so that the loads
+// of all of a thread's faces can be in flight at once.
 template <typename T, int F, int FILM>
 __device__ __forceinline__ void hface(const AdjParams<T> &A, const int *f, bool own, T &aD0, T &aD1) {
     constexpr int F1 = (F + 1) % 3, F2 = (F + 2) % 3;
@@ -1096,23 +1106,62 @@ __device__ __forceinline__ void hface(const AdjParams<T> &A, const int *f, bool 
             return;
         }
     }
-    const T lH = A.lH[F][p.slot(f[0], f[1], f[2])];
-    const T g1 = -p.hc * lH, g2 = p.hc * lH;
-    aD0 = g1;
-    aD1 = g2;
+    const T *hp = A.lH[F] + p.slot(f[0], f[1], f[2]);
     const int a1 = f[F1], a2 = f[F2];
-    if (p.psiH[F][F1] && (a1 < p.nlo[F1] || a1 >= p.n[F1] - p.nhi[F1])) {
-        const long long qq = p.psi_index(F1, f);
-        const T aps = A.lpsiH[F][F1][qq] + g1;
-        if (own) A.lpsiHo[F][F1][qq] = p.bH[F1][a1] * aps;
-        aD0 = g1 + p.cH[F1][a1] * aps;
+    const bool s1 = p.psiH[F][F1] && (a1 < p.nlo[F1] || a1 >= p.n[F1] - p.nhi[F1]);
+    const bool s2 = p.psiH[F][F2] && (a2 < p.nlo[F2] || a2 >= p.n[F2] - p.nhi[F2]);
+    if constexpr (sizeof(T) == 8) {
+        // float64: the slab state loaded where needed only (the unconditional
+        // form's registers cost a wave per SIMD here, and it measured slower)
+        const T lH = *hp;
+        const T g1 = -p.hc * lH, g2 = p.hc * lH;
+        aD0 = g1;
+        aD1 = g2;
+        if (s1) {
+            const long long q1 = p.psi_index(F1, f);
+            const T aps = A.lpsiH[F][F1][q1] + g1;
+            if (own) A.lpsiHo[F][F1][q1] = p.bH[F1][a1] * aps;
+            aD0 = g1 + p.cH[F1][a1] * aps;
+        }
+        if (s2) {
+            const long long q2 = p.psi_index(F2, f);
+            const T aps = A.lpsiH[F][F2][q2] + g2;
+            if (own) A.lpsiHo[F][F2][q2] = p.bH[F2][a2] * aps;
+            aD1 = g2 + p.cH[F2][a2] * aps;
+        }
+    } else {
+        const long long q1 = s1 ? p.psi_index(F1, f) : 0, q2 = s2 ? p.psi_index(F2, f) : 0;
+        const T lH = *hp;
+        const T ps1 = *(s1 ? A.lpsiH[F][F1] + q1 : hp), ps2 = *(s2 ? A.lpsiH[F][F2] + q2 : hp);
+        const T b1 = *(s1 ? p.bH[F1] + a1 : hp), c1 = *(s1 ? p.cH[F1] + a1 : hp);
+        const T b2 = *(s2 ? p.bH[F2] + a2 : hp), c2 = *(s2 ? p.cH[F2] + a2 : hp);
+        const T g1 = -p.hc * lH, g2 = p.hc * lH;
+        aD0 = g1;
+        aD1 = g2;
+        if (s1) {
+            const T aps = ps1 + g1;
+            if (own) A.lpsiHo[F][F1][q1] = b1 * aps;
+            aD0 = g1 + c1 * aps;
+        }
+        if (s2) {
+            const T aps = ps2 + g2;
+            if (own) A.lpsiHo[F][F2][q2] = b2 * aps;
+            aD1 = g2 + c2 * aps;
+        }
     }
-    if (p.psiH[F][F2] && (a2 < p.nlo[F2] || a2 >= p.n[F2] - p.nhi[F2])) {
-        const long long qq = p.psi_index(F2, f);
-        const T aps = A.lpsiH[F][F2][qq] + g2;
-        if (own) A.lpsiHo[F][F2][qq] = p.bH[F2][a2] * aps;
-        aD1 = g2 + p.cH[F2][a2] * aps;
+}
+
+// float64: a neighbour face of family F at t - e_axis, false past a wall
+// (values zero)
+template <typename T, int F, int FILM>
+__device__ __forceinline__ bool hface_nb(const AdjParams<T> &A, const int *t, int axis, T &x0, T &x1) {
+    int u[3];
+    if (!nb<-1>(A.p.n, A.p.per, t, axis, u)) {
+        x0 = x1 = T(0);
+        return false;
     }
+    hface<T, F, FILM>(A, u, false, x0, x1);
+    return true;
 }
 
 // the loss term of the state at the start of the step (film-energy
@@ -1162,50 +1211,53 @@ __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, l
 template <typename T, int FILM>
 __device__ __forceinline__ void hfield_general(const AdjParams<T> &A, const int *t, T *d) {
     const KParams<T> &p = A.p;
-    T a, b, x0, x1, n;
-    int u[3];
-    // own face of family 1: with the family-1 faces at k - 1 and i - 1
-    hface<T, 1, FILM>(A, t, true, a, b);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 2, u)) {
+    T a, b, x0, x1;
+    bool ok;
+    if constexpr (sizeof(T) == 8) {
+        // own face of family 1: with the family-1 faces at k - 1 and i - 1
+        hface<T, 1, FILM>(A, t, true, a, b);
+        ok = hface_nb<T, 1, FILM>(A, t, 2, x0, x1);
+        d[0] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[2], p.invd[2]);
+        ok = hface_nb<T, 1, FILM>(A, t, 0, x0, x1);
+        d[5] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[0], p.invd[0]);
+        // family 2: with the family-2 faces at j - 1 and i - 1
+        hface<T, 2, FILM>(A, t, true, a, b);
+        ok = hface_nb<T, 2, FILM>(A, t, 1, x0, x1);
+        d[1] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[1], p.invd[1]);
+        ok = hface_nb<T, 2, FILM>(A, t, 0, x0, x1);
+        d[2] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[0], p.invd[0]);
+        // family 0: with the family-0 faces at k - 1 and j - 1
+        hface<T, 0, FILM>(A, t, true, a, b);
+        ok = hface_nb<T, 0, FILM>(A, t, 2, x0, x1);
+        d[3] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[2], p.invd[2]);
+        ok = hface_nb<T, 0, FILM>(A, t, 1, x0, x1);
+        d[4] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[1], p.invd[1]);
+    } else {
+        // the same in float32 with every neighbour evaluated (one past a wall
+        // at the own slot, its values dropped): no load waits on a branch
+        int u[3];
+        hface<T, 1, FILM>(A, t, true, a, b);
+        ok = nb_or_self<-1>(p.n, p.per, t, 2, u);
         hface<T, 1, FILM>(A, u, false, x0, x1);
-        n = x0;
-    }
-    d[0] = dif(n - a, T(0), p.dT[2], p.invd[2]);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 0, u)) {
+        d[0] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[2], p.invd[2]);
+        ok = nb_or_self<-1>(p.n, p.per, t, 0, u);
         hface<T, 1, FILM>(A, u, false, x0, x1);
-        n = x1;
-    }
-    d[5] = dif(n - b, T(0), p.dT[0], p.invd[0]);
-    // family 2: with the family-2 faces at j - 1 and i - 1
-    hface<T, 2, FILM>(A, t, true, a, b);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 1, u)) {
+        d[5] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[0], p.invd[0]);
+        hface<T, 2, FILM>(A, t, true, a, b);
+        ok = nb_or_self<-1>(p.n, p.per, t, 1, u);
         hface<T, 2, FILM>(A, u, false, x0, x1);
-        n = x1;
-    }
-    d[1] = dif(n - b, T(0), p.dT[1], p.invd[1]);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 0, u)) {
+        d[1] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[1], p.invd[1]);
+        ok = nb_or_self<-1>(p.n, p.per, t, 0, u);
         hface<T, 2, FILM>(A, u, false, x0, x1);
-        n = x0;
-    }
-    d[2] = dif(n - a, T(0), p.dT[0], p.invd[0]);
-    // family 0: with the family-0 faces at k - 1 and j - 1
-    hface<T, 0, FILM>(A, t, true, a, b);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 2, u)) {
+        d[2] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[0], p.invd[0]);
+        hface<T, 0, FILM>(A, t, true, a, b);
+        ok = nb_or_self<-1>(p.n, p.per, t, 2, u);
         hface<T, 0, FILM>(A, u, false, x0, x1);
-        n = x1;
-    }
-    d[3] = dif(n - b, T(0), p.dT[2], p.invd[2]);
-    n = T(0);
-    if (nb<-1>(p.n, p.per, t, 1, u)) {
+        d[3] = dif((ok ? x1 : T(0)) - b, T(0), p.dT[2], p.invd[2]);
+        ok = nb_or_self<-1>(p.n, p.per, t, 1, u);
         hface<T, 0, FILM>(A, u, false, x0, x1);
-        n = x0;
+        d[4] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[1], p.invd[1]);
     }
-    d[4] = dif(n - a, T(0), p.dT[1], p.invd[1]);
 }
 
 // the transposed half step on the E side: lambda E_C += the transposed curl
@@ -1239,12 +1291,34 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
             o0[F] = -(p.hc * l);
             o1[F] = p.hc * l;
         }
-        if (nb<-1>(p.n, p.per, t, 2, u)) n1m2 = -(p.hc * A.lH[1][p.slot(u[0], u[1], u[2])]);
-        if (nb<-1>(p.n, p.per, t, 1, u)) n2m1 = p.hc * A.lH[2][p.slot(u[0], u[1], u[2])];
-        if (nb<-1>(p.n, p.per, t, 0, u)) n2m0 = -(p.hc * A.lH[2][p.slot(u[0], u[1], u[2])]);
-        if (nb<-1>(p.n, p.per, t, 2, u)) n0m2 = p.hc * A.lH[0][p.slot(u[0], u[1], u[2])];
-        if (nb<-1>(p.n, p.per, t, 1, u)) n0m1 = -(p.hc * A.lH[0][p.slot(u[0], u[1], u[2])]);
-        if (nb<-1>(p.n, p.per, t, 0, u)) n1m0 = p.hc * A.lH[1][p.slot(u[0], u[1], u[2])];
+        if constexpr (sizeof(T) == 8) {
+            if (nb<-1>(p.n, p.per, t, 2, u)) n1m2 = -(p.hc * A.lH[1][p.slot(u[0], u[1], u[2])]);
+            if (nb<-1>(p.n, p.per, t, 1, u)) n2m1 = p.hc * A.lH[2][p.slot(u[0], u[1], u[2])];
+            if (nb<-1>(p.n, p.per, t, 0, u)) n2m0 = -(p.hc * A.lH[2][p.slot(u[0], u[1], u[2])]);
+            if (nb<-1>(p.n, p.per, t, 2, u)) n0m2 = p.hc * A.lH[0][p.slot(u[0], u[1], u[2])];
+            if (nb<-1>(p.n, p.per, t, 1, u)) n0m1 = -(p.hc * A.lH[0][p.slot(u[0], u[1], u[2])]);
+            if (nb<-1>(p.n, p.per, t, 0, u)) n1m0 = p.hc * A.lH[1][p.slot(u[0], u[1], u[2])];
+        } else {
+            // the neighbours' lambda H (a wall's read at the own slot and dropped)
+            bool ok2 = nb_or_self<-1>(p.n, p.per, t, 2, u);
+            const T h1m2 = A.lH[1][p.slot(u[0], u[1], u[2])], h0m2 = A.lH[0][p.slot(u[0], u[1], u[2])];
+            bool ok1 = nb_or_self<-1>(p.n, p.per, t, 1, u);
+            const T h2m1 = A.lH[2][p.slot(u[0], u[1], u[2])], h0m1 = A.lH[0][p.slot(u[0], u[1], u[2])];
+            bool ok0 = nb_or_self<-1>(p.n, p.per, t, 0, u);
+            const T h2m0 = A.lH[2][p.slot(u[0], u[1], u[2])], h1m0 = A.lH[1][p.slot(u[0], u[1], u[2])];
+            if (ok2) {
+                n1m2 = -(p.hc * h1m2);
+                n0m2 = p.hc * h0m2;
+            }
+            if (ok1) {
+                n2m1 = p.hc * h2m1;
+                n0m1 = -(p.hc * h0m1);
+            }
+            if (ok0) {
+                n2m0 = -(p.hc * h2m0);
+                n1m0 = p.hc * h1m0;
+            }
+        }
         dd[0] = dif(n1m2 - o0[1], T(0), p.dT[2], p.invd[2]);
         dd[1] = dif(n2m1 - o1[2], T(0), p.dT[1], p.invd[1]);
         dd[2] = dif(n2m0 - o0[2], T(0), p.dT[0], p.invd[0]);
@@ -1313,29 +1387,80 @@ __device__ __forceinline__ void eedge(const AdjParams<T> &A, const int *e, const
                                       T &eD0, T &eD1) {
     constexpr int X1 = (X + 1) % 3, X2 = (X + 2) % 3;
     const KParams<T> &p = A.p;
-    const T lx = A.mu[X][p.slot(e[0], e[1], e[2])];
+    const T *mp = A.mu[X] + p.slot(e[0], e[1], e[2]);
+    const T lx = *mp;
     eD0 = lx;
     eD1 = -lx;
     if (PML) {
         const int a1 = e[X1], a2 = e[X2];
-        if (p.psiE[X][X1] && (a1 < p.nlo[X1] || a1 >= p.n[X1] - p.nhi[X1])) {
-            const long long q1 = p.psi_index(X1, e);
-            const T aps = in1[q1] + lx;
-            if (own) {
-                own->q1 = q1;
-                own->v1 = p.bE[X1][a1] * aps;
+        const bool s1 = p.psiE[X][X1] && (a1 < p.nlo[X1] || a1 >= p.n[X1] - p.nhi[X1]);
+        const bool s2 = p.psiE[X][X2] && (a2 < p.nlo[X2] || a2 >= p.n[X2] - p.nhi[X2]);
+        if constexpr (sizeof(T) == 8) {
+            // float64: the slab state loaded where needed only (fewer registers)
+            if (s1) {
+                const long long q1 = p.psi_index(X1, e);
+                const T aps = in1[q1] + lx;
+                if (own) {
+                    own->q1 = q1;
+                    own->v1 = p.bE[X1][a1] * aps;
+                }
+                eD0 = lx + p.cE[X1][a1] * aps;
             }
-            eD0 = lx + p.cE[X1][a1] * aps;
-        }
-        if (p.psiE[X][X2] && (a2 < p.nlo[X2] || a2 >= p.n[X2] - p.nhi[X2])) {
-            const long long q2 = p.psi_index(X2, e);
-            const T aps = in2[q2] - lx;
-            if (own) {
-                own->q2 = q2;
-                own->v2 = p.bE[X2][a2] * aps;
+            if (s2) {
+                const long long q2 = p.psi_index(X2, e);
+                const T aps = in2[q2] - lx;
+                if (own) {
+                    own->q2 = q2;
+                    own->v2 = p.bE[X2][a2] * aps;
+                }
+                eD1 = -lx + p.cE[X2][a2] * aps;
             }
-            eD1 = -lx + p.cE[X2][a2] * aps;
+        } else {
+            // float32: unconditional loads (a lane outside a slab reads mu again
+            // and drops it), so that the loads of all of a thread's edges are in
+            // flight at once
+            const long long q1 = s1 ? p.psi_index(X1, e) : 0, q2 = s2 ? p.psi_index(X2, e) : 0;
+            const T ps1 = *(s1 ? in1 + q1 : mp), ps2 = *(s2 ? in2 + q2 : mp);
+            const T b1 = *(s1 ? p.bE[X1] + a1 : mp), c1 = *(s1 ? p.cE[X1] + a1 : mp);
+            const T b2 = *(s2 ? p.bE[X2] + a2 : mp), c2 = *(s2 ? p.cE[X2] + a2 : mp);
+            if (s1) {
+                const T aps = ps1 + lx;
+                if (own) {
+                    own->q1 = q1;
+                    own->v1 = b1 * aps;
+                }
+                eD0 = lx + c1 * aps;
+            }
+            if (s2) {
+                const T aps = ps2 - lx;
+                if (own) {
+                    own->q2 = q2;
+                    own->v2 = b2 * aps;
+                }
+                eD1 = -lx + c2 * aps;
+            }
         }
+    }
+}
+
+// a neighbour edge of family X at t + e_axis: false past a wall (values
+// zero); float32 evaluates at the own slot there and drops the values (no
+// load waits on a branch), float64 branches (fewer registers)
+template <typename T, int X, int PML>
+__device__ __forceinline__ bool eedge_nb(const AdjParams<T> &A, const int *t, int axis, const T *in1, const T *in2,
+                                         T &x0, T &x1) {
+    int u[3];
+    if constexpr (sizeof(T) == 8) {
+        if (!nb<1>(A.p.n, A.p.per, t, axis, u)) {
+            x0 = x1 = T(0);
+            return false;
+        }
+        eedge<T, X, PML>(A, u, in1, in2, nullptr, x0, x1);
+        return true;
+    } else {
+        const bool ok = nb_or_self<1>(A.p.n, A.p.per, t, axis, u);
+        eedge<T, X, PML>(A, u, in1, in2, nullptr, x0, x1);
+        return ok;
     }
 }
 
@@ -1362,25 +1487,13 @@ __device__ __forceinline__ void efield_body(const AdjParams<T> &A, const int *t,
     eedge<T, 1, PML>(A, t, i1a, i1b, PML ? &w1 : nullptr, o0[1], o1[1]);
     eedge<T, 2, PML>(A, t, i2a, i2b, PML ? &w2 : nullptr, o0[2], o1[2]);
     T n1p2 = T(0), n2p1 = T(0), n2p0 = T(0), n0p2 = T(0), n0p1 = T(0), n1p0 = T(0);
-    int u[3];
-    if (nb<1>(p.n, p.per, t, 2, u)) {
-        eedge<T, 1, PML>(A, u, i1a, i1b, nullptr, x0, x1);
-        n1p2 = x0;
-        eedge<T, 0, PML>(A, u, i0a, i0b, nullptr, x0, x1);
-        n0p2 = x1;
-    }
-    if (nb<1>(p.n, p.per, t, 1, u)) {
-        eedge<T, 2, PML>(A, u, i2a, i2b, nullptr, x0, x1);
-        n2p1 = x1;
-        eedge<T, 0, PML>(A, u, i0a, i0b, nullptr, x0, x1);
-        n0p1 = x0;
-    }
-    if (nb<1>(p.n, p.per, t, 0, u)) {
-        eedge<T, 2, PML>(A, u, i2a, i2b, nullptr, x0, x1);
-        n2p0 = x0;
-        eedge<T, 1, PML>(A, u, i1a, i1b, nullptr, x0, x1);
-        n1p0 = x1;
-    }
+    // the +1 neighbours' edges
+    if (eedge_nb<T, 1, PML>(A, t, 2, i1a, i1b, x0, x1)) n1p2 = x0;
+    if (eedge_nb<T, 0, PML>(A, t, 2, i0a, i0b, x0, x1)) n0p2 = x1;
+    if (eedge_nb<T, 2, PML>(A, t, 1, i2a, i2b, x0, x1)) n2p1 = x1;
+    if (eedge_nb<T, 0, PML>(A, t, 1, i0a, i0b, x0, x1)) n0p1 = x0;
+    if (eedge_nb<T, 2, PML>(A, t, 0, i2a, i2b, x0, x1)) n2p0 = x0;
+    if (eedge_nb<T, 1, PML>(A, t, 0, i1a, i1b, x0, x1)) n1p0 = x1;
     if (PML) {
         T *o0a = par ? A.lpsiE[0][1] : A.lpsiE2[0][1], *o0b = par ? A.lpsiE[0][2] : A.lpsiE2[0][2];
         T *o1a = par ? A.lpsiE[1][2] : A.lpsiE2[1][2], *o1b = par ? A.lpsiE[1][0] : A.lpsiE2[1][0];
