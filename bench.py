@@ -314,6 +314,47 @@ def adjoint_cost(steps, window, graphs=True):
     return out
 
 
+def adjoint_cost_c2(steps, graphs=True):
+    """The adjoint on the 512 x 256 x 128 resonator: loss = film EM energy
+    over the last quarter of `steps`, gradients w.r.t. H0 and eps_r of a
+    32 x 16 x 4 patch in the substrate under the film centre; wall time
+    against the forward run of the same steps (float32 and float64)."""
+    import numpy as np
+    from paper_2510_22221_amd import mpx
+    from synth import workloads as W
+
+    w = W.c2(steps + 10)
+    w.probes = [W.Probe("film_energy", film=0)]
+    kf = int(np.nonzero((w.ids == 3).any(axis=(1, 2)))[0].min())
+    ys, xs = np.nonzero(w.ids[kf] == 3)
+    eps_box = (int(xs.mean()) - 16, int(ys.mean()) - 8, kf - 8, 32, 16, 4)
+    window = steps // 4
+    out = {"workload": f"single CPW resonator + film, {w.nx}x{w.ny}x{w.nz} cells, PML 10", "steps": steps,
+           "loss_window": window, "eps_cells": 32 * 16 * 4,
+           "schedule": "tape (segments keep their forward tapes as memory allows), fused field passes"}
+    gs = None if graphs else 0
+    for name, prec in (("f32", mpx.F32), ("f64", mpx.F64)):
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        s.step(20)
+        s.sync()
+        s.close()
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        fwd = time.perf_counter() - t0
+        s.close()
+        s = mpx.from_workload(w, precision=prec, graph_steps=gs)
+        t0 = time.perf_counter()
+        r = s.adjoint(steps, steps - window, eps_box=eps_box, ms_box=(0, 0, 0, 0, 0, 0))
+        adj = time.perf_counter() - t0
+        s.close()
+        out[name] = {"forward_s": round(fwd, 4), "adjoint_s": round(adj, 4), "adjoint_over_forward": round(adj / fwd, 3),
+                     "loss": r["loss"], "dL_dH0z": float(r["dH0"][2])}
+        log(f"  adjoint 512x256x128 {name}: forward {fwd:.3f} s, adjoint {adj:.3f} s, ratio {adj / fwd:.2f}")
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -391,6 +432,8 @@ def main():
     ap.add_argument("--anticrossing-steps", type=int, default=100000,
                     help="steps of the sweep analysed for the anti-crossing (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=20000, help="steps of the adjoint cost run (0: skip)")
+    ap.add_argument("--adjoint-c2-steps", type=int, default=2000,
+                    help="steps of the adjoint cost run on the 512x256x128 resonator (0: skip)")
     ap.add_argument("--adjoint-window", type=int, default=5000)
     ap.add_argument("--adjoint-no-graphs", action="store_true",
                     help="launch the adjoint's kernels directly (for kernel traces)")
@@ -457,6 +500,9 @@ def main():
         log(f"adjoint: {args.adjoint_steps} steps, loss over the last {args.adjoint_window}")
         out["adjoint"] = adjoint_cost(args.adjoint_steps, min(args.adjoint_window, args.adjoint_steps),
                                       graphs=not args.adjoint_no_graphs)
+    if args.adjoint_c2_steps > 0:
+        log(f"adjoint on the 512x256x128 resonator: {args.adjoint_c2_steps} steps")
+        out["adjoint_512x256x128"] = adjoint_cost_c2(args.adjoint_c2_steps, graphs=not args.adjoint_no_graphs)
     if not args.no_cpu:
         log(f"CPU oracle baseline: about {args.cpu_seconds} s per thread setting")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
