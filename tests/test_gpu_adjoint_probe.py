@@ -189,6 +189,31 @@ def test_trace_adjoint_is_linear_in_the_weights_and_graph_free():
     assert r1["loss"] == r4["loss"]
 
 
+def test_trace_adjoint_kept_tapes_match_recompute():
+    """The weighted-trace loss with segments that keep their forward tapes
+    (all of them, or a cap that keeps only some) against every segment
+    recomputed from its checkpoint: float64 bitwise."""
+    w = small_case(True)
+    n, K = 48, 5
+    kf, jf, i_f, kz0 = film_geometry(w)
+    ijk, eb, mb = (i_f, jf + 1, kz0 - 1), (i_f - 2, jf - 1, kz0 - 3, 4, 2, 2), (i_f - 1, jf, kf, 3, 1, 1)
+    wt = np.random.default_rng(21).standard_normal(n)
+    out = {}
+    for cap in (0, -1, 2 ** 16, 2 ** 18, 2 ** 20):
+        say(f"trace adjoint, kept-tape cap {cap}")
+        g = mpx.from_workload(w, precision=mpx.F64)
+        g.set_adjoint_memory(cap)
+        out[cap] = g.adjoint_probe(n, 1, ijk, wt, checkpoint_every=K, eps_box=eb, ms_box=mb)
+        out[cap]["E1"] = g.get(1)
+        g.close()
+    ref = out[0]
+    for cap, r in out.items():
+        assert r["loss"] == ref["loss"], cap
+        assert np.array_equal(r["E1"], ref["E1"]), cap
+        for key in ("dH0", "deps", "dMs"):
+            assert np.array_equal(r[key], ref[key]), (cap, key)
+
+
 def test_trace_adjoint_float32_tracks_float64():
     w = small_case(True)
     n, K = 60, 8
