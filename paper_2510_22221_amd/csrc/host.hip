@@ -78,6 +78,7 @@ struct mpx_sim {
     int kchunk = 16;
     bool narrow = false; // separate passes on 64 x 4 tiles whatever the width (schedule 6)
     void *d_coef = nullptr;
+    void *d_coefv = nullptr; // the same rows packed per class (KParams::coefv)
     long long n_coef_ext = 0; // extended triples after the class entries of d_coef
     // materials
     bool have_mat = false;
@@ -272,6 +273,7 @@ void fill_params(const mpx_sim *s, KParams<T> &p, int mode = MODE_INPLACE, int p
     p.mat = s->d_mat;
     p.coef = (const CoefDev<T> *)s->d_coef;
     p.coefx = p.coef + kCoefEntries;
+    p.coefv = (const T *)s->d_coefv;
     p.nfilm = (int)s->films.size();
     p.films = s->d_films;
     p.blocktab = s->d_blocktab;
@@ -2117,6 +2119,11 @@ mpx_status mpx_create(const mpx_grid_desc *g, mpx_precision prec, int32_t hip_de
             CK(hipMemset(s->H2[c], 0, s->nslot * s->esz));
         }
         CK(hipMalloc(&s->d_coef, kCoefEntries * (prec == MPX_F64 ? sizeof(CoefDev<double>) : sizeof(CoefDev<float>))));
+        {
+            const size_t vb = 256 * (prec == MPX_F64 ? kCoefRow<double> * sizeof(double) : kCoefRow<float> * sizeof(float));
+            CK(hipMalloc(&s->d_coefv, vb));
+            CK(hipMemset(s->d_coefv, 0, vb));
+        }
         CK(hipMalloc(&s->d_id, s->nslot));
         CK(hipMemset(s->d_id, 0, s->nslot));
         CK(hipMalloc(&s->d_cls, s->nslot));
@@ -2145,6 +2152,7 @@ mpx_status mpx_destroy(mpx_sim *s) {
     drop_graph(s);
     for (auto e : s->ev) (void)hipEventDestroy(e);
     (void)hipFree(s->d_coef);
+    (void)hipFree(s->d_coefv);
     for (int c = 0; c < 3; c++) {
         (void)hipFree(s->E[c]);
         (void)hipFree(s->H[c]);
@@ -2473,6 +2481,32 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
         (void)hipFree(s->d_coef);
         s->d_coef = nullptr;
         s->n_coef_ext = (long long)cdx.size() / kCoefPerClass;
+        // the packed rows: ca, cb of the x, y, z edges of each row, in the
+        // field precision (float: rounded once from the float64 values, as
+        // in the table)
+        {
+            const size_t nrow = ntot / kCoefPerClass;
+            const int rw = s->prec == MPX_F64 ? kCoefRow<double> : kCoefRow<float>;
+            std::vector<double> v64((size_t)nrow * rw, 0.0);
+            for (size_t r = 0; r < nrow; r++)
+                for (int C = 0; C < kCoefPerClass; C++) {
+                    const size_t q = r * kCoefPerClass + C;
+                    const CoefDev<double> &c = q < (size_t)kCoefEntries ? cd[q] : cdx[q - kCoefEntries];
+                    v64[r * rw + 2 * C] = c.pec ? 0.0 : c.ca;
+                    v64[r * rw + 2 * C + 1] = c.pec ? 0.0 : c.cb;
+                }
+            (void)hipFree(s->d_coefv);
+            s->d_coefv = nullptr;
+            if (s->prec == MPX_F64) {
+                CK(hipMalloc(&s->d_coefv, v64.size() * sizeof(double)));
+                CK(hipMemcpy(s->d_coefv, v64.data(), v64.size() * sizeof(double), hipMemcpyHostToDevice));
+            } else {
+                std::vector<float> v32(v64.size());
+                for (size_t q = 0; q < v64.size(); q++) v32[q] = (float)v64[q];
+                CK(hipMalloc(&s->d_coefv, v32.size() * sizeof(float)));
+                CK(hipMemcpy(s->d_coefv, v32.data(), v32.size() * sizeof(float), hipMemcpyHostToDevice));
+            }
+        }
         if (s->prec == MPX_F64) {
             std::vector<CoefDev<double>> all(cd);
             all.insert(all.end(), cdx.begin(), cdx.end());

@@ -74,6 +74,9 @@ struct CoefDev {
 constexpr int kMixed = 255; // class byte of a slot whose edges take the general path
 constexpr int kCoefPerClass = 3;
 constexpr int kCoefEntries = kCoefPerClass * 256;
+// values per packed row (coefv): six, float rows padded to 32 bytes
+template <typename T>
+constexpr int kCoefRow = sizeof(T) == 4 ? 8 : 6;
 
 template <typename T>
 struct KParams {
@@ -98,6 +101,11 @@ struct KParams {
     // 2^20 of them), three entries each: the same allocation as coef, after
     // its kCoefEntries class entries
     const CoefDev<T> *coefx;
+    // the same rows packed for the separate E pass: row r (a class, or 256 +
+    // an extended triple) holds ca, cb of its x, y and z edges side by side
+    // (kCoefRow values; float rows padded to eight), so that one or two wide
+    // loads fetch a slot's six coefficients
+    const T *coefv;
     const uint8_t *id;
     const uint8_t *cls; // per slot: the shared id of the 8 cells around it, or 255
     const uint8_t *pflags; // per separate-pass tile: 1 CPML, 2 source, 4 film within reach

@@ -13,7 +13,8 @@
 // so the address work per load is one or two integer operations; blocks at a
 // boundary use folded, zero-filled loads.  Per-tile CPML / source / film
 // flags come from a host table (one per tile shape); edge coefficients come
-// from the material table by the slot's class byte (no per-block staging).
+// from the packed row of the slot's class (its six values in one or two
+// 16-byte loads; no per-block staging).
 #include "film.h"
 #include "stencil.h"
 
@@ -79,8 +80,10 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
         c0 = (p.cls16 + k * sz)[o];
     else
         c0 = (p.cls + k * sz)[o];
-    const CoefMem<T> L{p.coef};
     const int kSkip = c16 ? 0xffff : kMixed;
+    // the slot's six coefficients in one or two wide loads (a skipped slot
+    // reads row 0 and uses none)
+    const CoefRow<T> L = coef_row<T>(p.coefv, c0 == kSkip ? 0 : c0);
     T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
     const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
     const long long step = tsrc ? p.step[0] : 0;
@@ -98,7 +101,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
             Psi2<T> r;
             if (tpml && v0) r = psi_load<T, 0, true>(p, q0);
             if (v0)
-                n0 = e_apply<T, 0, CoefMem<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy), dif(hy0, hy_km, dz, iz),
+                n0 = e_apply<T, 0, CoefRow<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy), dif(hy0, hy_km, dz, iz),
                                                      r, tsrc, step);
             if (tpml) psi_store<T, 0>(p.psiE[0], r);
         }
@@ -106,7 +109,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
             Psi2<T> r;
             if (tpml && v1) r = psi_load<T, 1, true>(p, q1);
             if (v1)
-                n1 = e_apply<T, 1, CoefMem<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz), dif(hz0, hz_xm, dx, ix),
+                n1 = e_apply<T, 1, CoefRow<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz), dif(hz0, hz_xm, dx, ix),
                                                      r, tsrc, step);
             if (tpml) psi_store<T, 1>(p.psiE[1], r);
         }
@@ -114,7 +117,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
             Psi2<T> r;
             if (tpml && v2) r = psi_load<T, 2, true>(p, q2);
             if (v2)
-                n2 = e_apply<T, 2, CoefMem<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix), dif(hx0, hx_ym, dy, iy),
+                n2 = e_apply<T, 2, CoefRow<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix), dif(hx0, hx_ym, dy, iy),
                                                      r, tsrc, step);
             if (tpml) psi_store<T, 2>(p.psiE[2], r);
         }
@@ -132,13 +135,13 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
         if (v2) r2 = psi_load<T, 2, true>(p, q2);
     }
     if (!inside || c0 == kSkip) return;
-    const T n0 = v0 ? e_apply<T, 0, CoefMem<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy),
+    const T n0 = v0 ? e_apply<T, 0, CoefRow<T>, false>(p, L, q0, c0, e0, dif(hz0, hz_ym, dy, iy),
                                                        dif(hy0, hy_km, dz, iz), r0, tsrc, step)
                     : T(0);
-    const T n1 = v1 ? e_apply<T, 1, CoefMem<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz),
+    const T n1 = v1 ? e_apply<T, 1, CoefRow<T>, false>(p, L, q1, c0, e1, dif(hx0, hx_km, dz, iz),
                                                        dif(hz0, hz_xm, dx, ix), r1, tsrc, step)
                     : T(0);
-    const T n2 = v2 ? e_apply<T, 2, CoefMem<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix),
+    const T n2 = v2 ? e_apply<T, 2, CoefRow<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix),
                                                        dif(hx0, hx_ym, dy, iy), r2, tsrc, step)
                     : T(0);
     ex[o] = n0;
@@ -311,11 +314,13 @@ __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by,
 // slots, or on grids at least two wide tiles across, 256 x 1 (each block
 // then reads and writes 256 consecutive slots of every array: measured 5 %
 // (float32) and 9 % (float64) faster per step on a 512-wide grid, slower on
-// narrow ones).  In float32 the E pass is held to 64 VGPRs (8 waves per
-// SIMD; it fits without spilling).  XC: the variant for grids with
+// narrow ones).  In float32 the E pass is held to 72 VGPRs (7 waves per
+// SIMD): with the slot's packed coefficient row loaded at once it fits
+// without spilling, and it measured 4 % faster than the per-edge table loads
+// at 64 VGPRs (at 64 the row spills).  XC: the variant for grids with
 // extended-table slots (16-bit classes).
 template <typename T, int TX, int TY, bool XC>
-__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 7 : 1, 8)))
 k_epass(KParams<T> p) {
     epass_block<T, XC, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
