@@ -688,13 +688,15 @@ mpx_status update_pass_flags(mpx_sim *s) {
     const std::vector<uint8_t> fl = tile_flags(s, kPassTX, kPassTY);
     (void)hipFree(s->d_pflags);
     s->d_pflags = nullptr;
-    CK(hipMalloc(&s->d_pflags, std::max<size_t>(1, fl.size())));
+    // rounded up to whole 4-byte words: the E pass reads its flag byte
+    // through the scalar cache, one aligned word at a time
+    CK(hipMalloc(&s->d_pflags, (fl.size() + 4) / 4 * 4));
     CK(hipMemcpy(s->d_pflags, fl.data(), fl.size(), hipMemcpyHostToDevice));
     (void)hipFree(s->d_pflags_w);
     s->d_pflags_w = nullptr;
     if (s->n[0] >= kWideMinNx) {
         const std::vector<uint8_t> fw = tile_flags(s, kWideTX, kWideTY);
-        CK(hipMalloc(&s->d_pflags_w, std::max<size_t>(1, fw.size())));
+        CK(hipMalloc(&s->d_pflags_w, (fw.size() + 4) / 4 * 4));
         CK(hipMemcpy(s->d_pflags_w, fw.data(), fw.size(), hipMemcpyHostToDevice));
     }
     return MPX_OK;

@@ -50,8 +50,25 @@ constexpr int kOOB = 0x7ffffff0; // a byte offset past every resource: the load 
 // list (class byte 255, or 16-bit class 0xffff) is skipped and updated
 // afterwards by the mixed-slot kernel from the same old values.
 // ---------------------------------------------------------------------------
-template <typename T, bool XC>
-__device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tsrc) {
+// whether this wave takes the CPML path: a wide tile that reaches CPML slabs
+// only along x (flag 1 without 8) needs it only in the waves whose 64 slots,
+// with the one-slot halo, reach an x slab (the same test as the tile's, on
+// the wave's range; uniform over the wave, so the other waves skip it)
+template <typename T, int TX>
+__device__ __forceinline__ bool wave_pml(const KParams<T> &p, int bx, int f) {
+    if (!(f & 1)) return false;
+    if (TX != kWideTX || (f & 8)) return true;
+    const int w0 = bx * TX + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
+    return (p.nlo[0] > 0 && w0 - 1 < p.nlo[0]) || (p.nhi[0] > 0 && w0 + 64 >= p.n[0] - p.nhi[0]);
+}
+
+// CLS: the slot class read, 0 the class byte, 1 the 16-bit class (a grid
+// with extended triples), 2 whichever the instance has (batch members of one
+// launch differ; the test is uniform over a member's lanes).  f: the tile's
+// flag byte, first used after every field load has been issued (so that the
+// loads do not wait for it).
+template <typename T, int CLS, int TX>
+__device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, int k, int f, int bxt) {
     const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
     const bool inside = i < p.n[0] && j < p.n[1];
     const int ic = min(i, p.n[0] - 1), jc = min(j, p.n[1] - 1);
@@ -68,15 +85,19 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
     const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
     const T hz0 = bld<T>(rz, vo, 0), hz_xm = bld<T>(rz, vxm, 0), hz_ym = bld<T>(rz, vym, 0);
+    T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
+    const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
     // the coefficient triple's row: the class byte (255: the slot is on the
-    // mixed list), or with extended triples (XC) the 16-bit class (0xffff:
-    // on the mixed list), whose rows past 255 are the extended table's
-    // (a batch member without 16-bit classes takes the byte: the test is
-    // uniform over the launch's lanes of one member)
-    bool c16 = false;
-    if constexpr (XC) c16 = p.cls16 != nullptr;
+    // mixed list), or with extended triples the 16-bit class (0xffff: on the
+    // mixed list), whose rows past 255 are the extended table's
+    bool c16 = CLS == 1;
+    if constexpr (CLS == 2) c16 = p.cls16 != nullptr;
     int c0;
-    if (c16)
+    if constexpr (CLS == 0)
+        c0 = (p.cls + k * sz)[o];
+    else if constexpr (CLS == 1)
+        c0 = (p.cls16 + k * sz)[o];
+    else if (c16)
         c0 = (p.cls16 + k * sz)[o];
     else
         c0 = (p.cls + k * sz)[o];
@@ -84,8 +105,7 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     // the slot's six coefficients in one or two wide loads (a skipped slot
     // reads row 0 and uses none)
     const CoefRow<T> L = coef_row<T>(p.coefv, c0 == kSkip ? 0 : c0);
-    T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
-    const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
+    const bool tpml = wave_pml<T, TX>(p, bxt, f), tsrc = (f & 2) != 0;
     const long long step = tsrc ? p.step[0] : 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
     int q0[3], q1[3], q2[3];
@@ -154,25 +174,24 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     }
 }
 
-// whether this wave takes the CPML path: a wide tile that reaches CPML slabs
-// only along x (flag 1 without 8) needs it only in the waves whose 64 slots,
-// with the one-slot halo, reach an x slab (the same test as the tile's, on
-// the wave's range; uniform over the wave, so the other waves skip it)
-template <typename T, int TX>
-__device__ __forceinline__ bool wave_pml(const KParams<T> &p, int bx, int f) {
-    if (!(f & 1)) return false;
-    if (TX != kWideTX || (f & 8)) return true;
-    const int w0 = bx * TX + (__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63);
-    return (p.nlo[0] > 0 && w0 - 1 < p.nlo[0]) || (p.nhi[0] > 0 && w0 + 64 >= p.n[0] - p.nhi[0]);
-}
-
 // a block: the TX x TY slots (bx, by) of plane k, flags from the table of
 // that tile shape
-template <typename T, bool XC, int TX = PTX, int TY = PTY>
-__device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
+// the flag byte of tile (bx, by, k) of the TX x TY table, read through the
+// scalar cache (the aligned word that holds it; the tables are whole words):
+// a vector load here would put the field loads behind its wait, since the
+// vector memory counter completes in order
+template <typename T, int TX, int TY>
+__device__ __forceinline__ int tile_flag(const KParams<T> &p, int bx, int by, int k) {
     const int nxt = (p.n[0] + TX - 1) / TX, nyt = (p.n[1] + TY - 1) / TY;
-    const int f = (TX == PTX ? p.pflags : p.pflags_w)[bx + nxt * (by + nyt * k)];
-    epass_tile<T, XC>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 2) != 0);
+    typedef __attribute__((address_space(4))) const uint32_t cword;
+    const long long ti = bx + (long long)nxt * (by + (long long)nyt * k);
+    const uint32_t w = ((cword *)(TX == PTX ? p.pflags : p.pflags_w))[ti >> 2];
+    return (int)((w >> (8 * (int)(ti & 3))) & 0xffu);
+}
+
+template <typename T, int CLS, int TX = PTX, int TY = PTY>
+__device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
+    epass_tile<T, CLS, TX>(p, bx * TX, by * TY, k, tile_flag<T, TX, TY>(p, bx, by, k), bx);
 }
 
 // the mixed slots, one thread each: the general path (folded loads; edge
@@ -215,8 +234,8 @@ __device__ __forceinline__ void emixed_slot(const KParams<T> &p, int m) {
 // on a periodic axis and reads zero at a wall (the E there is tangential to
 // it); lanes past the domain store nothing.
 // ---------------------------------------------------------------------------
-template <typename T, int NHALF>
-__device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, int k, bool tpml, bool tfilm) {
+template <typename T, int NHALF, int TX>
+__device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, int k, int f, int bxt) {
     const int i = i0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y;
     const bool inside = i < p.n[0] && j < p.n[1];
     const int ic = min(i, p.n[0] - 1), jc = min(j, p.n[1] - 1);
@@ -238,6 +257,8 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
     const T ey0 = bld<T>(ry, vo, 0), ey_xp = bld<T>(ry, vxp, 0), ey_kp = bld<T>(ay, vo, 0);
     const T ez0 = bld<T>(rz, vo, 0), ez_xp = bld<T>(rz, vxp, 0), ez_yp = bld<T>(rz, vyp, 0);
     const T h0 = bld<T>(gx, vo, 0), h1 = bld<T>(gy, vo, 0), h2 = bld<T>(gz, vo, 0);
+    // the tile's flags, first used after every field load has been issued
+    const bool tpml = wave_pml<T, TX>(p, bxt, f), tfilm = (f & 4) != 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
     const int idx[3] = {ic, jc, k};
     Psi2<T> r0, r1, r2;
@@ -303,9 +324,7 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
 
 template <typename T, int NHALF, int TX = PTX, int TY = PTY>
 __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by, int k) {
-    const int nxt = (p.n[0] + TX - 1) / TX, nyt = (p.n[1] + TY - 1) / TY;
-    const int f = (TX == PTX ? p.pflags : p.pflags_w)[bx + nxt * (by + nyt * k)];
-    hpass_tile<T, NHALF>(p, bx * TX, by * TY, k, wave_pml<T, TX>(p, bx, f), (f & 4) != 0);
+    hpass_tile<T, NHALF, TX>(p, bx * TX, by * TY, k, tile_flag<T, TX, TY>(p, bx, by, k), bx);
 }
 
 // grid (x tiles, y tiles, planes) in natural order: the blocks resident at
@@ -322,7 +341,7 @@ __device__ __forceinline__ void hpass_block(const KParams<T> &p, int bx, int by,
 template <typename T, int TX, int TY, bool XC>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 7 : 1, 8)))
 k_epass(KParams<T> p) {
-    epass_block<T, XC, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+    epass_block<T, XC ? 1 : 0, TX, TY>(p, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int NHALF, int TX, int TY>
@@ -363,7 +382,7 @@ __global__ void __launch_bounds__(PTX *PTY)
     const int w = blockIdx.x;
     if (w >= nwork) return;
     const int4 wk = work[w];
-    epass_block<T, XC>(plist[wk.x], wk.y, wk.z, wk.w);
+    epass_block<T, XC ? 2 : 0>(plist[wk.x], wk.y, wk.z, wk.w);
 }
 
 // work[w] = (instance, first list entry of a 256-entry block)
