@@ -1203,6 +1203,16 @@ __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, l
     l2 = le[2];
 }
 
+// the flag byte of this block's tile, read through the scalar cache (the
+// aligned word that holds it; the table is whole words), so that the wait for
+// it does not hold vector loads issued before its first use
+__device__ __forceinline__ int adj_tile_flag(const uint8_t *tab) {
+    typedef __attribute__((address_space(4))) const uint32_t cword;
+    const unsigned ti = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t w = ((cword *)tab)[ti >> 2];
+    return (int)((w >> (8 * (ti & 3))) & 0xffu);
+}
+
 // the six differences of the transposed curl a slot's half-step pass adds to
 // its lambda E, in a tile near a CPML slab (FILM = 0) or a film's reach
 // (FILM = 1): d = {d0a, d0b, d1a, d1b, d2a, d2b}, lambda E_C gaining
@@ -1269,7 +1279,7 @@ __global__ void __launch_bounds__(256) k_adj_hfield(AdjParams<T> A) {
     if (i >= p.n[0] || j >= p.n[1]) return;
     const int t[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
-    const uint8_t fl = A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)];
+    const uint8_t fl = (uint8_t)adj_tile_flag(A.aflags);
     // lambda E and the edge coefficients (one class read) before the faces
     T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
     T ca[3], cb[3];
@@ -1517,7 +1527,7 @@ __global__ void __launch_bounds__(256) k_adj_efield(AdjParams<T> A) {
     if (i >= p.n[0] || j >= p.n[1]) return;
     const int t[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
-    if (A.aflags[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] & 1)
+    if (adj_tile_flag(A.aflags) & 1)
         efield_body<T, 1>(A, t, q);
     else
         efield_body<T, 0>(A, t, q);

@@ -1678,7 +1678,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
                 }
                 fl[t] = fv;
             }
-            CK(hipMalloc(&h.d_aflags, std::max(1, nt)));
+            CK(hipMalloc(&h.d_aflags, ((size_t)nt + 4) / 4 * 4)); // whole words (read through the scalar cache)
             CK(hipMemcpy(h.d_aflags, fl.data(), nt, hipMemcpyHostToDevice));
         }
         if (!h.af.empty()) {
