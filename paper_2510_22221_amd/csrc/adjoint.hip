@@ -63,9 +63,9 @@ __device__ __forceinline__ int mag_site(const KParams<T> &p, int c, const int *i
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_film(AdjParams<T> A) {
     const KParams<T> &p = A.p;
-    const int4 bt = p.blocktab[blockIdx.x];
+    const int4 bt = block_entry(p.blocktab, blockIdx.x);
     const int f = bt.x, c = bt.y;
-    const FilmDev &F = p.films[f];
+    const FilmDev F = film_desc(p.films, f);
     const AdjFilmDev &G = A.af[f];
     const long long l = (long long)bt.z + threadIdx.x;
     if (l >= F.ns) return;

@@ -39,6 +39,26 @@ __device__ __forceinline__ T ldz(const KParams<T> &p, const T *a, int i, int j, 
     return a[p.slot(ii, jj, kk)];
 }
 
+// a film descriptor and a film-block table entry read through the scalar
+// cache (both tables are uniform per block and read-only within a launch):
+// their waits do not hold vector loads, and scalar loads return sooner
+typedef __attribute__((address_space(4))) const uint32_t cword_t;
+
+__device__ __forceinline__ FilmDev film_desc(const FilmDev *films, int f) {
+    static_assert(sizeof(FilmDev) % 4 == 0, "whole words");
+    const cword_t *src = (const cword_t *)(films + f);
+    FilmDev d;
+    uint32_t *dst = (uint32_t *)&d;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(FilmDev) / 4); q++) dst[q] = src[q];
+    return d;
+}
+
+__device__ __forceinline__ int4 block_entry(const int4 *tab, int b) {
+    const cword_t *src = (const cword_t *)(tab + b);
+    return make_int4((int)src[0], (int)src[1], (int)src[2], (int)src[3]);
+}
+
 // is the face of family c at slot idx (folded) a magnetic site of a film?
 template <typename T>
 __device__ __forceinline__ bool face_is_magnetic(const KParams<T> &p, int c, const int *idx) {

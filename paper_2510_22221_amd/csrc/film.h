@@ -55,9 +55,9 @@ template <typename T>
 __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int inc_step, int blk) {
     __shared__ double red[256];
     if (inc_step && blk == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
-    const int4 bt = p.blocktab[blk]; // film, family, first local index
+    const int4 bt = block_entry(p.blocktab, blk); // film, family, first local index
     const int f = bt.x, c = bt.y;
-    const FilmDev &F = p.films[f];
+    const FilmDev F = film_desc(p.films, f);
     const long long l = (long long)bt.z + threadIdx.x;
     double own = 0.0;
     if (l < F.ns) {

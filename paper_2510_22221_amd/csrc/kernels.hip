@@ -97,7 +97,7 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     }
     double d1, d2;
     curl_e64(p, cq, idx, d1, d2);
-    const FilmDev &F = p.films[f];
+    const FilmDev F = film_desc(p.films, f);
     bool inside;
     const long long l = film_local<T>(F, idx, inside);
     mag = inside && F.prm[(cq * 3) * F.ns + l] > 0.0;
@@ -126,9 +126,9 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
 // B^ prepass: B^n and B^* of every face of the grown face box
 template <typename T>
 __device__ __forceinline__ void bhat_body(const KParams<T> &p, int phase, int blk) {
-    const int4 bt = p.blocktab_ext[blk];
+    const int4 bt = block_entry(p.blocktab_ext, blk);
     const int f = bt.x, c = bt.y;
-    const FilmDev &F = p.films[f];
+    const FilmDev F = film_desc(p.films, f);
     const long long l = (long long)bt.z + threadIdx.x;
     if (l >= F.nse) return;
     const int idx[3] = {F.e0[0] + (int)(l % F.en[0]), F.e0[1] + (int)((l / F.en[0]) % F.en[1]),
@@ -176,9 +176,9 @@ __global__ void __launch_bounds__(256) k_film_batch(const KParams<T> *__restrict
 // copy the scratch of a single (bracket) half step into the state
 template <typename T>
 __global__ void __launch_bounds__(256) k_film_commit(KParams<T> p) {
-    const int4 bt = p.blocktab[blockIdx.x];
+    const int4 bt = block_entry(p.blocktab, blockIdx.x);
     const int f = bt.x, c = bt.y;
-    const FilmDev &F = p.films[f];
+    const FilmDev F = film_desc(p.films, f);
     const long long l = (long long)bt.z + threadIdx.x;
     if (l >= F.ns) return;
     int idx[3];
