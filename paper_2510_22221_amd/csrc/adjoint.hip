@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_adj_film(AdjParams<T> A) {
     const int4 bt = block_entry(p.blocktab, blockIdx.x);
     const int f = bt.x, c = bt.y;
     const FilmDev F = film_desc(p.films, f);
-    const AdjFilmDev &G = A.af[f];
+    const AdjFilmDev G = scalar_desc(A.af, f);
     const long long l = (long long)bt.z + threadIdx.x;
     if (l >= F.ns) return;
     const double ms = F.prm[(c * 3 + 0) * F.ns + l];
@@ -972,17 +972,15 @@ __device__ __forceinline__ void edge_coefs(const KParams<T> &p, const int *idx, 
     ca[0] = ca[1] = ca[2] = cb[0] = cb[1] = cb[2] = T(0);
     ok[0] = ok[1] = ok[2] = false;
     if (cl != kMixed) {
-        const CoefDev<T> c0 = p.coef[kCoefPerClass * cl], c1 = p.coef[kCoefPerClass * cl + 1],
-                         c2 = p.coef[kCoefPerClass * cl + 2];
-        ca[0] = c0.ca;
-        cb[0] = c0.cb;
-        ok[0] = !c0.pec;
-        ca[1] = c1.ca;
-        cb[1] = c1.cb;
-        ok[1] = !c1.pec;
-        ca[2] = c2.ca;
-        cb[2] = c2.cb;
-        ok[2] = !c2.pec;
+        // the class's packed row (one or two wide loads; a PEC edge has
+        // ca = cb = 0, every other edge cb > 0)
+        const CoefRow<T> r = coef_row<T>(p.coefv, cl);
+#pragma unroll
+        for (int C = 0; C < 3; C++) {
+            ca[C] = r.ca[C];
+            cb[C] = r.cb[C];
+            ok[C] = r.cb[C] != T(0);
+        }
     }
     // an edge on a lower wall (a non-periodic axis other than its own) is held
     // at zero; a mixed slot's edges read the four cells around them, which
@@ -1008,7 +1006,7 @@ __device__ __forceinline__ void edge_coefs(const KParams<T> &p, const int *idx, 
 template <typename T>
 __device__ __forceinline__ int first_region(const AdjParams<T> &A, const int *idx, long long &lr) {
     for (int f = 0; f < A.p.nfilm; f++) {
-        const AdjFilmDev &G = A.af[f];
+        const AdjFilmDev G = scalar_desc(A.af, f);
         const int r0 = idx[0] - G.r0[0], r1 = idx[1] - G.r0[1], r2 = idx[2] - G.r0[2];
         if (r0 >= 0 && r0 < G.rn[0] && r1 >= 0 && r1 < G.rn[1] && r2 >= 0 && r2 < G.rn[2]) {
             lr = (long long)r0 + (long long)G.rn[0] * ((long long)r1 + (long long)G.rn[1] * r2);
@@ -1043,7 +1041,7 @@ __device__ __forceinline__ bool nb_or_self(const int *n, const int *per, const i
 // adjoints stored for the field pass
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_film_faces(AdjParams<T> A, int f) {
-    const AdjFilmDev &G = A.af[f];
+    const AdjFilmDev G = scalar_desc(A.af, f);
     const long long lr = (long long)blockIdx.x * 256 + threadIdx.x;
     if (lr >= G.nr) return;
     const int idx[3] = {G.r0[0] + (int)(lr % G.rn[0]), G.r0[1] + (int)((lr / G.rn[0]) % G.rn[1]),

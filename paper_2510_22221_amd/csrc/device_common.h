@@ -44,19 +44,59 @@ __device__ __forceinline__ T ldz(const KParams<T> &p, const T *a, int i, int j, 
 // their waits do not hold vector loads, and scalar loads return sooner
 typedef __attribute__((address_space(4))) const uint32_t cword_t;
 
-__device__ __forceinline__ FilmDev film_desc(const FilmDev *films, int f) {
-    static_assert(sizeof(FilmDev) % 4 == 0, "whole words");
-    const cword_t *src = (const cword_t *)(films + f);
-    FilmDev d;
+template <typename D>
+__device__ __forceinline__ D scalar_desc(const D *tab, int f) {
+    static_assert(sizeof(D) % 4 == 0, "whole words");
+    const cword_t *src = (const cword_t *)(tab + f);
+    D d;
     uint32_t *dst = (uint32_t *)&d;
 #pragma unroll
-    for (int q = 0; q < (int)(sizeof(FilmDev) / 4); q++) dst[q] = src[q];
+    for (int q = 0; q < (int)(sizeof(D) / 4); q++) dst[q] = src[q];
     return d;
 }
+
+__device__ __forceinline__ FilmDev film_desc(const FilmDev *films, int f) { return scalar_desc(films, f); }
 
 __device__ __forceinline__ int4 block_entry(const int4 *tab, int b) {
     const cword_t *src = (const cword_t *)(tab + b);
     return make_int4((int)src[0], (int)src[1], (int)src[2], (int)src[3]);
+}
+
+// a slot's row of the packed table (KParams::coefv), fetched with one or two
+// 16-byte loads and served to e_apply as its table (the class argument is
+// the row's own)
+template <typename T>
+struct CoefRow {
+    T ca[3], cb[3];
+    __device__ __forceinline__ void get(int, int C, T &a, T &b) const {
+        a = ca[C];
+        b = cb[C];
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ CoefRow<T> coef_row(const T *v, int row) {
+    CoefRow<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *(const float4 *)(v + kCoefRow<float> * (long long)row);
+        const float2 b = *(const float2 *)(v + kCoefRow<float> * (long long)row + 4);
+        r.ca[0] = a.x;
+        r.cb[0] = a.y;
+        r.ca[1] = a.z;
+        r.cb[1] = a.w;
+        r.ca[2] = b.x;
+        r.cb[2] = b.y;
+    } else {
+        const double2 *q = (const double2 *)(v + kCoefRow<double> * (long long)row);
+        const double2 a = q[0], b = q[1], c = q[2];
+        r.ca[0] = a.x;
+        r.cb[0] = a.y;
+        r.ca[1] = b.x;
+        r.cb[1] = b.y;
+        r.ca[2] = c.x;
+        r.cb[2] = c.y;
+    }
+    return r;
 }
 
 // is the face of family c at slot idx (folded) a magnetic site of a film?

@@ -1755,9 +1755,10 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
                 if (probes) CK(launch_probes<T>(p, np, s->probe_maxpart, st));
                 if (m + 1 < len) {
                     if (floss) CK(launch_tape_loss<T>(p, film, 1, tp.lossp(m + 1), st, LF.cb));
+                    // the film's second half step with the merged H/M pass
+                    // (one launch on wide grids, as in stepping)
                     p.films = tvar(tp, m, V_P2);
-                    CK(launch_film<T>(p, nblk, 2, 0, st));
-                    CK(launch_hbulk<T>(p, 2, 1, st));
+                    CK(launch_hbulk_film<T>(p, nblk, 1, st));
                 } else {
                     p.films = tvar(tp, m, V_C);
                     CK(launch_commit<T>(p, nblk, st));

@@ -35,61 +35,6 @@ struct CoefMem {
     }
 };
 
-// a slot's row of the packed table (KParams::coefv), fetched with one or two
-// 16-byte loads and served to e_apply as its table (the class argument is
-// the row's own)
-template <typename T>
-struct CoefRow {
-    T ca[3], cb[3];
-    __device__ __forceinline__ void get(int, int C, T &a, T &b) const {
-        a = ca[C];
-        b = cb[C];
-    }
-};
-
-// the same row read per edge when e_apply asks: one 8- or 16-byte load of
-// the edge's (ca, cb) pair (fewer values live at once than the whole row)
-template <typename T>
-struct CoefPair {
-    const T *r;
-    __device__ __forceinline__ void get(int, int C, T &a, T &b) const {
-        if constexpr (sizeof(T) == 4) {
-            const float2 v = *(const float2 *)(r + 2 * C);
-            a = v.x;
-            b = v.y;
-        } else {
-            const double2 v = *(const double2 *)(r + 2 * C);
-            a = v.x;
-            b = v.y;
-        }
-    }
-};
-
-template <typename T>
-__device__ __forceinline__ CoefRow<T> coef_row(const T *v, int row) {
-    CoefRow<T> r;
-    if constexpr (sizeof(T) == 4) {
-        const float4 a = *(const float4 *)(v + kCoefRow<float> * (long long)row);
-        const float2 b = *(const float2 *)(v + kCoefRow<float> * (long long)row + 4);
-        r.ca[0] = a.x;
-        r.cb[0] = a.y;
-        r.ca[1] = a.z;
-        r.cb[1] = a.w;
-        r.ca[2] = b.x;
-        r.cb[2] = b.y;
-    } else {
-        const double2 *q = (const double2 *)(v + kCoefRow<double> * (long long)row);
-        const double2 a = q[0], b = q[1], c = q[2];
-        r.ca[0] = a.x;
-        r.cb[0] = a.y;
-        r.ca[1] = b.x;
-        r.cb[1] = b.y;
-        r.ca[2] = c.x;
-        r.cb[2] = c.y;
-    }
-    return r;
-}
-
 template <typename T>
 __device__ __forceinline__ void stage_coef(const KParams<T> &p, CoefLds<T> &L, int tid, int nthreads) {
     for (int q = tid; q < kCoefEntries; q += nthreads) {
