@@ -344,7 +344,7 @@ mpx_status mpx_adjoint(mpx_sim *sim, int64_t nsteps, int64_t loss_from, int32_t 
  *   field      0, 1, 2 for E_x, E_y, E_z;
  *   ijk        a stored site (0 <= ijk[a] < the grid's size on axis a);
  *   weights    nsteps finite host values (read during the call only).
- * Tape schedule only (mpx_set_adjoint_schedule 0).  Memory, checkpoints and
+ * Tape schedules only (mpx_set_adjoint_schedule 0 or 2).  Memory, checkpoints and
  * the state on return as for mpx_adjoint.  Synchronous.
  * Errors: MPX_E_INVALID (arguments, a non-finite weight), MPX_E_STATE,
  * MPX_E_UNSUPPORTED under schedule 1, MPX_E_NOMEM / MPX_E_DEVICE. */
@@ -358,8 +358,13 @@ mpx_status mpx_adjoint_probe(mpx_sim *sim, int64_t nsteps, int32_t field, const 
  *     values the adjoint maps read are taped, then its adjoint steps run
  *     from the tape (one captured graph replayed per segment, unless graphs
  *     are off: mpx_set_graph_steps(sim, 0));
+ *     Where no film's reach (its face box grown by one slot) meets a CPML
+ *     slab, the transposes of the two half steps around an integer time run
+ *     as one field pass;
  *   1 plain: every reverse step reloads its input state and recomputes its
- *     half steps (the reference the tape schedule is tested against).
+ *     half steps (the reference the tape schedule is tested against);
+ *   2 tape, every half-step transpose in a pass of its own (the same bits
+ *     as 0).
  * Errors: MPX_E_INVALID for another value. */
 mpx_status mpx_set_adjoint_schedule(mpx_sim *sim, int32_t schedule);
 

@@ -1166,7 +1166,8 @@ __device__ __forceinline__ bool hface_nb(const AdjParams<T> &A, const int *t, in
 // gradient, scaled) for the slot t: added to its three lambda E values (in
 // registers) and to lambda H of its three faces (film faces: no other thread
 // of the pass reads them)
-template <typename T>
+// (PART: 0 both terms, 1 the lambda E term only, 2 the lambda H term only)
+template <typename T, int PART = 0>
 __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, long long q, T &l0, T &l1, T &l2) {
     const KParams<T> &p = A.p;
     const FilmDev &F = p.films[A.lfilm];
@@ -1186,7 +1187,7 @@ __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, l
                 for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
                 if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) se += eps;
             }
-        if (se != 0.0) le[C] += (T)(A.lscale * p.dV * p.eps0 * se * 0.25 * A.ltape[C * tb + ri]);
+        if (PART != 2 && se != 0.0) le[C] += (T)(A.lscale * p.dV * p.eps0 * se * 0.25 * A.ltape[C * tb + ri]);
         int nc = 0;
         for (int u = 0; u < 2; u++) {
             int cc[3] = {t[0], t[1], t[2]};
@@ -1194,7 +1195,7 @@ __device__ __forceinline__ void loss_term(const AdjParams<T> &A, const int *t, l
             for (int a = 0; a < 3; a++) cc[a] = fold(cc[a], p.n[a], p.per[a]);
             if (cc[0] >= 0 && cc[1] >= 0 && cc[2] >= 0 && film_cell(p, F, cc[0], cc[1], cc[2], eps)) nc++;
         }
-        if (nc) A.lH[C][q] += (T)(A.lscale * p.dV * p.mu0 * 0.5 * nc * A.ltape[(3 + C) * tb + ri]);
+        if (PART != 1 && nc) A.lH[C][q] += (T)(A.lscale * p.dV * p.mu0 * 0.5 * nc * A.ltape[(3 + C) * tb + ri]);
     }
     l0 = le[0];
     l1 = le[1];
@@ -1266,6 +1267,225 @@ __device__ __forceinline__ void hfield_general(const AdjParams<T> &A, const int 
         hface<T, 0, FILM>(A, u, false, x0, x1);
         d[4] = dif((ok ? x0 : T(0)) - a, T(0), p.dT[1], p.invd[1]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// The merged pass of two consecutive half-step transposes on the E side: the
+// first half step of step m (with the E step's lambda E = ca lambda E', the
+// eps-box sums, the loss term's lambda E part and a weighted trace's term of
+// the state at step m's start), then the second half step of step m - 1,
+// whose lambda H of non-film faces is the same (the first pass changes lambda
+// E only; the film kernels between them change the film region's faces,
+// which both take from their own tables).  A face's CPML state goes through
+// both recursions in one thread (read from set lpsiH, stored in lpsiHo);
+// every value follows the two single passes' operation sequence, so the
+// results are theirs, bitwise.  Used only where no film's reach meets a CPML
+// slab (the film-region passes keep their state per half step).
+// ---------------------------------------------------------------------------
+
+// the two half steps' curl-part adjoints (a0, a1: the first; b0, b1: the
+// second) of the face of family F at slot f; own: store its lambda psiH after
+// both maps
+template <typename T, int F, int FILM>
+__device__ __forceinline__ void hface2(const AdjParams<T> &A, const int *f, bool own, T &a0, T &a1, T &b0, T &b1) {
+    constexpr int F1 = (F + 1) % 3, F2 = (F + 2) % 3;
+    const KParams<T> &p = A.p;
+    if (FILM) {
+        long long lr;
+        const int fr = first_region(A, f, lr);
+        if (fr >= 0) {
+            const AdjFilmDev G = scalar_desc(A.af, fr), Gb = scalar_desc(A.afb, fr);
+            a0 = (T)G.aDr[(F * 2) * G.nr + lr];
+            a1 = (T)G.aDr[(F * 2 + 1) * G.nr + lr];
+            b0 = (T)Gb.aDr[(F * 2) * Gb.nr + lr];
+            b1 = (T)Gb.aDr[(F * 2 + 1) * Gb.nr + lr];
+            return;
+        }
+    }
+    const T lH = A.lH[F][p.slot(f[0], f[1], f[2])];
+    const T g1 = -p.hc * lH, g2 = p.hc * lH;
+    a0 = b0 = g1;
+    a1 = b1 = g2;
+    const int c1 = f[F1], c2 = f[F2];
+    if (p.psiH[F][F1] && (c1 < p.nlo[F1] || c1 >= p.n[F1] - p.nhi[F1])) {
+        const long long qq = p.psi_index(F1, f);
+        const T bb = p.bH[F1][c1], cc = p.cH[F1][c1];
+        const T aps = A.lpsiH[F][F1][qq] + g1;
+        a0 = g1 + cc * aps;
+        const T aps2 = bb * aps + g1;
+        b0 = g1 + cc * aps2;
+        if (own) A.lpsiHo[F][F1][qq] = bb * aps2;
+    }
+    if (p.psiH[F][F2] && (c2 < p.nlo[F2] || c2 >= p.n[F2] - p.nhi[F2])) {
+        const long long qq = p.psi_index(F2, f);
+        const T bb = p.bH[F2][c2], cc = p.cH[F2][c2];
+        const T aps = A.lpsiH[F][F2][qq] + g2;
+        a1 = g2 + cc * aps;
+        const T aps2 = bb * aps + g2;
+        b1 = g2 + cc * aps2;
+        if (own) A.lpsiHo[F][F2][qq] = bb * aps2;
+    }
+}
+
+// the six differences of each half step (d: the first, e: the second), as
+// hfield_general's
+template <typename T, int FILM>
+__device__ __forceinline__ void hfield_general2(const AdjParams<T> &A, const int *t, T *d, T *e) {
+    const KParams<T> &p = A.p;
+    T a0, a1, b0, b1, x0, x1, y0, y1;
+    int u[3];
+    bool ok;
+    // own face of family 1: with the family-1 faces at k - 1 and i - 1
+    hface2<T, 1, FILM>(A, t, true, a0, a1, b0, b1);
+    ok = nb_or_self<-1>(p.n, p.per, t, 2, u);
+    hface2<T, 1, FILM>(A, u, false, x0, x1, y0, y1);
+    d[0] = dif((ok ? x0 : T(0)) - a0, T(0), p.dT[2], p.invd[2]);
+    e[0] = dif((ok ? y0 : T(0)) - b0, T(0), p.dT[2], p.invd[2]);
+    ok = nb_or_self<-1>(p.n, p.per, t, 0, u);
+    hface2<T, 1, FILM>(A, u, false, x0, x1, y0, y1);
+    d[5] = dif((ok ? x1 : T(0)) - a1, T(0), p.dT[0], p.invd[0]);
+    e[5] = dif((ok ? y1 : T(0)) - b1, T(0), p.dT[0], p.invd[0]);
+    // family 2: with the family-2 faces at j - 1 and i - 1
+    hface2<T, 2, FILM>(A, t, true, a0, a1, b0, b1);
+    ok = nb_or_self<-1>(p.n, p.per, t, 1, u);
+    hface2<T, 2, FILM>(A, u, false, x0, x1, y0, y1);
+    d[1] = dif((ok ? x1 : T(0)) - a1, T(0), p.dT[1], p.invd[1]);
+    e[1] = dif((ok ? y1 : T(0)) - b1, T(0), p.dT[1], p.invd[1]);
+    ok = nb_or_self<-1>(p.n, p.per, t, 0, u);
+    hface2<T, 2, FILM>(A, u, false, x0, x1, y0, y1);
+    d[2] = dif((ok ? x0 : T(0)) - a0, T(0), p.dT[0], p.invd[0]);
+    e[2] = dif((ok ? y0 : T(0)) - b0, T(0), p.dT[0], p.invd[0]);
+    // family 0: with the family-0 faces at k - 1 and j - 1
+    hface2<T, 0, FILM>(A, t, true, a0, a1, b0, b1);
+    ok = nb_or_self<-1>(p.n, p.per, t, 2, u);
+    hface2<T, 0, FILM>(A, u, false, x0, x1, y0, y1);
+    d[3] = dif((ok ? x1 : T(0)) - a1, T(0), p.dT[2], p.invd[2]);
+    e[3] = dif((ok ? y1 : T(0)) - b1, T(0), p.dT[2], p.invd[2]);
+    ok = nb_or_self<-1>(p.n, p.per, t, 1, u);
+    hface2<T, 0, FILM>(A, u, false, x0, x1, y0, y1);
+    d[4] = dif((ok ? x0 : T(0)) - a0, T(0), p.dT[1], p.invd[1]);
+    e[4] = dif((ok ? y0 : T(0)) - b0, T(0), p.dT[1], p.invd[1]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_hfield2(AdjParams<T> A) {
+    const KParams<T> &p = A.p;
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (i >= p.n[0] || j >= p.n[1]) return;
+    const int t[3] = {i, j, k};
+    const long long q = p.slot(i, j, k);
+    const uint8_t fl = (uint8_t)adj_tile_flag(A.aflags);
+    T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
+    T ca[3], cb[3];
+    bool ok[3];
+    edge_coefs<T>(p, t, q, ca, cb, ok);
+    T dd[6], de[6];
+    if (fl == 0) {
+        // no CPML state, no film region: both half steps take -/+ hc lambda H
+        T o0[3], o1[3];
+        T n1m2 = T(0), n2m1 = T(0), n2m0 = T(0), n0m2 = T(0), n0m1 = T(0), n1m0 = T(0);
+        int u[3];
+#pragma unroll
+        for (int F = 0; F < 3; F++) {
+            const T l = A.lH[F][q];
+            o0[F] = -(p.hc * l);
+            o1[F] = p.hc * l;
+        }
+        bool ok2 = nb_or_self<-1>(p.n, p.per, t, 2, u);
+        const T h1m2 = A.lH[1][p.slot(u[0], u[1], u[2])], h0m2 = A.lH[0][p.slot(u[0], u[1], u[2])];
+        bool ok1 = nb_or_self<-1>(p.n, p.per, t, 1, u);
+        const T h2m1 = A.lH[2][p.slot(u[0], u[1], u[2])], h0m1 = A.lH[0][p.slot(u[0], u[1], u[2])];
+        bool ok0 = nb_or_self<-1>(p.n, p.per, t, 0, u);
+        const T h2m0 = A.lH[2][p.slot(u[0], u[1], u[2])], h1m0 = A.lH[1][p.slot(u[0], u[1], u[2])];
+        if (ok2) {
+            n1m2 = -(p.hc * h1m2);
+            n0m2 = p.hc * h0m2;
+        }
+        if (ok1) {
+            n2m1 = p.hc * h2m1;
+            n0m1 = -(p.hc * h0m1);
+        }
+        if (ok0) {
+            n2m0 = -(p.hc * h2m0);
+            n1m0 = p.hc * h1m0;
+        }
+        dd[0] = dif(n1m2 - o0[1], T(0), p.dT[2], p.invd[2]);
+        dd[1] = dif(n2m1 - o1[2], T(0), p.dT[1], p.invd[1]);
+        dd[2] = dif(n2m0 - o0[2], T(0), p.dT[0], p.invd[0]);
+        dd[3] = dif(n0m2 - o1[0], T(0), p.dT[2], p.invd[2]);
+        dd[4] = dif(n0m1 - o0[0], T(0), p.dT[1], p.invd[1]);
+        dd[5] = dif(n1m0 - o1[1], T(0), p.dT[0], p.invd[0]);
+#pragma unroll
+        for (int w = 0; w < 6; w++) de[w] = dd[w];
+    } else if (fl & 4) {
+        hfield_general2<T, 1>(A, t, dd, de);
+    } else {
+        hfield_general2<T, 0>(A, t, dd, de);
+    }
+    if (A.btape) {
+        // dL/dca += lambda E' E^n, dL/dcb += lambda E' x^n over the eps box
+        const int r[3] = {A.bs[0] + 1, A.bs[1] + 1, A.bs[2] + 1};
+        const long long ri = region_index_folded(p.n, p.per, A.bb, r, t);
+        if (ri >= 0) {
+            const long long tb = (long long)r[0] * r[1] * r[2];
+            const T lv[3] = {l0, l1, l2};
+#pragma unroll
+            for (int C = 0; C < 3; C++) {
+                A.gca_box[C * tb + ri] += (double)lv[C] * A.btape[C * tb + ri];
+                A.gcb_box[C * tb + ri] += (double)lv[C] * A.btape[(3 + C) * tb + ri];
+            }
+        }
+    }
+    // the first half step of step m (the E step's scaling first)
+    l0 = ok[0] ? ca[0] * l0 : T(0);
+    l1 = ok[1] ? ca[1] * l1 : T(0);
+    l2 = ok[2] ? ca[2] * l2 : T(0);
+    l0 = l0 + (dd[0] + dd[1]);
+    l1 = l1 + (dd[2] + dd[3]);
+    l2 = l2 + (dd[4] + dd[5]);
+    if (A.ltape && (fl & 4) && A.seg0[0] + A.m > A.loss_from) loss_term<T, 1>(A, t, q, l0, l1, l2);
+    if (A.pw && q == A.pw_slot) {
+        const long long n = A.seg0[0] + A.m;
+        if (n >= 1) {
+            const T v = (T)(A.pw_scale * A.pw[n - 1]);
+            if (A.pw_comp == 0)
+                l0 += v;
+            else if (A.pw_comp == 1)
+                l1 += v;
+            else
+                l2 += v;
+        }
+    }
+    // the second half step of step m - 1
+    l0 = l0 + (de[0] + de[1]);
+    l1 = l1 + (de[2] + de[3]);
+    l2 = l2 + (de[4] + de[5]);
+    A.lE[0][q] = l0;
+    A.lE[1][q] = l1;
+    A.lE[2][q] = l2;
+    A.mu[0][q] = ok[0] ? cb[0] * l0 : T(0);
+    A.mu[1][q] = ok[1] ? cb[1] * l1 : T(0);
+    A.mu[2][q] = ok[2] ? cb[2] * l2 : T(0);
+}
+
+// the loss term's lambda H part of the state at step m's start, for the film
+// region's faces (before the film kernels of the next half step read them)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_loss_h(AdjParams<T> A) {
+    const KParams<T> &p = A.p;
+    if (!(A.seg0[0] + A.m > A.loss_from)) return;
+    const FilmDev F = film_desc(p.films, A.lfilm);
+    const int r[3] = {F.cb[3] + 1, F.cb[4] + 1, F.cb[5] + 1};
+    const long long lr = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (lr >= (long long)r[0] * r[1] * r[2]) return;
+    int t[3] = {F.cb[0] + (int)(lr % r[0]), F.cb[1] + (int)((lr / r[0]) % r[1]),
+                F.cb[2] + (int)(lr / ((long long)r[0] * r[1]))};
+    for (int a = 0; a < 3; a++) {
+        if (t[a] >= p.n[a] && p.per[a]) t[a] -= p.n[a];
+        if (t[a] >= p.n[a]) return;
+    }
+    T l0 = T(0), l1 = T(0), l2 = T(0);
+    loss_term<T, 2>(A, t, p.slot(t[0], t[1], t[2]), l0, l1, l2);
 }
 
 // the transposed half step on the E side: lambda E_C += the transposed curl
@@ -1670,6 +1890,30 @@ hipError_t launch_adj_half_fused(const AdjParams<T> &A, int nblk, int scale, con
     return hipGetLastError();
 }
 
+// the film part of a half-step transpose (the magnetic faces' LLG transpose,
+// the film reach's faces and their table), then the merged field pass
+template <typename T>
+hipError_t launch_adj_film_part(const AdjParams<T> &A, int nblk, const long long *film_nr, hipStream_t s) {
+    if (nblk) k_adj_film<T><<<dim3(nblk), dim3(256), 0, s>>>(A);
+    for (int f = 0; f < A.p.nfilm; f++)
+        if (film_nr[f] > 0)
+            k_adj_film_faces<T><<<dim3((unsigned)((film_nr[f] + 255) / 256), 3), dim3(256), 0, s>>>(A, f);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_hfield2(const AdjParams<T> &A, hipStream_t s) {
+    k_adj_hfield2<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_loss_h(const AdjParams<T> &A, const int *film_cb, hipStream_t s) {
+    const long long nr = (long long)(film_cb[3] + 1) * (film_cb[4] + 1) * (film_cb[5] + 1);
+    if (nr > 0) k_adj_loss_h<T><<<dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s>>>(A);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_adj_estep_fused(const AdjParams<T> &A, hipStream_t s) {
     k_adj_efield<T><<<slot_grid(A.p.n), dim3(64, 4), 0, s>>>(A);
@@ -1702,6 +1946,9 @@ hipError_t launch_copy_segs(const CopySeg *segs, int nseg, int nblk, hipStream_t
     template hipError_t launch_film_energy<T>(const KParams<T> &, int, double *, double *, double, hipStream_t); \
     template hipError_t launch_adj_half_fused<T>(const AdjParams<T> &, int, int, const long long *, hipStream_t); \
     template hipError_t launch_adj_estep_fused<T>(const AdjParams<T> &, hipStream_t);                           \
+    template hipError_t launch_adj_film_part<T>(const AdjParams<T> &, int, const long long *, hipStream_t);     \
+    template hipError_t launch_adj_hfield2<T>(const AdjParams<T> &, hipStream_t);                               \
+    template hipError_t launch_adj_loss_h<T>(const AdjParams<T> &, const int *, hipStream_t);                    \
     template hipError_t launch_add_one<T>(T *, long long, double, hipStream_t);                                 \
     template hipError_t launch_tape_loss<T>(const KParams<T> &, int, int, double *, hipStream_t, const int *);   \
     template hipError_t launch_adj_loss_tape<T>(const AdjParams<T> &, int, double, const double *,              \

@@ -70,7 +70,8 @@ struct mpx_sim {
     void *H2[3] = {nullptr, nullptr, nullptr};
     int parity = 0;
     int fused = 0; // separate passes (the fastest schedule measured on gfx950)
-    int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule
+    int adj_schedule = 0; // mpx_adjoint: 0 tape schedule, 1 plain recompute-per-step schedule, 2 tape schedule
+                          // with every half-step transpose in a pass of its own
     // tape schedule: the most device memory the tapes kept from the forward
     // run may take (-1: three quarters of the free memory, with the
     // checkpoints of the other segments; 0: none, every segment recomputed)
@@ -1044,7 +1045,7 @@ struct AdjHost {
     void *lpsiH2[3][3] = {}, *lpsiE2[3][3] = {};  // tape schedule: second lambda psi sets
     uint8_t *d_aflags = nullptr;
     void *mu[3] = {};
-    std::vector<double *> aDr;
+    std::vector<double *> aDr, aDr2; // per film: the reach's curl-part table of each half step of a step
     std::vector<long long> film_nr;
 };
 
@@ -1081,6 +1082,7 @@ void adj_free(AdjHost &h) {
     (void)hipFree(h.d_aflags);
     for (int c = 0; c < 3; c++) (void)hipFree(h.mu[c]);
     for (double *d : h.aDr) (void)hipFree(d);
+    for (double *d : h.aDr2) (void)hipFree(d);
     (void)hipFree(h.gbox_a);
     (void)hipFree(h.gbox_b);
     (void)hipFree(h.d_seg0);
@@ -1604,12 +1606,14 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     AdjHost h;
     Tape tp;
     // captured segments: 0 the forward run with the tape and the probes, 1 a
-    // recompute with the tape, 2 the reverse steps
-    hipGraph_t graph[3] = {};
-    hipGraphExec_t gexec[3] = {};
+    // recompute with the tape, 2 and 3 the reverse steps from lambda psiH set
+    // 0 and set 1
+    hipGraph_t graph[4] = {};
+    hipGraphExec_t gexec[4] = {};
     char *pages = nullptr; // the tapes kept from the forward run
     bool probe_added = false;
     double *d_lacc = nullptr; // the film-energy loss's own eps_r term per film cell
+    bool merge = s->adj_schedule == 0; // one field pass for the two half-step transposes around an integer time
     auto body = [&]() -> mpx_status {
         mpx_status q;
         if ((q = adj_alloc(s, h, neps, false)) != MPX_OK) return q;
@@ -1650,9 +1654,11 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
                 nr *= g.rn[a];
             }
             g.nr = nr;
-            double *d = nullptr;
+            double *d = nullptr, *d2 = nullptr;
             CK(hipMalloc(&d, 6 * nr * sizeof(double)));
+            CK(hipMalloc(&d2, 6 * nr * sizeof(double)));
             h.aDr.push_back(d);
+            h.aDr2.push_back(d2);
             g.aDr = d;
             h.film_nr.push_back(nr);
         }
@@ -1681,12 +1687,22 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             CK(hipMalloc(&h.d_aflags, ((size_t)nt + 4) / 4 * 4)); // whole words (read through the scalar cache)
             CK(hipMemcpy(h.d_aflags, fl.data(), nt, hipMemcpyHostToDevice));
         }
+        // the merged reverse pass needs the films' reaches off the CPML slabs
+        // (their faces keep no CPML state between half steps)
+        for (auto &g : h.af)
+            for (int a = 0; a < 3; a++) {
+                if (s->nlo[a] > 0 && g.r0[a] < s->nlo[a]) merge = false;
+                if (s->nhi[a] > 0 && g.r0[a] + g.rn[a] > s->n[a] - s->nhi[a]) merge = false;
+            }
         if (!h.af.empty()) {
             CK(hipMemcpy(h.d_af, h.af.data(), h.af.size() * sizeof(AdjFilmDev), hipMemcpyHostToDevice));
             // lambda M ping-pong: the first map of a step reads lM and writes
             // lMout, the second reads lMout and writes lM
             std::vector<AdjFilmDev> af2 = h.af;
-            for (auto &g : af2) std::swap(g.lM, g.lMout);
+            for (size_t f = 0; f < af2.size(); f++) {
+                std::swap(af2[f].lM, af2[f].lMout);
+                af2[f].aDr = h.aDr2[f]; // the first half step's table (kept for the merged pass)
+            }
             CK(hipMalloc(&h.d_af2, af2.size() * sizeof(AdjFilmDev)));
             CK(hipMemcpy(h.d_af2, af2.data(), af2.size() * sizeof(AdjFilmDev), hipMemcpyHostToDevice));
         }
@@ -1767,10 +1783,15 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             }
             return MPX_OK;
         };
-        std::function<mpx_status(int)> rev;
+        std::function<int(int, int)> rev;
+        // the lambda psiH set a segment's reverse steps end in
+        auto rev_end = [&](int len, int cs) { return merge ? cs ^ ((len + 1) & 1) : cs; };
         // one captured graph per kind serves every full-length segment
         auto run = [&](int kind, int len) -> mpx_status {
-            auto direct = [&]() { return kind == 2 ? rev(len) : fwd(len, kind == 0); };
+            auto direct = [&]() -> mpx_status {
+                if (kind >= 2) return rev(len, kind - 2) < 0 ? MPX_E_DEVICE : MPX_OK;
+                return fwd(len, kind == 0);
+            };
             if (len != K || ncp < 2 || s->graph_steps <= 0) return direct();
             if (!gexec[kind]) {
                 CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1892,61 +1913,107 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             CK(launch_add_one<T>((T *)h.lE[ls.field], pw_slot, S * ls.w[N - 1], st));
         }
 
-        rev = [&](int len) -> mpx_status {
-            for (int m = len - 1; m >= 0; m--) {
-                if (d_lacc) {
-                    // the loss's eps_r term of the step's input state
-                    KParams<T> pe;
-                    fill_params<T>(s, pe, MODE_INPLACE, s->parity);
-                    CK(launch_adj_loss_eps_tape<T>(pe, film, dt * S, tp.lossp(m), h.d_seg0, m, loss_from, d_lacc,
-                                                   st, LF.cb));
-                }
-                AdjParams<T> A;
-                adj_params<T>(s, h, A);
-                A.aflags = h.d_aflags;
-                A.seg0 = h.d_seg0;
-                A.m = m;
-                A.btape = neps > 0 ? tp.boxp(m) : nullptr;
-                A.gca_box = h.gbox_a;
-                A.gcb_box = h.gbox_b;
+        // the reverse steps' parameters for step m of the segment in hand
+        auto params = [&](int m) {
+            AdjParams<T> A;
+            adj_params<T>(s, h, A);
+            A.aflags = h.d_aflags;
+            A.seg0 = h.d_seg0;
+            A.m = m;
+            A.btape = neps > 0 ? tp.boxp(m) : nullptr;
+            A.gca_box = h.gbox_a;
+            A.gcb_box = h.gbox_b;
+            for (int a = 0; a < 3; a++) {
+                A.bb[a] = eps_box[a];
+                A.bs[a] = eps_box[3 + a];
+            }
+            A.ltape = floss ? tp.lossp(m) : nullptr;
+            A.lfilm = film;
+            A.lscale = dt * S;
+            A.loss_from = loss_from;
+            A.pw = d_w;
+            A.pw_slot = pw_slot;
+            A.pw_comp = ls.field;
+            A.pw_scale = S;
+            for (int c = 0; c < 3; c++) {
+                A.mu[c] = (T *)h.mu[c];
+                for (int a = 0; a < 3; a++) A.lpsiE2[c][a] = (T *)h.lpsiE2[c][a];
+            }
+            return A;
+        };
+        // lambda psiH: set 0 (adj_params' lpsiH) or 1 (lpsiH2); a half-step
+        // pass reads set `from` and writes the other
+        auto psi_sets = [&](AdjParams<T> &A, int from) {
+            for (int c = 0; c < 3; c++)
                 for (int a = 0; a < 3; a++) {
-                    A.bb[a] = eps_box[a];
-                    A.bs[a] = eps_box[3 + a];
+                    A.lpsiH[c][a] = (T *)(from ? h.lpsiH2[c][a] : h.lpsiH[c][a]);
+                    A.lpsiHo[c][a] = (T *)(from ? h.lpsiH[c][a] : h.lpsiH2[c][a]);
                 }
-                A.ltape = floss ? tp.lossp(m) : nullptr;
-                A.lfilm = film;
-                A.lscale = dt * S;
-                A.loss_from = loss_from;
-                A.pw = d_w;
-                A.pw_slot = pw_slot;
-                A.pw_comp = ls.field;
-                A.pw_scale = S;
-                for (int c = 0; c < 3; c++) {
-                    A.mu[c] = (T *)h.mu[c];
-                    for (int a = 0; a < 3; a++) {
-                        A.lpsiE2[c][a] = (T *)h.lpsiE2[c][a];
-                        A.lpsiHo[c][a] = (T *)h.lpsiH2[c][a];
-                    }
-                }
-                // the second half step: lambda psiH set 1 -> set 2
-                A.p.films = tvar(tp, m, V_P1);
-                A.af = h.d_af;
-                CK(launch_adj_half_fused<T>(A, nblk, 0, h.film_nr.data(), st));
-                CK(launch_adj_estep_fused<T>(A, st));
-                // the first half step (with the E step's lambda E = ca lambda E',
-                // the eps-box sums and the loss term of the step's input
-                // state): lambda psiH set 2 -> set 1
-                for (int c = 0; c < 3; c++)
-                    for (int a = 0; a < 3; a++) {
-                        A.lpsiH[c][a] = (T *)h.lpsiH2[c][a];
-                        A.lpsiHo[c][a] = (T *)h.lpsiH[c][a];
-                    }
-                A.p.films = tvar(tp, m, V_R1);
-                A.af = h.d_af2;
-                CK(launch_adj_half_fused<T>(A, nblk, 1, h.film_nr.data(), st));
+        };
+        auto loss_eps = [&](int m) -> mpx_status {
+            if (d_lacc) {
+                // the loss's eps_r term of the step's input state
+                KParams<T> pe;
+                fill_params<T>(s, pe, MODE_INPLACE, s->parity);
+                CK(launch_adj_loss_eps_tape<T>(pe, film, dt * S, tp.lossp(m), h.d_seg0, m, loss_from, d_lacc, st,
+                                               LF.cb));
             }
             return MPX_OK;
         };
+        // the adjoint steps of a segment from its tape, lambda psiH starting
+        // in set cs; returns the set it ends in.  Per step m (backwards): the
+        // second half step's transpose, the E step's, the first half step's.
+        // With `merge`, the first half step of step m and the second of step
+        // m - 1 share one field pass (their film parts run before it).
+        rev = [&](int len, int cs) -> int {
+            int cur = cs;
+            for (int m = len - 1; m >= 0; m--) {
+                if (!merge || m == len - 1) {
+                    if (loss_eps(m) != MPX_OK) return -1;
+                    AdjParams<T> A = params(m);
+                    psi_sets(A, cur);
+                    A.p.films = tvar(tp, m, V_P1);
+                    A.af = h.d_af;
+                    if (launch_adj_half_fused<T>(A, nblk, 0, h.film_nr.data(), st) != hipSuccess) return -1;
+                    cur ^= 1;
+                    if (launch_adj_estep_fused<T>(A, st) != hipSuccess) return -1;
+                }
+                if (merge && m > 0) {
+                    // the first half step of step m: its film part, the loss
+                    // term's lambda H part of step m's input state
+                    AdjParams<T> A = params(m);
+                    psi_sets(A, cur);
+                    A.p.films = tvar(tp, m, V_R1);
+                    A.af = h.d_af2;
+                    if (launch_adj_film_part<T>(A, nblk, h.film_nr.data(), st) != hipSuccess) return -1;
+                    if (floss && launch_adj_loss_h<T>(A, LF.cb, st) != hipSuccess) return -1;
+                    // the second half step of step m - 1: its film part
+                    if (loss_eps(m - 1) != MPX_OK) return -1;
+                    AdjParams<T> B = params(m - 1);
+                    psi_sets(B, cur ^ 1);
+                    B.p.films = tvar(tp, m - 1, V_P1);
+                    B.af = h.d_af;
+                    if (launch_adj_film_part<T>(B, nblk, h.film_nr.data(), st) != hipSuccess) return -1;
+                    // both field transposes in one pass, then step m - 1's E step
+                    A.afb = h.d_af;
+                    if (launch_adj_hfield2<T>(A, st) != hipSuccess) return -1;
+                    cur ^= 1;
+                    if (launch_adj_estep_fused<T>(B, st) != hipSuccess) return -1;
+                } else {
+                    // the first half step (with the E step's lambda E = ca
+                    // lambda E', the eps-box sums and the loss term of the
+                    // step's input state)
+                    AdjParams<T> A = params(m);
+                    psi_sets(A, cur);
+                    A.p.films = tvar(tp, m, V_R1);
+                    A.af = h.d_af2;
+                    if (launch_adj_half_fused<T>(A, nblk, 1, h.film_nr.data(), st) != hipSuccess) return -1;
+                    cur ^= 1;
+                }
+            }
+            return cur;
+        };
+        int psi_cur = 0;
         for (int g = ncp - 1; g >= 0; g--) {
             const long long c0 = (long long)g * K;
             const int len = (int)std::min<long long>(K, N - c0);
@@ -1961,7 +2028,8 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
             CK(launch_set_step(s->d_step, s->step, st));
             CK(launch_set_step(h.d_seg0, c0, st));
             if (g < g0 && (q = run(1, len)) != MPX_OK) return q;
-            if ((q = run(2, len)) != MPX_OK) return q;
+            if ((q = run(2 + psi_cur, len)) != MPX_OK) return q;
+            psi_cur = rev_end(len, psi_cur);
         }
         // the initial magnetisation M0 = Ms u
         if (step0 == 0 && s->have_u) CK(launch_adj_init_ms(s->d_blocktab, nblk, s->d_films, h.d_af, s->u, st));
@@ -1994,7 +2062,7 @@ mpx_status run_adjoint_tape(mpx_sim *s, long long N, const AdjLoss &ls, int K, c
     if (r != MPX_OK) (void)hipStreamSynchronize(st);
     (void)hipFree(d_w);
     (void)hipFree(d_lacc);
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < 4; k++) {
         if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
         if (graph[k]) (void)hipGraphDestroy(graph[k]);
     }
@@ -3124,7 +3192,7 @@ mpx_status mpx_adjoint(mpx_sim *s, int64_t nsteps, int64_t loss_from, int32_t fi
     AdjLoss ls;
     ls.film = film;
     ls.loss_from = loss_from;
-    if (s->adj_schedule == 0)
+    if (s->adj_schedule != 1)
         r = s->prec == MPX_F64 ? run_adjoint_tape<double>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs)
                                : run_adjoint_tape<float>(s, nsteps, ls, K, eps_box, ms_box, loss, dL_dH0, dL_deps, dL_dMs);
     else
@@ -3141,7 +3209,7 @@ mpx_status mpx_adjoint_probe(mpx_sim *s, int64_t nsteps, int32_t field, const in
     if (r != MPX_OK) return r;
     if (!s->have_mat) return fail(s, MPX_E_STATE, "adjoint before set_materials");
     if (!s->films.empty() && !s->have_u) return fail(s, MPX_E_STATE, "adjoint before init_magnetization");
-    if (s->adj_schedule != 0) return fail(s, MPX_E_UNSUPPORTED, "a weighted-trace loss needs the tape schedule");
+    if (s->adj_schedule == 1) return fail(s, MPX_E_UNSUPPORTED, "a weighted-trace loss needs the tape schedule");
     if (nsteps < 1 || field < 0 || field > 2 || !ijk || !weights || checkpoint_every < 0 || !eps_box || !ms_box ||
         !loss || !dL_dH0)
         return fail(s, MPX_E_INVALID, "adjoint arguments");
@@ -3172,7 +3240,7 @@ mpx_status mpx_adjoint_probe(mpx_sim *s, int64_t nsteps, int32_t field, const in
 mpx_status mpx_set_adjoint_schedule(mpx_sim *s, int32_t schedule) {
     mpx_status r = check_live(s);
     if (r != MPX_OK) return r;
-    if (schedule < 0 || schedule > 1) return fail(s, MPX_E_INVALID, "adjoint schedule");
+    if (schedule < 0 || schedule > 2) return fail(s, MPX_E_INVALID, "adjoint schedule");
     s->adj_schedule = schedule;
     return MPX_OK;
 }

@@ -190,6 +190,9 @@ struct AdjParams {
     T *eD[3][2];           // per edge: lambda of the two curl parts of H
     double *gca[3], *gcb[3]; // per edge: accumulated dL/dca, dL/dcb
     const AdjFilmDev *af;
+    // the merged pass of two half-step transposes (the first half step of
+    // step m, then the second of step m - 1): the film tables of the second
+    const AdjFilmDev *afb;
     // fused schedule: destination set of lambda psiH (read from lpsiH), the
     // second lambda psiE set (the E-step adjoint of step n reads set n & 1
     // and writes the other), per-tile flags (1 CPML, 4 film reach, with a
@@ -247,6 +250,10 @@ long long box_tape_size(const int *box);
 // lambda E = ca lambda E') and the E-step adjoint as one stencil pass each
 template <typename T>
 hipError_t launch_adj_half_fused(const AdjParams<T> &A, int nblk, int scale, const long long *film_nr, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_film_part(const AdjParams<T> &A, int nblk, const long long *film_nr, hipStream_t s);
+template <typename T> hipError_t launch_adj_hfield2(const AdjParams<T> &A, hipStream_t s);
+template <typename T> hipError_t launch_adj_loss_h(const AdjParams<T> &A, const int *film_cb, hipStream_t s);
 template <typename T> hipError_t launch_adj_estep_fused(const AdjParams<T> &A, hipStream_t s);
 template <typename T> hipError_t launch_adj_estep(const AdjParams<T> &A, hipStream_t s);
 template <typename T> hipError_t launch_adj_loss(const AdjParams<T> &A, int film, double scale, hipStream_t s);

@@ -367,7 +367,10 @@ class Sim:
         return {"loss": loss.value, "dH0": np.array(dh0[:]), "deps": deps, "dMs": dms}
 
     def set_adjoint_schedule(self, schedule: int):
-        """0: tape schedule (default); 1: plain recompute-per-step schedule."""
+        """0: tape schedule (default; the two half-step transposes around an
+        integer time in one pass where the films allow); 1: plain
+        recompute-per-step schedule; 2: tape schedule with every half-step
+        transpose in a pass of its own (same results as 0)."""
         self._ck(self._L.mpx_set_adjoint_schedule(self._h, int(schedule)), "set_adjoint_schedule")
 
     def set_adjoint_memory(self, max_bytes: int):

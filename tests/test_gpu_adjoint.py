@@ -390,3 +390,44 @@ def test_kept_tapes_match_recompute(prec):
                 err = float(np.abs(r[key] - ref[key]).max()) / sc
                 say(f"  {key}: max |kept - recomputed| / max = {err:.2e}")
                 assert err <= 1e-6, (cap, key)
+
+
+def pmlz_case():
+    """The small case with CPML slabs on the z faces only: the film's reach
+    stays off them, so the merged reverse pass runs, with CPML state."""
+    w = W.random_case(11, nx=20, ny=16, nz=14, nsteps=60, bc=(W.PEC, W.PEC, W.PEC, W.PEC, W.PML, W.PML),
+                      npml=(0, 0, 0, 0, 2, 2))
+    w.H0 = (3e6, 0.0, 5e6)
+    return w
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+@pytest.mark.parametrize("case,n,n0,K", [("pec", 60, 30, 7), ("pmlz", 60, 0, 60), ("pmlz", 33, 20, 1),
+                                         ("periodic", 40, 10, 6), ("pmlz", 41, 10, 8), ("pml", 30, 10, 5)])
+def test_merged_reverse_pass_bitwise(case, n, n0, K, prec):
+    """The tape schedule's merged pass (the first half step of step m and the
+    second of step m - 1 in one field pass) against a pass per half step
+    (schedule 2): the same bits, for every gradient, the loss and the end
+    state."""
+    w = {"pec": lambda: small_case(False), "pml": lambda: small_case(True), "periodic": periodic_case,
+         "pmlz": pmlz_case}[case]()
+    fc = np.argwhere(w.ids == 3)
+    lo, hi = fc.min(axis=0), fc.max(axis=0)  # (k, j, i)
+    eps_box = (max(0, lo[2] - 2), max(0, lo[1] - 1), max(0, lo[0] - 3), min(6, w.nx - max(0, lo[2] - 2)), 4, 3)
+    ms_box = (lo[2], lo[1], lo[0], hi[2] - lo[2] + 1, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1)
+    say(f"merged vs separate reverse passes: {case} n={n} n0={n0} K={K} precision {prec}")
+    out = []
+    for sched in (0, 2):
+        g = mpx.from_workload(w, precision=prec)
+        g.set_adjoint_schedule(sched)
+        r = g.adjoint(n, n0, film=0, checkpoint_every=K, eps_box=eps_box, ms_box=ms_box)
+        r["fields"] = [g.get(f) for f in range(6)]
+        out.append(r)
+        g.close()
+    a, b = out
+    assert a["loss"] == b["loss"]
+    for f in range(6):
+        assert np.array_equal(a["fields"][f], b["fields"][f]), f
+    for key in ("dH0", "deps", "dMs"):
+        assert np.array_equal(a[key], b[key]), key
+    assert float(np.abs(b["dH0"]).max()) > 0

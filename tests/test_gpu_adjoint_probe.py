@@ -319,3 +319,24 @@ def test_probe_functional_splitting_resonator():
     assert close(H0.grad[2].item(), gz, abs(gz))
     assert close(f.grad.item(), gf, abs(gf))
     assert close(eps.grad.item(), ge, abs(ge), tol=1e-4)
+
+
+@pytest.mark.parametrize("prec", [mpx.F64, mpx.F32])
+def test_trace_adjoint_merged_pass_bitwise(prec):
+    """The weighted-trace adjoint with the merged reverse pass equals the
+    one with a pass per half step (schedule 2), bitwise."""
+    w = small_case(True)
+    n, K = 44, 6
+    kf, jf, i_f, kz0 = film_geometry(w)
+    ijk, eb, mb = (i_f, jf, kz0 - 1), (i_f - 2, jf - 1, kz0 - 3, 4, 2, 2), (i_f - 1, jf, kf, 3, 1, 1)
+    wt = np.random.default_rng(33).standard_normal(n)
+    out = []
+    for sched in (0, 2):
+        g = mpx.from_workload(w, precision=prec)
+        g.set_adjoint_schedule(sched)
+        out.append(g.adjoint_probe(n, 2, ijk, wt, checkpoint_every=K, eps_box=eb, ms_box=mb))
+        g.close()
+    a, b = out
+    assert a["loss"] == b["loss"]
+    for key in ("dH0", "deps", "dMs"):
+        assert np.array_equal(a[key], b[key]), key
