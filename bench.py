@@ -55,11 +55,19 @@ def algorithmic_bytes(w, esz):
 
 
 def kernel_source_hash():
+    """Hash of the forward kernels' sources with comments and blank lines
+    removed (an edited comment leaves the measured kernels, and this hash,
+    as they were)."""
+    import re
+
     h = hashlib.sha256()
     for f in ("kernels.hip", "passes.hip", "fused.hip", "sweep.hip", "stencil.h", "film.h", "device_common.h",
               "mpx_internal.h"):
-        with open(os.path.join(ROOT, "paper_2510_22221_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2510_22221_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(ln.rstrip() for ln in src.splitlines() if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

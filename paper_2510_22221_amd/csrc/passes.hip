@@ -174,8 +174,6 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     }
 }
 
-// a block: the TX x TY slots (bx, by) of plane k, flags from the table of
-// that tile shape
 // the flag byte of tile (bx, by, k) of the TX x TY table, read through the
 // scalar cache (the aligned word that holds it; the tables are whole words):
 // a vector load here would put the field loads behind its wait, since the
@@ -189,6 +187,8 @@ __device__ __forceinline__ int tile_flag(const KParams<T> &p, int bx, int by, in
     return (int)((w >> (8 * (int)(ti & 3))) & 0xffu);
 }
 
+// a block: the TX x TY slots (bx, by) of plane k, flags from the table of
+// that tile shape
 template <typename T, int CLS, int TX = PTX, int TY = PTY>
 __device__ __forceinline__ void epass_block(const KParams<T> &p, int bx, int by, int k) {
     epass_tile<T, CLS, TX>(p, bx * TX, by * TY, k, tile_flag<T, TX, TY>(p, bx, by, k), bx);
