@@ -147,10 +147,11 @@ def roofline_for(w, esz, kt, dtype_name, schedule=0, wkey="c5"):
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": traffic_from_profiles(name, dtype_name, wkey),
            "algorithmic_bytes_per_launch": ab[name], "avg_launch_ms": round(ms, 5), "launches_timed": nl,
-           "film_half1_and_probe_ms_per_step": round(kt[2][0], 5)}
+           "film_half1_ms_per_step": round(kt[2][0], 5)}
     if not fused:
         # the H/M pass group also holds the film's second half step (on
-        # 256 x 1 tiles in the same launch)
+        # 256 x 1 tiles in the same launch, with the probes when all of them
+        # read only E or a film's mean M)
         out["other_stencil_kernel"] = {"kernel": ("h_pass", "e_pass")[0 if name == "e_pass" else 1],
                                        "avg_launch_ms": round(kt[1 if name == "e_pass" else 0][0], 5)}
     return out

@@ -62,6 +62,82 @@ __device__ __forceinline__ int4 block_entry(const int4 *tab, int b) {
     return make_int4((int)src[0], (int)src[1], (int)src[2], (int)src[3]);
 }
 
+// ---------------------------------------------------------------------------
+// probes at an integer time (the probe launch, and the probe block of the
+// merged H/M launch for the kinds that read neither H nor energy partials)
+// ---------------------------------------------------------------------------
+// whether a probe samples at the step in progress (its counter `step`), and
+// the sample's index
+__device__ __forceinline__ bool probe_due(const ProbeDev &P, long long step, long long &sample) {
+    const long long ev = P.every > 1 ? P.every : 1;
+    const long long ks = step - P.start + 1;
+    if (ks % ev) return false;
+    sample = ks / ev - 1;
+    return true;
+}
+
+// the sums of three runs of partials (run w: nb[w] >= 1 values from
+// part + b0[w]) as a 256-thread block reduces each run (thread t adds values
+// t, t + 256, ... in order, then a halving tree), formed by one wavefront:
+// lane t keeps the sums of threads t, t + 64, t + 128, t + 192 of all three
+// runs (twelve independent loads per round; an index past a run reads its
+// last value and drops it), takes the tree's first two levels in registers
+// and the rest by shuffles -- the same additions in the same grouping, with
+// no LDS. Lane 0 holds the sums.
+__device__ __forceinline__ void block_order_sums3(const double *part, const int *b0, const int *nb, double *out) {
+    const int t = (int)threadIdx.x; // 0..63
+    double s[3][4];
+    for (int w = 0; w < 3; w++)
+        for (int q = 0; q < 4; q++) s[w][q] = 0.0;
+    const int nmax = max(nb[0], max(nb[1], nb[2]));
+    for (int base = t; base < nmax; base += 256)
+        for (int w = 0; w < 3; w++)
+            for (int q = 0; q < 4; q++) {
+                const int b = base + 64 * q;
+                const bool in = b < nb[w];
+                const double x = part[b0[w] + (in ? b : nb[w] - 1)];
+                s[w][q] = in ? s[w][q] + x : s[w][q];
+            }
+    for (int w = 0; w < 3; w++) {
+        double r = (s[w][0] + s[w][2]) + (s[w][1] + s[w][3]); // levels 128 and 64
+        for (int st = 32; st > 0; st >>= 1) {
+            const double o = __shfl_down(r, st, 64);
+            if (t < st) r = r + o;
+        }
+        out[w] = r;
+    }
+}
+
+// the values of such a probe, formed by the first wavefront of the block (the
+// others take no part): the E component at its site, or the film's mean M
+// from its film blocks' partial sums in block order; valid in lane 0
+template <typename T>
+__device__ __forceinline__ void probe_e_or_m_values(const KParams<T> &p, const ProbeDev &P, double *v) {
+    if (P.kind == 0) {
+        if (threadIdx.x == 0) v[0] = (double)ldz(p, p.E[P.field], P.i, P.j, P.k);
+        return;
+    }
+    const FilmDev &F = p.films[P.film];
+    double sum[3];
+    block_order_sums3(p.partial, F.blk0, F.nblk, sum);
+    for (int w = 0; w < 3; w++) v[w] = sum[w] / F.ncells;
+}
+
+// thread 0 stores a sample into the probe's ring and raises the non-finite
+// flag
+template <typename T>
+__device__ __forceinline__ void probe_store(const KParams<T> &p, const ProbeDev &P, long long sample,
+                                            const double *v) {
+    if (threadIdx.x != 0) return;
+    const long long slot = sample % P.cap;
+    bool bad = false;
+    for (int w = 0; w < P.nval; w++) {
+        P.data[slot * P.nval + w] = v[w];
+        if (!isfinite(v[w])) bad = true;
+    }
+    if (bad) atomicOr(p.flag, 1);
+}
+
 // a slot's row of the packed table (KParams::coefv), fetched with one or two
 // 16-byte loads and served to e_apply as its table (the class argument is
 // the row's own)

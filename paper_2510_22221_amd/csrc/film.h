@@ -51,6 +51,34 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// the site solve of one magnetic face: P, Q are B^* and B^ at the face
+// (own family) and the means of the four nearest faces of each other family,
+// M the magnetisation of the half step's start; the bias is added to P and Q
+// here.  Trapezoidal LLG over the half step at its fixed point:
+// b = M - k (M x H_eff(M)) with H_eff = Q - M, a = -(k P + (alpha/Ms) M),
+// X = (b + (a.b) a - a x b) / (1 + |a|^2), M' = Ms X / |X|
+__device__ __forceinline__ void llg_site(double kf, const double *H0, double ms, double al, double ga, double *P,
+                                         double *Q, const double *M, double *Mn) {
+    for (int w = 0; w < 3; w++) {
+        P[w] += H0[w];
+        Q[w] += H0[w];
+    }
+    const double kk = kf * ga;
+    // b = M^n - k (M^n x H_eff^n), with H_eff^n = Q - M^n
+    double MxQ[3], b[3], a[3];
+    cross3(M, Q, MxQ);
+    for (int w = 0; w < 3; w++) b[w] = M[w] - kk * MxQ[w];
+    // a at the fixed point: H_eff^{n+1} = P - M^{n+1}
+    for (int w = 0; w < 3; w++) a[w] = -(kk * P[w] + (al / ms) * M[w]);
+    // X = (b + (a.b) a - a x b) / (1 + |a|^2), then M' = Ms X/|X|
+    double axb[3], X[3];
+    cross3(a, b, axb);
+    const double ab = dot3(a, b), aa = dot3(a, a);
+    for (int w = 0; w < 3; w++) X[w] = (b[w] + ab * a[w] - axb[w]) / (1.0 + aa);
+    const double nx = sqrt(dot3(X, X));
+    for (int w = 0; w < 3; w++) Mn[w] = ms * X[w] / nx;
+}
+
 template <typename T>
 __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int inc_step, int blk) {
     __shared__ double red[256];
@@ -101,25 +129,9 @@ __device__ __forceinline__ void film_body(const KParams<T> &p, int phase, int in
                 P[cp] = ((vs[0][0] + vs[1][0]) + (vs[0][1] + vs[1][1])) * 0.25;
             }
             const double *Msrc = (phase == 1) ? F.M : F.M1;
-            for (int w = 0; w < 3; w++) {
-                P[w] += p.H0[w];
-                Q[w] += p.H0[w];
-                M[w] = Msrc[(c * 3 + w) * F.ns + l];
-            }
-            const double kk = p.kf * ga;
-            // b = M^n - k (M^n x H_eff^n), with H_eff^n = Q - M^n
-            double MxQ[3], b[3], a[3];
-            cross3(M, Q, MxQ);
-            for (int w = 0; w < 3; w++) b[w] = M[w] - kk * MxQ[w];
-            // a at the fixed point: H_eff^{n+1} = P - M^{n+1}
-            for (int w = 0; w < 3; w++) a[w] = -(kk * P[w] + (al / ms) * M[w]);
-            // X = (b + (a.b) a - a x b) / (1 + |a|^2), then M' = Ms X/|X|
-            double axb[3], X[3], Mn[3];
-            cross3(a, b, axb);
-            const double ab = dot3(a, b), aa = dot3(a, a);
-            for (int w = 0; w < 3; w++) X[w] = (b[w] + ab * a[w] - axb[w]) / (1.0 + aa);
-            const double nx = sqrt(dot3(X, X));
-            for (int w = 0; w < 3; w++) Mn[w] = ms * X[w] / nx;
+            for (int w = 0; w < 3; w++) M[w] = Msrc[(c * 3 + w) * F.ns + l];
+            double Mn[3];
+            llg_site(p.kf, p.H0, ms, al, ga, P, Q, M, Mn);
             const double hnew = bs - Mn[c];
             if (phase == 1) {
                 for (int w = 0; w < 3; w++) F.M1[(c * 3 + w) * F.ns + l] = Mn[w];

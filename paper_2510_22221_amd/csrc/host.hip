@@ -466,6 +466,17 @@ mpx_status upload_profiles(mpx_sim *s) {
     return MPX_OK;
 }
 
+// the number of probes that ride in the merged H/M launch: all of them when
+// every one reads only E or a film's mean-M partials and the launch has film
+// blocks on 256 x 1 tiles, else none (the probe launch takes them)
+int folded_probes(const mpx_sim *s, bool wide) {
+    const int np = (int)s->probes.size();
+    if (np == 0 || s->nblk == 0 || !wide) return 0;
+    for (const ProbeHost &pr : s->probes)
+        if (!probe_reads_e_or_m(pr.dev.kind, pr.dev.field)) return 0;
+    return np;
+}
+
 // One step of the body (not the last): the fused pass or the two separate
 // stencil passes, then the film half steps and the probes.  `par` is the
 // current buffer parity; the fused schedule flips it.
@@ -516,18 +527,20 @@ mpx_status run_body(mpx_sim *s, int &par, bool timed) {
     }
     // two-pass schedule, in place: E pass, the film's first half step (its
     // prepass reads H before the bulk pass moves it) and probes, then the
-    // film's second half step with the bulk H pass
+    // film's second half step with the bulk H pass (and the probes, when all
+    // of them read only E or mean M: the H/M launch writes neither)
     KParams<T> p;
     fill_params<T>(s, p, MODE_INPLACE, par);
+    const int npf = folded_probes(s, p.wide != 0);
     if ((r = rec(0, 0)) != MPX_OK) return r;
     CK(launch_epass<T>(p, st));
     if ((r = rec(0, 1)) != MPX_OK) return r;
     if ((r = rec(2, 0)) != MPX_OK) return r;
     CK(launch_film<T>(p, nblk, 1, 0, st));
-    CK(launch_probes<T>(p, np, s->probe_maxpart, st));
+    if (npf == 0) CK(launch_probes<T>(p, np, s->probe_maxpart, st));
     if ((r = rec(2, 1)) != MPX_OK) return r;
     if ((r = rec(1, 0)) != MPX_OK) return r;
-    CK(launch_hbulk_film<T>(p, nblk, 1, st));
+    CK(launch_hbulk_film<T>(p, nblk, 1, st, npf));
     if ((r = rec(1, 1)) != MPX_OK) return r;
     return MPX_OK;
 }
@@ -2636,6 +2649,11 @@ mpx_status mpx_set_materials(mpx_sim *s, const mpx_material *table, int32_t n, c
             f.en[a] = span ? s->n[a] : f.bn[a] + 1;
         }
         f.nse = (long long)f.en[0] * f.en[1] * f.en[2];
+        // the kernels index a family's grown box with 32-bit integers
+        if (f.nse >= (1ll << 31)) {
+            s->have_mat = false;
+            return fail(s, MPX_E_UNSUPPORTED, "film face box above 2^31 faces");
+        }
         CK(hipMalloc(&f.Bn, 3 * f.nse * sizeof(double)));
         CK(hipMalloc(&f.Bs, 3 * f.nse * sizeof(double)));
         CK(hipMemset(f.Bn, 0, 3 * f.nse * sizeof(double)));

@@ -123,19 +123,73 @@ __device__ __forceinline__ void bhat(const KParams<T> &p, int phase, int f, int 
     bs = b - cu;
 }
 
+// ldz()'s value with its load issued whatever the domain test says (at slot
+// 0 when the site lies outside, the value then dropped): a value merged out
+// of a branch waits for its load, a selected one does not
+template <typename T>
+__device__ __forceinline__ T ldz_sel(const KParams<T> &p, const T *a, int i, int j, int k) {
+    const int ii = fold(i, p.n[0], p.per[0]), jj = fold(j, p.n[1], p.per[1]), kk = fold(k, p.n[2], p.per[2]);
+    const bool ok = ii >= 0 && jj >= 0 && kk >= 0;
+    const T v = a[ok ? p.slot(ii, jj, kk) : 0];
+    return ok ? v : T(0);
+}
+
+// curl_e64() with ldz_sel loads
+template <typename T>
+__device__ __forceinline__ void curl_e64_sel(const KParams<T> &p, int c, const int *idx, double &d1, double &d2) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    int u1[3] = {idx[0], idx[1], idx[2]}, u2[3] = {idx[0], idx[1], idx[2]};
+    u1[c1] += 1;
+    u2[c2] += 1;
+    const double e2a = (double)ldz_sel(p, p.E[c2], idx[0], idx[1], idx[2]);
+    const double e2b = (double)ldz_sel(p, p.E[c2], u1[0], u1[1], u1[2]);
+    const double e1a = (double)ldz_sel(p, p.E[c1], idx[0], idx[1], idx[2]);
+    const double e1b = (double)ldz_sel(p, p.E[c1], u2[0], u2[1], u2[2]);
+    d1 = (e2b - e2a) / p.d[c1];
+    d2 = (e1b - e1a) / p.d[c2];
+}
+
+// bhat() for phase 1 at a face of film F's grown box, by the same
+// operations, with every load issued before the film test picks the value (a
+// face outside the film reads site 0's entries and drops them)
+template <typename T>
+__device__ __forceinline__ void bhat_phase1(const KParams<T> &p, const FilmDev &F, int cq, const int *idx,
+                                            double &bn, double &bs, double &bn2, double &bs2, bool &mag,
+                                            double &cu) {
+    double d1, d2;
+    curl_e64_sel(p, cq, idx, d1, d2);
+    bool inside;
+    const long long l = film_local<T>(F, idx, inside); // 0 outside
+    const double h0 = (double)p.H[cq][p.slot(idx[0], idx[1], idx[2])];
+    const double ms = F.prm[(cq * 3) * F.ns + l];
+    const double m = F.M[(cq * 3 + cq) * F.ns + l];
+    mag = inside && ms > 0.0;
+    cu = p.hcd * (d1 - d2);
+    const double b = mag ? h0 + m : h0 + 0.0;
+    const double n2 = (h0 - cu) + 0.0;
+    bn2 = mag ? 0.0 : n2;
+    bs2 = mag ? 0.0 : n2 - cu;
+    bn = b;
+    bs = b - cu;
+}
+
 // B^ prepass: B^n and B^* of every face of the grown face box
 template <typename T>
 __device__ __forceinline__ void bhat_body(const KParams<T> &p, int phase, int blk) {
     const int4 bt = block_entry(p.blocktab_ext, blk);
     const int f = bt.x, c = bt.y;
     const FilmDev F = film_desc(p.films, f);
-    const long long l = (long long)bt.z + threadIdx.x;
-    if (l >= F.nse) return;
-    const int idx[3] = {F.e0[0] + (int)(l % F.en[0]), F.e0[1] + (int)((l / F.en[0]) % F.en[1]),
-                        F.e0[2] + (int)(l / ((long long)F.en[0] * F.en[1]))};
+    const int le = bt.z + (int)threadIdx.x; // grown boxes hold fewer than 2^31 faces
+    if (le >= (int)F.nse) return;
+    const int idx[3] = {F.e0[0] + le % F.en[0], F.e0[1] + (le / F.en[0]) % F.en[1],
+                        F.e0[2] + le / (F.en[0] * F.en[1])};
+    const long long l = le;
     double bn, bs, bn2, bs2, cu;
     bool mag;
-    bhat(p, phase, f, c, idx, bn, bs, bn2, bs2, mag, cu);
+    if (phase == 1)
+        bhat_phase1(p, F, c, idx, bn, bs, bn2, bs2, mag, cu);
+    else
+        bhat(p, phase, f, c, idx, bn, bs, bn2, bs2, mag, cu);
     F.Bn[c * F.nse + l] = bn;
     F.Bs[c * F.nse + l] = bs;
     if (phase == 1 && F.Bn2) {
@@ -256,16 +310,6 @@ __device__ __forceinline__ void energy_site(const KParams<T> &p, const int *idx,
     }
 }
 
-// whether a probe samples at the step in progress (its counter `step`), and
-// the sample's index
-__device__ __forceinline__ bool probe_due(const ProbeDev &P, long long step, long long &sample) {
-    const long long ev = P.every > 1 ? P.every : 1;
-    const long long ks = step - P.start + 1;
-    if (ks % ev) return false;
-    sample = ks / ev - 1;
-    return true;
-}
-
 template <typename T>
 __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
     __shared__ double red[256];
@@ -273,34 +317,17 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
     long long sample;
     if (!probe_due(P, p.step[0], sample)) return; // uniform over the block
     double v[3] = {0.0, 0.0, 0.0};
-    if (P.kind == 0) {
+    if (probe_reads_e_or_m(P.kind, P.field)) {
+        if (threadIdx.x < 64) probe_e_or_m_values(p, P, v);
+    } else if (P.kind == 0) {
         if (threadIdx.x == 0) {
+            // an H component; sites on an upper wall are not stored and are zero
             const int idx[3] = {P.i, P.j, P.k};
-            if (P.field < 3)
-                v[0] = (double)ldz(p, p.E[P.field], P.i, P.j, P.k);
-            else {
-                // sites on an upper wall are not stored and are zero
-                const int c = P.field - 3;
-                bool wall = false;
-                for (int a = 0; a < 3; a++)
-                    if (idx[a] >= p.n[a]) wall = true;
-                v[0] = wall ? 0.0 : h_integer_time(p, c, idx);
-            }
-        }
-    } else if (P.kind == 1) {
-        const FilmDev &F = p.films[P.film];
-        for (int w = 0; w < 3; w++) {
-            const int b0 = F.blk0[w], nb = F.nblk[w];
-            double s = 0.0;
-            for (int b = threadIdx.x; b < nb; b += blockDim.x) s += p.partial[b0 + b];
-            red[threadIdx.x] = s;
-            __syncthreads();
-            for (int st = 128; st > 0; st >>= 1) {
-                if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-                __syncthreads();
-            }
-            v[w] = red[0] / F.ncells;
-            __syncthreads();
+            const int c = P.field - 3;
+            bool wall = false;
+            for (int a = 0; a < 3; a++)
+                if (idx[a] >= p.n[a]) wall = true;
+            v[0] = wall ? 0.0 : h_integer_time(p, c, idx);
         }
     } else if (P.kind == 2) {
         // film EM energy: the partial sums of k_probe_parts, in block order
@@ -330,15 +357,7 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
         }
         v[0] = 0.5 * p.dV * (sum[0] + p.mu0 * sum[1]);
     }
-    if (threadIdx.x == 0) {
-        const long long slot = sample % P.cap;
-        bool bad = false;
-        for (int w = 0; w < P.nval; w++) {
-            P.data[slot * P.nval + w] = v[w];
-            if (!isfinite(v[w])) bad = true;
-        }
-        if (bad) atomicOr(p.flag, 1);
-    }
+    probe_store(p, P, sample, v);
 }
 
 // EM energy density sum of one film cell (eps0 eps_r <E^2>/2 + mu0 <H^2>/2 over

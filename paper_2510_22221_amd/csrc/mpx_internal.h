@@ -59,6 +59,13 @@ struct ProbeDev {
     long long npart;
 };
 
+// a probe the merged H/M launch can take (it reads nothing that launch
+// writes): a point probe of an E component (kind 0, field below 3) or a
+// film's mean M (kind 1)
+__host__ __device__ inline bool probe_reads_e_or_m(int kind, int field) {
+    return (kind == 0 && field < 3) || kind == 1;
+}
+
 // Coefficients of an edge, computed on the host with the same operation
 // sequence the device uses for mixed edges (so the table path is bitwise
 // identical to the general one).  The table holds kCoefPerClass entries per
@@ -277,7 +284,10 @@ constexpr int kPassTX = 64, kPassTY = 4; // separate-pass tile: 64 x 4 slots of 
 constexpr int kWideTX = 256, kWideTY = 1; // the wide tile of the single-instance passes
 constexpr int kWideMinNx = 512;           // grids this wide use it
 
-template <typename T> hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s);
+// the bulk H/M pass with the film's second half step (and, nprobe > 0, the
+// probes, all of kinds probe_reads_e_or_m accepts; 256 x 1 tiles and films only)
+template <typename T>
+hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s, int nprobe = 0);
 template <typename T> hipError_t launch_film(const KParams<T> &p, int nblk, int phase, int inc, hipStream_t s);
 template <typename T> hipError_t launch_fused(const KParams<T> &p, int kchunk, int variant, hipStream_t s);
 template <typename T> hipError_t launch_sweep(const KParams<T> &p, int kchunk, hipStream_t s);

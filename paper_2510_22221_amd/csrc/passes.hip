@@ -357,15 +357,41 @@ __global__ void __launch_bounds__(TX *TY) k_hbulk(KParams<T> p, int inc_step) {
 // planes.  The two touch disjoint data: the film blocks read the prepass the
 // first half step wrote and write M and H of magnetic faces, which the bulk
 // blocks load but never store or use.
+// the probes of an integer time when every one of them reads only E or the
+// film's mean-M partials (which this launch does not write), in the block
+// right after the film blocks: its first wavefront reads the step counter,
+// samples each probe due and then advances the counter (no other block of
+// the launch reads it)
 template <typename T>
-__global__ void __launch_bounds__(kWideTX) k_hbulk_film(KParams<T> p, int inc_step, int zf, int nfb) {
+__device__ __forceinline__ void probe_block(const KParams<T> &p, int nprobe, int inc_step) {
+    if (threadIdx.x >= 64) return; // one wavefront does it all
+    const long long step = p.step[0];
+    for (int pb = 0; pb < nprobe; pb++) {
+        const ProbeDev &P = p.probes[pb];
+        long long sample;
+        if (!probe_due(P, step, sample)) continue; // uniform over the wavefront
+        double v[3] = {0.0, 0.0, 0.0};
+        probe_e_or_m_values(p, P, v);
+        probe_store(p, P, sample, v);
+    }
+    // lane 0 advances the counter after every lane has read it (one
+    // wavefront: its reads above precede this store)
+    if (inc_step && threadIdx.x == 0) p.step[0] = step + 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWideTX) k_hbulk_film(KParams<T> p, int inc_step, int zf, int nfb, int nprobe) {
     if ((int)blockIdx.z < zf) {
         const int fb = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
-        if (fb < nfb) film_body(p, 2, 0, fb);
+        if (fb < nfb)
+            film_body(p, 2, 0, fb);
+        else if (fb == nfb && nprobe > 0)
+            probe_block(p, nprobe, inc_step);
         return;
     }
     const int k = (int)blockIdx.z - zf;
-    if (inc_step && blockIdx.x == 0 && blockIdx.y == 0 && k == 0 && threadIdx.x == 0) p.step[0] = p.step[0] + 1;
+    if (inc_step && nprobe == 0 && blockIdx.x == 0 && blockIdx.y == 0 && k == 0 && threadIdx.x == 0)
+        p.step[0] = p.step[0] + 1;
     hpass_block<T, 2, kWideTX, kWideTY>(p, blockIdx.x, blockIdx.y, k);
 }
 
@@ -454,7 +480,9 @@ hipError_t launch_hbulk(const KParams<T> &p, int nhalf, int inc, hipStream_t s) 
 // the film's second half step (nblk blocks) and the merged H/M pass; on
 // 256 x 1 tiles one launch, else two
 template <typename T>
-hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s) {
+hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t s, int nprobe) {
+    // probes ride in the launch only beside film blocks on 256 x 1 tiles
+    if (nprobe > 0 && (nblk == 0 || !p.wide)) return hipErrorInvalidValue;
     if (nblk == 0) return launch_hbulk<T>(p, 2, inc, s);
     if (!p.wide) {
         hipError_t e = launch_film<T>(p, nblk, 2, 0, s);
@@ -464,8 +492,8 @@ hipError_t launch_hbulk_film(const KParams<T> &p, int nblk, int inc, hipStream_t
     static_assert(kWideTX == 256 && kWideTY == 1, "film blocks are 256 threads along x");
     const dim3 g = pass_grid<kWideTX, kWideTY>(p.n);
     const int per_plane = (int)(g.x * g.y);
-    const int zf = (nblk + per_plane - 1) / per_plane;
-    k_hbulk_film<T><<<dim3(g.x, g.y, g.z + zf), dim3(kWideTX, kWideTY), 0, s>>>(p, inc, zf, nblk);
+    const int zf = (nblk + (nprobe > 0 ? 1 : 0) + per_plane - 1) / per_plane;
+    k_hbulk_film<T><<<dim3(g.x, g.y, g.z + zf), dim3(kWideTX, kWideTY), 0, s>>>(p, inc, zf, nblk, nprobe);
     return hipGetLastError();
 }
 
@@ -496,7 +524,7 @@ hipError_t launch_hbulk_batch(const KParams<T> *plist, const int4 *work, int nwo
 #define MPX_PASSES(T)                                                                                      \
     template hipError_t launch_epass<T>(const KParams<T> &, hipStream_t);                                 \
     template hipError_t launch_hbulk<T>(const KParams<T> &, int, int, hipStream_t);                       \
-    template hipError_t launch_hbulk_film<T>(const KParams<T> &, int, int, hipStream_t);                  \
+    template hipError_t launch_hbulk_film<T>(const KParams<T> &, int, int, hipStream_t, int);                  \
     template hipError_t launch_epass_batch<T>(const KParams<T> *, const int4 *, int, const int2 *, int,   \
                                               bool, hipStream_t);                                         \
     template hipError_t launch_hbulk_batch<T>(const KParams<T> *, const int4 *, int, int, int, hipStream_t);

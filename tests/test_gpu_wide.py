@@ -119,3 +119,42 @@ def test_narrow_tile_schedule_bitwise_equal_wide_tiles():
         for pid, p in enumerate(w.probes):
             nv = 3 if p.kind == "mean_m" else 1
             assert np.array_equal(g.read_probe(pid, nv), ref.read_probe(pid, nv)), (prec, pid)
+
+
+def test_probes_in_the_h_pass_launch_bitwise():
+    """E-point and mean-M probes, strided ones among them, ride in the merged
+    H/M launch on wide grids (its probe block reads the step counter and
+    advances it). One H-point probe more sends every probe back to the probe
+    launch. Both runs must give the same fields, traces and step counter in
+    both precisions."""
+    w = wide_case(40)
+    w.probes = []
+    for prec in (mpx.F64, mpx.F32):
+        runs = []
+        for with_h in (False, True):
+            say(f"520-wide box, E and mean-M probes{' + an H probe' if with_h else ''}, prec={prec}")
+            s = mpx.from_workload(w, precision=prec, graph_steps=4)
+            spec = [(mpx.PROBE_FIELD, 1, (260, 6, 5), 1), (mpx.PROBE_MEAN_M, 0, None, 1),
+                    (mpx.PROBE_FIELD, 2, (100, 5, 4), 3), (mpx.PROBE_MEAN_M, 0, None, 4)]
+            pids = []
+            for kind, fld, ijk, every in spec:
+                if kind == mpx.PROBE_MEAN_M:
+                    pids.append((s.add_probe(kind, film=0, cap=64, every=every), 3))
+                else:
+                    pids.append((s.add_probe(kind, field=fld, ijk=ijk, cap=64, every=every), 1))
+            if with_h:
+                s.add_probe(mpx.PROBE_FIELD, field=4, ijk=(259, 6, 5), cap=64)
+            for c in CALLS:
+                s.step(c)
+            s.sync()
+            runs.append(([s.get(f).copy() for f in range(12)],
+                         [s.read_probe(pid, nv).copy() for pid, nv in pids], s.info()["step"]))
+            s.close()
+        (fa, pa, sa), (fb, pb, sb) = runs
+        assert sa == sb == sum(CALLS), (sa, sb)
+        for f in range(12):
+            assert np.array_equal(fa[f], fb[f]), (prec, f)
+        for q, (a, b) in enumerate(zip(pa, pb)):
+            assert a.shape == b.shape and a.size > 0, (prec, q, a.shape, b.shape)
+            assert np.array_equal(a, b), (prec, q)
+        assert np.any(pa[1] != 0.0), "mean M never sampled"
