@@ -55,9 +55,9 @@ def algorithmic_bytes(w, esz):
 
 
 def kernel_source_hash():
-    """Hash of the forward kernels' sources with comments and blank lines
-    removed (an edited comment leaves the measured kernels, and this hash,
-    as they were)."""
+    """Hash of the forward kernels' sources with comments removed and every
+    run of white space made one space (an edited comment or a reformatted
+    line leaves the measured kernels, and this hash, as they were)."""
     import re
 
     h = hashlib.sha256()
@@ -67,7 +67,7 @@ def kernel_source_hash():
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
-        h.update("\n".join(ln.rstrip() for ln in src.splitlines() if ln.strip()).encode())
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
