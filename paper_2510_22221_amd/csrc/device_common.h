@@ -64,7 +64,9 @@ __device__ __forceinline__ int4 block_entry(const int4 *tab, int b) {
 
 // ---------------------------------------------------------------------------
 // probes at an integer time (the probe launch, and the probe block of the
-// merged H/M launch for the kinds that read neither H nor energy partials)
+// merged H/M launch for the kinds that read neither H nor energy partials;
+// the probe launch's mean-M tree and block_order_sums3 add the same values
+// in the same grouping)
 // ---------------------------------------------------------------------------
 // whether a probe samples at the step in progress (its counter `step`), and
 // the sample's index
@@ -108,9 +110,10 @@ __device__ __forceinline__ void block_order_sums3(const double *part, const int 
     }
 }
 
-// the values of such a probe, formed by the first wavefront of the block (the
-// others take no part): the E component at its site, or the film's mean M
-// from its film blocks' partial sums in block order; valid in lane 0
+// the values of such a probe in the merged H/M launch's probe block, formed
+// by its first wavefront (the others take no part): the E component at its
+// site, or the film's mean M from its film blocks' partial sums in block
+// order; valid in lane 0
 template <typename T>
 __device__ __forceinline__ void probe_e_or_m_values(const KParams<T> &p, const ProbeDev &P, double *v) {
     if (P.kind == 0) {

@@ -317,8 +317,26 @@ __device__ __forceinline__ void probes_body(const KParams<T> &p, int pb) {
     long long sample;
     if (!probe_due(P, p.step[0], sample)) return; // uniform over the block
     double v[3] = {0.0, 0.0, 0.0};
-    if (probe_reads_e_or_m(P.kind, P.field)) {
-        if (threadIdx.x < 64) probe_e_or_m_values(p, P, v);
+    if (P.kind == 0 && P.field < 3) {
+        if (threadIdx.x == 0) v[0] = (double)ldz(p, p.E[P.field], P.i, P.j, P.k);
+    } else if (P.kind == 1) {
+        // the film's mean M: its film blocks' partials, thread t adding
+        // partials t, t + 256, ... then a halving tree (the probe block of the
+        // merged H/M launch forms the same additions in one wavefront)
+        const FilmDev &F = p.films[P.film];
+        for (int w = 0; w < 3; w++) {
+            const int b0 = F.blk0[w], nb = F.nblk[w];
+            double s = 0.0;
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) s += p.partial[b0 + b];
+            red[threadIdx.x] = s;
+            __syncthreads();
+            for (int st = 128; st > 0; st >>= 1) {
+                if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+                __syncthreads();
+            }
+            v[w] = red[0] / F.ncells;
+            __syncthreads();
+        }
     } else if (P.kind == 0) {
         if (threadIdx.x == 0) {
             // an H component; sites on an upper wall are not stored and are zero
