@@ -82,7 +82,7 @@ __device__ __forceinline__ bool probe_due(const ProbeDev &P, long long step, lon
 // part + b0[w]) as a 256-thread block reduces each run (thread t adds values
 // t, t + 256, ... in order, then a halving tree), formed by one wavefront:
 // lane t keeps the sums of threads t, t + 64, t + 128, t + 192 of all three
-// runs (twelve independent loads per round; an index past a run reads its
+// runs (twelve independent loads per loop pass; an index past a run reads its
 // last value and drops it), takes the tree's first two levels in registers
 // and the rest by shuffles -- the same additions in the same grouping, with
 // no LDS. Lane 0 holds the sums.
