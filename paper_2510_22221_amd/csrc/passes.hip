@@ -27,12 +27,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, lo
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <typename T>
+// AUX: the load's cache-policy bits (2: non-temporal)
+template <typename T, int AUX = 0>
 __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
     else
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
 }
 
 constexpr int kOOB = 0x7ffffff0; // a byte offset past every resource: the load returns 0
@@ -85,8 +86,12 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
     const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
     const T hz0 = bld<T>(rz, vo, 0), hz_xm = bld<T>(rz, vxm, 0), hz_ym = bld<T>(rz, vym, 0);
+    // E, the class and the new E are touched once per pass: non-temporal, so
+    // that they leave L2 first and the H rows and planes the neighbouring
+    // tiles read again, and the coefficient rows, stay
     T *ex = p.E[0] + k * sz, *ey = p.E[1] + k * sz, *ez = p.E[2] + k * sz;
-    const T e0 = ex[o], e1 = ey[o], e2 = ez[o];
+    const T e0 = __builtin_nontemporal_load(ex + o), e1 = __builtin_nontemporal_load(ey + o),
+            e2 = __builtin_nontemporal_load(ez + o);
     // the coefficient triple's row: the class byte (255: the slot is on the
     // mixed list), or with extended triples the 16-bit class (0xffff: on the
     // mixed list), whose rows past 255 are the extended table's
@@ -94,9 +99,9 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     if constexpr (CLS == 2) c16 = p.cls16 != nullptr;
     int c0;
     if constexpr (CLS == 0)
-        c0 = (p.cls + k * sz)[o];
+        c0 = __builtin_nontemporal_load(p.cls + k * sz + o);
     else if constexpr (CLS == 1)
-        c0 = (p.cls16 + k * sz)[o];
+        c0 = __builtin_nontemporal_load(p.cls16 + k * sz + o);
     else if (c16)
         c0 = (p.cls16 + k * sz)[o];
     else
@@ -141,9 +146,9 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
                                                      r, tsrc, step);
             if (tpml) psi_store<T, 2>(p.psiE[2], r);
         }
-        ex[o] = n0;
-        ey[o] = n1;
-        ez[o] = n2;
+        __builtin_nontemporal_store(n0, ex + o);
+        __builtin_nontemporal_store(n1, ey + o);
+        __builtin_nontemporal_store(n2, ez + o);
         return;
     }
     // float32: every load of the thread before any store (the CPML state of
@@ -164,9 +169,9 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const T n2 = v2 ? e_apply<T, 2, CoefRow<T>, false>(p, L, q2, c0, e2, dif(hy0, hy_xm, dx, ix),
                                                        dif(hx0, hx_ym, dy, iy), r2, tsrc, step)
                     : T(0);
-    ex[o] = n0;
-    ey[o] = n1;
-    ez[o] = n2;
+    __builtin_nontemporal_store(n0, ex + o);
+    __builtin_nontemporal_store(n1, ey + o);
+    __builtin_nontemporal_store(n2, ez + o);
     if (tpml) {
         psi_store<T, 0>(p.psiE[0], r0);
         psi_store<T, 1>(p.psiE[1], r1);
@@ -256,7 +261,10 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
     const T ex0 = bld<T>(rx, vo, 0), ex_yp = bld<T>(rx, vyp, 0), ex_kp = bld<T>(ax, vo, 0);
     const T ey0 = bld<T>(ry, vo, 0), ey_xp = bld<T>(ry, vxp, 0), ey_kp = bld<T>(ay, vo, 0);
     const T ez0 = bld<T>(rz, vo, 0), ez_xp = bld<T>(rz, vxp, 0), ez_yp = bld<T>(rz, vyp, 0);
-    const T h0 = bld<T>(gx, vo, 0), h1 = bld<T>(gy, vo, 0), h2 = bld<T>(gz, vo, 0);
+    // H and the new H are touched once per pass: non-temporal (the E halo
+    // stays in L2); the CPML state keeps the default policy (an x slab's rows
+    // share lines with the next row's block)
+    const T h0 = bld<T, 2>(gx, vo, 0), h1 = bld<T, 2>(gy, vo, 0), h2 = bld<T, 2>(gz, vo, 0);
     // the tile's flags, first used after every field load has been issued
     const bool tpml = wave_pml<T, TX>(p, bxt, f), tfilm = (f & 4) != 0;
     const T dx = p.dT[0], dy = p.dT[1], dz = p.dT[2], ix = p.invd[0], iy = p.invd[1], iz = p.invd[2];
@@ -284,7 +292,7 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
             if (tpml) r = psi_load<T, 0, false>(p, idx);
             const T n = h_apply<T, 0, NHALF>(p, h0, dif(ez_yp, ez0, dy, iy), dif(ey_kp, ey0, dz, iz), r);
             if (!mag[0]) {
-                hx[o] = n;
+                __builtin_nontemporal_store(n, hx + o);
                 if (tpml) psi_store<T, 0>(p.psiH[0], r);
             }
         }
@@ -293,7 +301,7 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
             if (tpml) r = psi_load<T, 1, false>(p, idx);
             const T n = h_apply<T, 1, NHALF>(p, h1, dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), r);
             if (!mag[1]) {
-                hy[o] = n;
+                __builtin_nontemporal_store(n, hy + o);
                 if (tpml) psi_store<T, 1>(p.psiH[1], r);
             }
         }
@@ -302,7 +310,7 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
             if (tpml) r = psi_load<T, 2, false>(p, idx);
             const T n = h_apply<T, 2, NHALF>(p, h2, dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), r);
             if (!mag[2]) {
-                hz[o] = n;
+                __builtin_nontemporal_store(n, hz + o);
                 if (tpml) psi_store<T, 2>(p.psiH[2], r);
             }
         }
@@ -312,9 +320,9 @@ __device__ __forceinline__ void hpass_tile(const KParams<T> &p, int i0, int j0, 
     const T n1 = h_apply<T, 1, NHALF>(p, h1, dif(ex_kp, ex0, dz, iz), dif(ez_xp, ez0, dx, ix), r1);
     const T n2 = h_apply<T, 2, NHALF>(p, h2, dif(ey_xp, ey0, dx, ix), dif(ex_yp, ex0, dy, iy), r2);
     T *hx = p.H[0] + k * sz, *hy = p.H[1] + k * sz, *hz = p.H[2] + k * sz;
-    if (!mag[0]) hx[o] = n0;
-    if (!mag[1]) hy[o] = n1;
-    if (!mag[2]) hz[o] = n2;
+    if (!mag[0]) __builtin_nontemporal_store(n0, hx + o);
+    if (!mag[1]) __builtin_nontemporal_store(n1, hy + o);
+    if (!mag[2]) __builtin_nontemporal_store(n2, hz + o);
     if (tpml) {
         if (!mag[0]) psi_store<T, 0>(p.psiH[0], r0);
         if (!mag[1]) psi_store<T, 1>(p.psiH[1], r1);
