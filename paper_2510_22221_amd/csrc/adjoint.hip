@@ -1375,7 +1375,10 @@ __global__ void __launch_bounds__(256) k_adj_hfield2(AdjParams<T> A) {
     const int t[3] = {i, j, k};
     const long long q = p.slot(i, j, k);
     const uint8_t fl = (uint8_t)adj_tile_flag(A.aflags);
-    T l0 = A.lE[0][q], l1 = A.lE[1][q], l2 = A.lE[2][q];
+    // the slot's lambda E is touched once per pass: non-temporal (the lambda
+    // H the neighbouring slots read again stays in L2)
+    T l0 = __builtin_nontemporal_load(A.lE[0] + q), l1 = __builtin_nontemporal_load(A.lE[1] + q),
+      l2 = __builtin_nontemporal_load(A.lE[2] + q);
     T ca[3], cb[3];
     bool ok[3];
     edge_coefs<T>(p, t, q, ca, cb, ok);
@@ -1460,9 +1463,9 @@ __global__ void __launch_bounds__(256) k_adj_hfield2(AdjParams<T> A) {
     l0 = l0 + (de[0] + de[1]);
     l1 = l1 + (de[2] + de[3]);
     l2 = l2 + (de[4] + de[5]);
-    A.lE[0][q] = l0;
-    A.lE[1][q] = l1;
-    A.lE[2][q] = l2;
+    __builtin_nontemporal_store(l0, A.lE[0] + q);
+    __builtin_nontemporal_store(l1, A.lE[1] + q);
+    __builtin_nontemporal_store(l2, A.lE[2] + q);
     A.mu[0][q] = ok[0] ? cb[0] * l0 : T(0);
     A.mu[1][q] = ok[1] ? cb[1] * l1 : T(0);
     A.mu[2][q] = ok[2] ? cb[2] * l2 : T(0);
@@ -1708,7 +1711,10 @@ __device__ __forceinline__ void efield_body(const AdjParams<T> &A, const int *t,
     // every load of the thread before any store: lambda H of the slot, then
     // the edges (own edges' new lambda psiE held until the end; the sets read
     // and written are different arrays)
-    const T lh0 = A.lH[0][q], lh1 = A.lH[1][q], lh2 = A.lH[2][q];
+    // (the slot's lambda H is touched once per pass: non-temporal; the mu
+    // the neighbouring edges read again stays in L2)
+    const T lh0 = __builtin_nontemporal_load(A.lH[0] + q), lh1 = __builtin_nontemporal_load(A.lH[1] + q),
+            lh2 = __builtin_nontemporal_load(A.lH[2] + q);
     PsiOut<T> w0, w1, w2;
     T o0[3], o1[3], x0, x1;
     eedge<T, 0, PML>(A, t, i0a, i0b, PML ? &w0 : nullptr, o0[0], o1[0]);
@@ -1733,9 +1739,12 @@ __device__ __forceinline__ void efield_body(const AdjParams<T> &A, const int *t,
         if (w2.q1 >= 0) o2a[w2.q1] = w2.v1;
         if (w2.q2 >= 0) o2b[w2.q2] = w2.v2;
     }
-    A.lH[0][q] = lh0 + (dif(o0[1] - n1p2, T(0), p.dT[2], p.invd[2]) + dif(o1[2] - n2p1, T(0), p.dT[1], p.invd[1]));
-    A.lH[1][q] = lh1 + (dif(o0[2] - n2p0, T(0), p.dT[0], p.invd[0]) + dif(o1[0] - n0p2, T(0), p.dT[2], p.invd[2]));
-    A.lH[2][q] = lh2 + (dif(o0[0] - n0p1, T(0), p.dT[1], p.invd[1]) + dif(o1[1] - n1p0, T(0), p.dT[0], p.invd[0]));
+    __builtin_nontemporal_store(
+        lh0 + (dif(o0[1] - n1p2, T(0), p.dT[2], p.invd[2]) + dif(o1[2] - n2p1, T(0), p.dT[1], p.invd[1])), A.lH[0] + q);
+    __builtin_nontemporal_store(
+        lh1 + (dif(o0[2] - n2p0, T(0), p.dT[0], p.invd[0]) + dif(o1[0] - n0p2, T(0), p.dT[2], p.invd[2])), A.lH[1] + q);
+    __builtin_nontemporal_store(
+        lh2 + (dif(o0[0] - n0p1, T(0), p.dT[1], p.invd[1]) + dif(o1[1] - n1p0, T(0), p.dT[0], p.invd[0])), A.lH[2] + q);
 }
 
 template <typename T>
