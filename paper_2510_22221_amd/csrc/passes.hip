@@ -83,8 +83,10 @@ __device__ __forceinline__ void epass_tile(const KParams<T> &p, int i0, int j0, 
     const auto rx = make_rsrc(p.H[0] + k * sz, pb), ry = make_rsrc(p.H[1] + k * sz, pb),
                rz = make_rsrc(p.H[2] + k * sz, pb);
     const auto bx = make_rsrc(p.H[0] + kb * sz, pb), by = make_rsrc(p.H[1] + kb * sz, pb);
-    const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
-    const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
+    // the -z plane's H is read here for the last time (the tiles of its own
+    // plane and of the next row read it before): non-temporal
+    const T hx0 = bld<T>(rx, vo, 0), hx_km = bld<T, 2>(bx, vo, 0), hx_ym = bld<T>(rx, vym, 0);
+    const T hy0 = bld<T>(ry, vo, 0), hy_km = bld<T, 2>(by, vo, 0), hy_xm = bld<T>(ry, vxm, 0);
     const T hz0 = bld<T>(rz, vo, 0), hz_xm = bld<T>(rz, vxm, 0), hz_ym = bld<T>(rz, vym, 0);
     // E, the class and the new E are touched once per pass: non-temporal, so
     // that they leave L2 first and the H rows and planes the neighbouring
