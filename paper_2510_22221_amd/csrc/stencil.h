@@ -123,7 +123,10 @@ struct Psi2 {
 };
 
 // E: the E-type psi (E = true) or H-type psi of component C at the folded
-// site idx
+// site idx.  A slot's psi is touched once per pass: the y- and z-slab arrays
+// load and store it non-temporal; the x-slab arrays keep the default policy
+// (a row's few slab values share cache lines with the next row's, which
+// another tile reads)
 template <typename T, int C, bool E>
 __device__ __forceinline__ Psi2<T> psi_load(const KParams<T> &p, const int *idx) {
     constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
@@ -136,13 +139,13 @@ __device__ __forceinline__ Psi2<T> psi_load(const KParams<T> &p, const int *idx)
     r.s2 = arr[C2] && (a2 < p.nlo[C2] || a2 >= p.n[C2] - p.nhi[C2]);
     if (r.s1) {
         r.q1 = p.psi_index(C1, idx);
-        r.ps1 = arr[C1][r.q1];
+        r.ps1 = C1 == 0 ? arr[C1][r.q1] : __builtin_nontemporal_load(arr[C1] + r.q1);
         r.b1 = bt[C1][a1];
         r.c1 = ct[C1][a1];
     }
     if (r.s2) {
         r.q2 = p.psi_index(C2, idx);
-        r.ps2 = arr[C2][r.q2];
+        r.ps2 = C2 == 0 ? arr[C2][r.q2] : __builtin_nontemporal_load(arr[C2] + r.q2);
         r.b2 = bt[C2][a2];
         r.c2 = ct[C2][a2];
     }
@@ -153,8 +156,18 @@ template <typename T, int C>
 __device__ __forceinline__ void psi_store(T *const *arr, const Psi2<T> &r) {
     constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
     if (!r.upd) return;
-    if (r.s1) arr[C1][r.q1] = r.ps1;
-    if (r.s2) arr[C2][r.q2] = r.ps2;
+    if (r.s1) {
+        if (C1 == 0)
+            arr[C1][r.q1] = r.ps1;
+        else
+            __builtin_nontemporal_store(r.ps1, arr[C1] + r.q1);
+    }
+    if (r.s2) {
+        if (C2 == 0)
+            arr[C2][r.q2] = r.ps2;
+        else
+            __builtin_nontemporal_store(r.ps2, arr[C2] + r.q2);
+    }
 }
 
 // the E edge of component C at raw position (gi, gj, gk) (possibly one past
